@@ -9,26 +9,29 @@ with the GPU library (``paper_2311_12519_amd``) and never imports it.
 
 What it computes, in the paper's terms:
 
-* BFV symmetric key generation, encryption and decryption (Section 3.1,
-  "Homomorphic Operations in BFV", the symmetric-encryption and decryption
+* BFV symmetric key generation, encryption and decryption (the "Homomorphic
+  Operations in BFV" section: the symmetric-encryption and decryption
   equations), with a ternary secret, a B-bounded rounded Gaussian error
   (B = 10 sigma) and a centered message.
 * The coefficient encoding of zero-padded input tensors and the kernel
-  polynomials of the padded convolution (Section 3.2, "Prior Art on
-  Homomorphic Convolution": channels padded with zeros, kernel elements used
+  polynomials of the padded convolution (the "Prior Art on
+  Homomorphic Convolution" section: channels padded with zeros, kernel elements used
   as scalars), in the exact geometry written out in ``plan``.
 * The homomorphic convolution as its plain definition: for every output
   channel o and tile, sum over input ciphertexts g of ct_g * K_{o,g} in
   Z_q[X]/(X^N+1), by schoolbook products over the nonzero taps.
-* The plaintext convolution it must reproduce (the lossless claim of
-  Section 4.2.1 and Section 1).
-* The Walsh-Hadamard matrix and Walsh weights of Section 4.1 ("Enabling Output
-  Channel Packing", Eq. (hadamard2) and its generalisation to c_n = 2^k).
+* The plaintext convolution it must reproduce (the method does not change
+  the inference result: introduction and "Optimal Parameter Selection").
+* The Walsh-Hadamard matrix and Walsh weights of the "Enabling Output
+  Channel Packing" section (Eq. (hadamard2) and its generalisation to c_n = 2^k).
 * The negacyclic NTT by O(N^2) evaluation at the odd powers of psi.
 
-Readings of the paper this oracle adopts (coefficient encoding with t = 2^20
-instead of SIMD batching; ternary secret; centered messages; c_n^{-1} folded
-into the Walsh kernels) are listed in the design doc of the repository.
+Readings of the paper this oracle adopts where the paper is silent or uses
+another setting: coefficient encoding with t = 2^20 instead of SIMD batch
+encoding (a power-of-two t admits no batching); a ternary secret instead of
+{0, 1}; centered messages in (-t/2, t/2]; the 1/c_n of Eq. (hadamard2) as
+the inverse of c_n mod q_i; decryption rounding half up (no tie can occur,
+q odd and t a power of two).
 
 Every function that is pinned by a test against something other than itself
 is noted as such in tests/test_oracle_pins.py; no function here is "parity
@@ -111,7 +114,7 @@ def is_prime(n: int) -> bool:
 def ntt_primes(N: int, L: int, bits: int = 31) -> list:
     """The L largest primes q < 2^bits with q = 1 mod 2N, in descending order.
 
-    q = 1 mod 2N is what the negacyclic NTT needs (Section 4.2.1, step 1 of the
+    q = 1 mod 2N is what the negacyclic NTT needs (the "Optimal Parameter Selection" section, step 1 of the
     parameter selection: q = 1 mod 2n)."""
     out = []
     q = ((1 << bits) - 1) // (2 * N) * (2 * N) + 1
@@ -136,7 +139,7 @@ def find_psi(q: int, N: int) -> int:
 # 128-bit security ceiling on log2(q) for a ternary secret (the public
 # Homomorphic Encryption Security Standard, Albrecht et al. 2018, Table
 # "uniform ternary", 128-bit column). The paper itself only states that its
-# parameters meet 128-bit security (Section 5.1).
+# parameters meet 128-bit security (the "Evaluation Setup" section).
 SECURITY_LOGQ_128 = {1024: 27, 2048: 54, 4096: 109, 8192: 218, 16384: 438, 32768: 881}
 
 
@@ -198,7 +201,7 @@ def sample_error(key: int, ctr: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# BFV key generation, encryption, decryption (Section 3.1)
+# BFV key generation, encryption, decryption (the "Homomorphic Operations in BFV" section)
 # ---------------------------------------------------------------------------
 
 def keygen(N: int, seed: int) -> np.ndarray:
@@ -325,7 +328,7 @@ def plan(N: int, H: int, W: int, Ci: int, Co: int, k: int, depthwise: bool = Fal
     """Geometry: channels zero-padded by p = (k-1)/2 and packed back to back.
 
     If one padded channel fits, c_i padded channels share a ciphertext
-    (Section 3.2: C x H x W split over ceil(CHW/n) ciphertexts, here with
+    (the "Prior Art on Homomorphic Convolution" section: C x H x W split over ceil(CHW/n) ciphertexts, here with
     padding); otherwise one channel is split into row tiles of R output rows
     with a 2p-row halo. ``ci`` may lower the channels per ciphertext."""
     if k not in (1, 3) or N & (N - 1):
@@ -497,7 +500,7 @@ def noise_ok(pl: Plan, w: np.ndarray, primes, log2_t: int = T_DEFAULT_LOG2) -> b
     """Decryption of every output is exact if the worst-case noise of the
     product, E = sum_g e_g K_{o,g} with |e| <= B, and the rounding term of the
     centered lift keep t*|E| + r*|Y| < q/2, r = q mod t (decryption-correctness
-    condition ||v|| < Delta/2 of Section 3.1), and |y| < t/2."""
+    condition ||v|| < Delta/2 of the "Homomorphic Operations in BFV" section), and |y| < t/2."""
     q = math.prod(primes)
     t = 1 << log2_t
     w = np.abs(np.asarray(w, dtype=np.int64))
@@ -507,7 +510,7 @@ def noise_ok(pl: Plan, w: np.ndarray, primes, log2_t: int = T_DEFAULT_LOG2) -> b
 
 
 # ---------------------------------------------------------------------------
-# Walsh-Hadamard output-channel packing (Section 4.1)
+# Walsh-Hadamard output-channel packing (the "Enabling Output Channel Packing" section)
 # ---------------------------------------------------------------------------
 
 def walsh_matrix(c_n: int) -> np.ndarray:
@@ -535,10 +538,16 @@ def walsh_weights(w: np.ndarray, c_n: int) -> np.ndarray:
 def walsh_kernel_residues(pl: Plan, w: np.ndarray, c_n: int, primes, G: int, j: int, g: int) -> np.ndarray:
     """Coefficient-domain Walsh kernel c_n^{-1} * Kw_{G,j,g} mod q_i, uint32 [L][N].
 
-    Kw is built from the Walsh weights exactly as K is built from f; the factor
-    1/c_n of Eq. (hadamard2) is the inverse of c_n mod q_i."""
-    gw = walsh_weights(w, c_n)
-    K = kernel_poly(pl, gw, G * c_n + j, g)
+    Kw_{G,j,g} = sum_b H[j][b] K_{G*c_n+b, g}: the Walsh components of the c_n
+    per-output-channel kernel polynomials (Eq. (hadamard2) applied to the
+    polynomials that carry [f0, f1]). For a standard layer this is the kernel
+    polynomial of the Walsh weights; for a depthwise layer the c_n terms sit
+    at the c_n different channel positions. The factor 1/c_n of Eq.
+    (hadamard2) is the inverse of c_n mod q_i."""
+    H = walsh_matrix(c_n)
+    K = np.zeros(pl.N, dtype=np.int64)
+    for b in range(c_n):
+        K += int(H[j, b]) * kernel_poly(pl, w, G * c_n + b, g)
     out = np.empty((len(primes), pl.N), dtype=np.uint32)
     for i, qi in enumerate(primes):
         inv = pow(c_n, -1, qi)

@@ -13,7 +13,7 @@
  * number-theoretic transform, and no blocking, fusion or reordering beyond
  * splitting independent outputs across OpenMP threads.
  *
- * Rings: R_q = Z_q[X]/(X^N + 1) (Section 3.1 "Homomorphic Operations in
+ * Rings: R_q = Z_q[X]/(X^N + 1) (Background, "Homomorphic Operations in
  * BFV"), one residue ring per RNS limb q_i < 2^31. All residues are canonical,
  * in [0, q_i).
  */
@@ -71,8 +71,8 @@ void orc_negacyclic_mul(const uint32_t *a, const uint32_t *b, uint32_t *r,
  *
  * for every requested output u = (tile, output channel), both ciphertext
  * parts p and every limb i. This is the padded convolution written as
- * PMult/CMult by scalar weights followed by HAdd (Section 3.2 "Prior Art on
- * Homomorphic Convolution" and Section 4.1): multiplying by the monomial
+ * PMult/CMult by scalar weights followed by HAdd (Background, "Prior Art on
+ * Homomorphic Convolution"; "Enabling Output Channel Packing"): multiplying by the monomial
  * w * X^e is CMult by w after a rotation by e.
  *
  * ct       : uint32 [n_tiles][n_groups][2][L][N]

@@ -46,7 +46,7 @@ def test_uniform_mod_exact_against_bigint():
 
 
 def test_error_sampler_distribution():
-    # rounded Gaussian, sigma = 3.2, bounded by B = 10 sigma (Section 3.1)
+    # rounded Gaussian, sigma = 3.2, bounded by B = 10 sigma (the "Homomorphic Operations in BFV" section)
     e = orc.sample_error(5, np.arange(400_000, dtype=np.uint64))
     assert e.min() >= -orc.B_ERR and e.max() <= orc.B_ERR
     assert abs(e.mean()) < 0.03
@@ -173,7 +173,7 @@ def test_ntt_sampled_indices_match_full():
     assert np.array_equal(orc.ntt(a, q, psi, ks), full[ks])
 
 
-# ---------------------------------------------------------------- BFV (Section 3.1)
+# ---------------------------------------------------------------- BFV (the "Homomorphic Operations in BFV" section)
 
 @pytest.mark.parametrize("N,L,bits", [(1024, 2, 30), (4096, 3, 31)])
 def test_encrypt_decrypt_roundtrip_and_fresh_noise(N, L, bits):
@@ -194,7 +194,7 @@ def test_encrypt_decrypt_roundtrip_and_fresh_noise(N, L, bits):
 
 
 def test_decrypt_detects_overflowing_noise():
-    # noise beyond Delta/2 breaks decryption (correctness condition of Section 3.1)
+    # noise beyond Delta/2 breaks decryption (correctness condition of the "Homomorphic Operations in BFV" section)
     N = 1024
     primes = orc.ntt_primes(N, 1, 31)
     q = primes[0]
@@ -253,7 +253,7 @@ CASES = [
 @pytest.mark.parametrize("case", CASES)
 def test_he_conv_decrypts_to_plain_conv(case):
     # lossless claim: decrypting the HE convolution gives the plaintext
-    # convolution exactly (Sections 1 and 4.2.1)
+    # convolution exactly (the introduction and the "Optimal Parameter Selection" section)
     N, L, bits, H, W, Ci, Co, k, dw, cir = case
     primes = orc.ntt_primes(N, L, bits)
     pl = orc.plan(N, H, W, Ci, Co, k, dw, cir)
@@ -304,7 +304,7 @@ def test_noise_overflow_breaks_decryption():
     assert not np.array_equal(orc.unpack_output(pl, dec), orc.direct_conv(x, w, 3))
 
 
-# ---------------------------------------------------------------- Walsh-Hadamard (Section 4.1)
+# ---------------------------------------------------------------- Walsh-Hadamard (the "Enabling Output Channel Packing" section)
 
 def test_walsh_basis_c4_is_the_printed_one():
     assert np.array_equal(orc.walsh_matrix(4), _golden("walsh_basis_c4.txt"))
@@ -326,6 +326,23 @@ def test_hadamard2_equation():
         assert list(orc.walsh_matrix(2) @ g) == [2 * f0, 2 * f1]
 
 
+def test_walsh_kernel_is_kernel_of_walsh_weights_for_standard_layers():
+    # linearity: for a standard layer the Walsh kernel equals the kernel
+    # polynomial built from the Walsh weights g = H f
+    N = 1024
+    primes = orc.ntt_primes(N, 1, 31)
+    pl = orc.plan(N, 6, 6, 5, 8, 3)
+    w = wl.weights(3, wl.Layer("t", 6, 6, 5, 8, 3))
+    gw = orc.walsh_weights(w, 4)
+    q = primes[0]
+    inv = pow(4, -1, q)
+    for G in range(2):
+        for j in range(4):
+            want = (orc._lift(orc.kernel_poly(pl, gw, G * 4 + j, 0), q).astype(np.uint64) * inv) % q
+            got = orc.walsh_kernel_residues(pl, w, 4, primes, G, j, 0)[0]
+            assert np.array_equal(got, want.astype(np.uint32))
+
+
 def test_walsh_weights_invert():
     w = wl.weights(3, wl.Layer("t", 4, 4, 5, 16, 3)).astype(np.int64)
     for c_n in (2, 4, 16):
@@ -334,22 +351,25 @@ def test_walsh_weights_invert():
         assert np.array_equal(back, c_n * w)
 
 
-@pytest.mark.parametrize("c_n", [2, 4])
-def test_walsh_kernels_reproduce_plain_product(c_n):
+@pytest.mark.parametrize("c_n,dw", [(2, False), (4, False), (2, True), (4, True)])
+def test_walsh_kernels_reproduce_plain_product(c_n, dw):
     # sum_j H[b][j] sum_g ct_g * (c_n^-1 Kw_{G,j,g}) == sum_g ct_g * K_{G c_n + b, g}
     N, L = 1024, 2
     primes = orc.ntt_primes(N, L, 31)
-    pl = orc.plan(N, 6, 6, 5, 8, 3)
+    C = 8
+    pl = orc.plan(N, 6, 6, 5 if not dw else C, C, 3, dw)
     rng = np.random.default_rng(8)
     ct = np.stack([rng.integers(0, q, size=(pl.tiles, pl.n_groups, 2, N)) for q in primes],
                   axis=3).astype(np.uint32)
-    w = wl.weights(9, wl.Layer("t", 6, 6, 5, 8, 3))
+    w = wl.weights(9, wl.Layer("t", 6, 6, pl.Ci, C, 3, depthwise=dw))
     plain = orc.conv_products(pl, ct, w, primes)
     H = orc.walsh_matrix(c_n)
     for G in range(pl.Co // c_n):
         A = np.zeros((c_n, 2, L, N), dtype=np.int64)
         for j in range(c_n):
             for g in range(pl.n_groups):
+                if dw and g != (G * c_n) // pl.ci:
+                    continue
                 Kw = orc.walsh_kernel_residues(pl, w, c_n, primes, G, j, g)
                 for p in range(2):
                     for i, q in enumerate(primes):
