@@ -1,0 +1,238 @@
+/*
+ * hyena.h -- C ABI of the MI355X (gfx950) homomorphic-convolution library.
+ *
+ * Method: Roh & Choi, "Hyena: Optimizing Homomorphically Encrypted
+ * Convolution for Private CNN Inference", ICCAD 2024.
+ *
+ * The library computes the cloud side of a homomorphically encrypted
+ * convolution layer: BFV ciphertexts of coefficient-encoded, zero-padded
+ * activation tensors are multiplied by kernel polynomials built from integer
+ * weights and summed over input ciphertexts, in Z_q[X]/(X^N+1) with q a
+ * product of RNS primes q_i < 2^31, q_i = 1 mod 2N.
+ *
+ *  - the "Homomorphic Operations in BFV" section: ciphertexts, HAdd, PMult,
+ *    CMult; symmetric encryption and decryption (test setup only).
+ *  - the "Prior Art on Homomorphic Convolution" section: padded convolution,
+ *    weights kept as integers and applied as CMult scalars; the C x H x W
+ *    tensor split over ceil(CHW/n) ciphertexts.
+ *  - the "Enabling Output Channel Packing" section, Eq. (hadamard2) and its
+ *    c_n = 2^k generalisation: output channels handled in groups of c_n
+ *    through Walsh-Hadamard weights.
+ *  - the "Lazy Reduction" section: products accumulated unreduced in a wide
+ *    integer, one reduction per output coefficient.
+ *
+ * Conventions shared by every call:
+ *  - Return 0 (HYENA_OK) on success or a negative HYENA_E* code; the text of
+ *    the last error of the calling thread is returned by hyena_last_error().
+ *  - Residues are uint32, canonical in [0, q_i). Polynomial arrays are limb
+ *    major: [..][L][N], N consecutive coefficients per limb.
+ *  - "Host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the device that was current at hyena_create. Device calls are
+ *    asynchronous on the given stream (0 = the null stream); the caller keeps
+ *    every buffer alive until the stream has passed the call.
+ *  - The caller allocates and owns every buffer it passes. The library keeps
+ *    no caller pointer after a call returns. A context owns its twiddle and
+ *    constant tables (device memory) until hyena_destroy; after creation it is
+ *    read-only and may be shared by threads and streams.
+ *  - No call allocates device memory except hyena_create, hyena_batch_create
+ *    and the explicit workspace queries' callers.
+ */
+#ifndef HYENA_H
+#define HYENA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hyena_stream_t; /* identical to hipStream_t */
+
+enum {
+    HYENA_OK = 0,
+    HYENA_EINVAL = -1,       /* null pointer, bad shape, c_n not a power of two ... */
+    HYENA_EUNSUPPORTED = -2, /* N, primes or security level not supported */
+    HYENA_ENOISE = -3,       /* worst-case noise or output would break decryption */
+    HYENA_EHIP = -4,         /* HIP runtime error */
+    HYENA_ENOMEM = -5        /* allocation failure */
+};
+
+/* hyena_create flags */
+#define HYENA_ALLOW_INSECURE 0x1u /* skip the 128-bit security ceiling on log2 q */
+#define HYENA_HOST_ONLY 0x2u      /* no device tables: only the host calls may be used */
+
+typedef struct hyena_ctx hyena_ctx;
+
+/*
+ * Create a context for ring degree N in {4096, 8192, 16384} (any power of two
+ * from 1024 to 16384 is accepted) with L RNS limbs and plaintext modulus
+ * t = 2^log2_t (1 <= log2_t <= 30).
+ *
+ * primes: L distinct primes, each 2^29 < q_i < 2^31 and q_i = 1 mod 2N (the
+ * NTT condition of the "Optimal Parameter Selection" section, step 1), or NULL for the defaults: the L
+ * largest such primes below 2^31 (below 2^30 if flags has bit 0x100,
+ * HYENA_PRIMES_30BIT). psi_i is the smallest integer >= 2 with
+ * psi_i^N = -1 mod q_i.
+ *
+ * Unless HYENA_ALLOW_INSECURE is set, sum log2 q_i must not exceed the
+ * 128-bit ceiling of the HE security standard for a ternary secret
+ * (N = 4096: 109 bits, 8192: 218, 16384: 438); the paper runs its parameters
+ * at 128-bit security (the "Evaluation Setup" section).
+ *
+ * Allocates the device tables on the current HIP device, unless flags has
+ * HYENA_HOST_ONLY (then device calls return EINVAL). Errors: EINVAL,
+ * EUNSUPPORTED, EHIP, ENOMEM.
+ */
+#define HYENA_PRIMES_30BIT 0x100u
+int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint32_t log2_t,
+                 uint32_t flags, hyena_ctx **out);
+void hyena_destroy(hyena_ctx *ctx);
+const char *hyena_last_error(void);
+
+/* Read back parameters: primes[L] and psi[L] (host arrays, either may be NULL). */
+int hyena_get_params(const hyena_ctx *ctx, uint32_t *N, uint32_t *L,
+                     uint32_t *primes, uint32_t *psi);
+
+/* ------------------------------------------------------------------------
+ * Test setup (host, deterministic by seed); "Homomorphic Operations in BFV".
+ * Random numbers: output number c of SplitMix64 seeded with key is
+ * mix(key + (c+1) * 0x9E3779B97F4A7C15) (Steele, Lea & Flood 2014).
+ * ---------------------------------------------------------------------- */
+
+/* Ternary secret: sk[j] = floor(3 * hi32(sm64(seed, j)) / 2^32) - 1. */
+int hyena_keygen(const hyena_ctx *ctx, uint64_t seed, int8_t *sk /* host [N] */);
+
+/*
+ * Symmetric BFV encryption of n messages (the "Homomorphic Operations in BFV" section):
+ *   c0 = [Delta*m + a*s + e]_q,  c1 = [-a]_q,  Delta = floor(q / t).
+ * msg: host int32 [n][N], centered in (-t/2, t/2]. ct: host uint32
+ * [n][2][L][N], coefficient domain. a_{m,i,j} = floor(q_i * sm64(seed,
+ * 2*((m*L+i)*N+j)) / 2^64); e_{m,j} is the rounded Gaussian, sigma = 3.2,
+ * bounded by B = 10 sigma (32), drawn from sm64(seed, 2*(m*N+j)+1) by an
+ * integer threshold table. Errors: EINVAL.
+ */
+int hyena_encrypt(const hyena_ctx *ctx, const int8_t *sk, const int32_t *msg,
+                  size_t n, uint64_t seed, uint32_t *ct);
+
+/*
+ * Decryption m = [round(t * [c0 + c1 s]_q / q)]_t, centered in (-t/2, t/2].
+ * ct: host uint32 [n][2][L][N] coefficient domain; msg: host int32 [n][N].
+ * Exact whenever the noise is below Delta/2 by a margin of L * 2^-30 q/t.
+ */
+int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
+                  size_t n, int32_t *msg);
+
+/* ------------------------------------------------------------------------
+ * Planning and layout (host).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Convolution layer descriptor. Fields marked "in" are set by the caller,
+ * "out" by hyena_conv_plan.
+ *
+ * Geometry (coefficient encoding of the zero-padded tensor, the "Prior Art on Homomorphic Convolution" section):
+ * p = (k-1)/2, Wp = W + 2p. If (H+2p)*Wp <= N the whole padded channel fits:
+ * R = H, tiles = 1, Bt = (H+2p)*Wp and ci = min(Ci, N/Bt) channels share a
+ * ciphertext (a caller may lower it through ci_req). Otherwise one channel is
+ * split into row tiles: ci = 1, R = N/Wp - 2p, tiles = ceil(H/R),
+ * Bt = (R+2p)*Wp. Input channel c' of group g sits at coefficients
+ * c'*Bt + r*Wp + col. The kernel polynomial of output o and group g is
+ * K_{o,g}(X) = sum f[o][g*ci+c'][di][dj] X^(O - c'*Bt - di*Wp - dj), with
+ * O = (ci-1)*Bt + (k-1)*Wp + (k-1); output row r, column col of tile tau is
+ * the coefficient O + r*Wp + col of output ciphertext (tau, o).
+ */
+typedef struct {
+    /* in */
+    uint32_t H, W, Ci, Co, k;   /* square or rectangular input, k in {1, 3} */
+    uint32_t stride;            /* 1 or 2: the server always computes stride 1 */
+    uint32_t depthwise;         /* 1: Co == Ci, one k x k filter per channel */
+    uint32_t c_n;               /* Walsh group size: power of two dividing Co */
+    uint32_t flags;             /* HYENA_FUSE_WHT ... */
+    uint32_t ci_req;            /* 0 = as many channels per ciphertext as fit */
+    uint32_t batch;             /* images sharing the weights (>= 1; 0 means 1) */
+    /* out */
+    uint32_t pad, Wp, R, tiles, ci, Bt, O, n_groups;
+    uint32_t n_in;              /* input ciphertexts per image = tiles * n_groups */
+    uint32_t n_out;             /* output ciphertexts per image = tiles * Co */
+    uint32_t w_groups;          /* g extent of the weight array: n_groups, or 1 if depthwise */
+} hyena_conv_desc;
+
+#define HYENA_FUSE_WHT 0x1u  /* Walsh butterflies fused into the MAC epilogue */
+
+/*
+ * Fill the "out" fields. Errors: EINVAL (shape), ENOISE (worst-case noise
+ * sum_g ||e_g K_{o,g}||_inf with |e| <= 32, or worst-case |y| over signed
+ * 4-bit activations and the 4-bit weight bound |f| <= 8, breaks the
+ * decryption condition ||v|| < Delta/2 of the "Homomorphic Operations in BFV" section or |y| < t/2).
+ */
+int hyena_conv_plan(const hyena_ctx *ctx, hyena_conv_desc *desc);
+
+/* x: host int8 [Ci][H][W] -> msg: host int32 [tiles][n_groups][N] (zero
+ * padding included; unused coefficients are 0). */
+int hyena_pack_input(const hyena_conv_desc *desc, uint32_t N, const int8_t *x, int32_t *msg);
+
+/* msg: host int32 [tiles][Co][N], decrypted outputs in hyena_conv order ->
+ * y: host int32 [Co][H][W], the stride-1 output (subsample for stride 2). */
+int hyena_unpack_output(const hyena_conv_desc *desc, uint32_t N, const int32_t *msg, int32_t *y);
+
+/* ------------------------------------------------------------------------
+ * Device hot path (device pointers, asynchronous on stream).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Offline weight preparation (the cloud stores kernel elements as integers,
+ * the "Enabling Output Channel Packing" section; the polynomial form is derived from them once per layer).
+ * For each Walsh group G, Walsh index j and input group g:
+ *   gw[G*c_n+j] = sum_b H[j][b] f[G*c_n+b]     (Sylvester H_{c_n})
+ *   Kw_{G,j,g} = c_n^{-1} (mod q_i) * (kernel polynomial of gw, as K above)
+ *   d_wntt[G][j][g][i] = NTT_i(Kw_{G,j,g})      (same transform as hyena_ntt)
+ * d_w: device int8 [Co][Ci][k][k] ([Co][1][k][k] if depthwise).
+ * d_wntt: device uint32 [Co/c_n][c_n][w_groups][L][N]. For c_n = 1 this is the
+ * NTT of K_{o,g}. Errors: EINVAL, EHIP.
+ */
+int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
+                         const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
+
+/*
+ * In-place forward negacyclic NTT of P polynomials, d_poly: device uint32
+ * [P][L][N] (limb i uses q_i):
+ *   A[k] = sum_j a[j] psi_i^((2 brv(k) + 1) j) mod q_i
+ * (evaluation at the odd powers of psi_i, bit-reversed order; the transform
+ * that turns the negacyclic product into a pointwise one, q = 1 mod 2N).
+ */
+int hyena_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
+
+/* In-place inverse of hyena_ntt, including the factor N^{-1}. */
+int hyena_intt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
+
+/*
+ * The homomorphic convolution in the NTT domain (Sections 3.2, 4.1, 4.2.2):
+ *   A[b][tau][G][j][p][i][k] = sum_g ct[b][tau][g][p][i][k] * W[G][j][g][i][k]  mod q_i
+ * accumulated lazily in 64 bits with one reduction per output coefficient.
+ * With HYENA_FUSE_WHT (or c_n = 1) the output is already per output channel:
+ *   Y[.][G*c_n+b] = sum_j H[b][j] A[.][G][j]  mod q_i,
+ * otherwise it holds the Walsh components A and hyena_wht_pack finishes.
+ * d_ct_ntt: device uint32 [batch][tiles][n_groups][2][L][N], NTT domain.
+ * d_wntt:   device uint32 [Co/c_n][c_n][w_groups][L][N] (hyena_encode_weights).
+ * d_out_ntt: device uint32 [batch][tiles][Co][2][L][N]; must not alias inputs.
+ * Errors: EINVAL, EHIP.
+ */
+int hyena_conv(const hyena_ctx *ctx, const hyena_conv_desc *desc,
+               const uint32_t *d_ct_ntt, const uint32_t *d_wntt,
+               uint32_t *d_out_ntt, hyena_stream_t stream);
+
+/*
+ * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
+ *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
+ * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by
+ * the position: blocks are [2][L][N] ciphertexts (poly_words = 2*L*N).
+ * d_in, d_out: device uint32 [G][c_n][2][L][N]; d_out may alias d_in.
+ */
+int hyena_wht_pack(const hyena_ctx *ctx, uint32_t c_n, const uint32_t *d_in,
+                   uint32_t *d_out, size_t G, hyena_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYENA_H */

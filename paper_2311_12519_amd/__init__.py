@@ -1,0 +1,267 @@
+"""Python binding of libhyena.so, the gfx950 Hyena homomorphic-convolution library.
+
+Argument marshalling only: every step of the convolution runs in the HIP
+kernels of the library. Host calls take numpy arrays; device calls take
+torch tensors that live on the GPU (torch is used for device memory and
+streams only) and the stream to run on (default: torch's current stream).
+
+The function names are those of the C ABI in ``include/hyena.h``. Importing
+this package never falls back to anything: if ``libhyena.so`` is missing or
+cannot be loaded, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhyena.so")
+
+HYENA_OK = 0
+HYENA_EINVAL = -1
+HYENA_EUNSUPPORTED = -2
+HYENA_ENOISE = -3
+HYENA_EHIP = -4
+HYENA_ENOMEM = -5
+
+HYENA_ALLOW_INSECURE = 0x1
+HYENA_HOST_ONLY = 0x2
+HYENA_PRIMES_30BIT = 0x100
+HYENA_FUSE_WHT = 0x1
+
+_ERRNAMES = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOISE", -4: "EHIP", -5: "ENOMEM"}
+
+
+class HyenaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"HYENA_{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ConvDesc(ctypes.Structure):
+    """Mirror of hyena_conv_desc."""
+    _fields_ = [(n, ctypes.c_uint32) for n in (
+        "H", "W", "Ci", "Co", "k", "stride", "depthwise", "c_n", "flags", "ci_req", "batch",
+        "pad", "Wp", "R", "tiles", "ci", "Bt", "O", "n_groups", "n_in", "n_out", "w_groups")]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+
+_SIGS = {
+    "hyena_create": [_u32, _u32, _P, _u32, _u32, _P],
+    "hyena_destroy": [_P],
+    "hyena_get_params": [_P, _P, _P, _P, _P],
+    "hyena_keygen": [_P, _u64, _P],
+    "hyena_encrypt": [_P, _P, _P, _sz, _u64, _P],
+    "hyena_decrypt": [_P, _P, _P, _sz, _P],
+    "hyena_conv_plan": [_P, _P],
+    "hyena_pack_input": [_P, _u32, _P, _P],
+    "hyena_unpack_output": [_P, _u32, _P, _P],
+    "hyena_encode_weights": [_P, _P, _P, _P, _P],
+    "hyena_ntt": [_P, _P, _sz, _P],
+    "hyena_intt": [_P, _P, _sz, _P],
+    "hyena_conv": [_P, _P, _P, _P, _P, _P],
+    "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhyena.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2311_12519_amd/build.py` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "hyena_destroy" else ctypes.c_int
+        L.hyena_last_error.restype = ctypes.c_char_p
+        L.hyena_last_error.argtypes = []
+        _register_extra(L)
+        _lib = L
+    return _lib
+
+
+def _register_extra(L):
+    """Signatures of the batched-path and cost-model entry points, if present."""
+    extra = {
+        "hyena_batch_create": [_P, _P, _u32, _u32, _P, _P],
+        "hyena_batch_destroy": [_P],
+        "hyena_batch_run": [_P, _P, _P, _P, _P],
+        "hyena_batch_capture": [_P, _P, _P, _P, _P],
+        "hyena_batch_replay": [_P, _P],
+        "hyena_batch_info": [_P, _P],
+        "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, ctypes.c_int, _P],
+        "hyena_mlp_forward": [_P, _P, _P, _u32, _P],
+        "hyena_mlp_backward": [_P, _P, _P, _P, _u32, _P, _P],
+        "hyena_mlp_adam": [_P, _P, _P, _P, _u32, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float, _u32, _P],
+    }
+    for name, args in extra.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "hyena_batch_destroy" else ctypes.c_int
+
+
+def _check(code: int) -> None:
+    if code != HYENA_OK:
+        raise HyenaError(code, lib().hyena_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray, dtype) -> ctypes.c_void_p:
+    if a.dtype != dtype or not a.flags["C_CONTIGUOUS"]:
+        raise TypeError(f"expected a C-contiguous {np.dtype(dtype).name} array")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev_ptr(t, dtype_name: str) -> ctypes.c_void_p:
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch." + dtype_name:
+        raise TypeError(f"expected a contiguous device tensor of torch.{dtype_name}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+class Ctx:
+    """Owns a hyena_ctx handle; destroyed with the object."""
+
+    def __init__(self, handle: ctypes.c_void_p, N: int, L: int, log2_t: int):
+        self.handle = handle
+        self.N, self.L, self.log2_t = N, L, log2_t
+        p = np.zeros(L, dtype=np.uint32)
+        s = np.zeros(L, dtype=np.uint32)
+        _check(lib().hyena_get_params(handle, None, None, _np_ptr(p, np.uint32), _np_ptr(s, np.uint32)))
+        self.primes = [int(x) for x in p]
+        self.psi = [int(x) for x in s]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.hyena_destroy(h)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def hyena_create(N: int, L: int, primes=None, log2_t: int = 20, flags: int = 0) -> Ctx:
+    out = ctypes.c_void_p()
+    pr = None
+    if primes is not None:
+        arr = np.ascontiguousarray(primes, dtype=np.uint32)
+        pr = _np_ptr(arr, np.uint32)
+    _check(lib().hyena_create(N, L, pr, log2_t, flags, ctypes.byref(out)))
+    return Ctx(out, N, L, log2_t)
+
+
+def hyena_destroy(ctx: Ctx) -> None:
+    if ctx.handle:
+        lib().hyena_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def hyena_keygen(ctx: Ctx, seed: int) -> np.ndarray:
+    sk = np.zeros(ctx.N, dtype=np.int8)
+    _check(lib().hyena_keygen(ctx.handle, seed, _np_ptr(sk, np.int8)))
+    return sk
+
+
+def hyena_encrypt(ctx: Ctx, sk: np.ndarray, msg: np.ndarray, seed: int) -> np.ndarray:
+    msg = np.ascontiguousarray(msg, dtype=np.int32).reshape(-1, ctx.N)
+    ct = np.zeros((msg.shape[0], 2, ctx.L, ctx.N), dtype=np.uint32)
+    _check(lib().hyena_encrypt(ctx.handle, _np_ptr(np.ascontiguousarray(sk, dtype=np.int8), np.int8),
+                               _np_ptr(msg, np.int32), msg.shape[0], seed, _np_ptr(ct, np.uint32)))
+    return ct
+
+
+def hyena_decrypt(ctx: Ctx, sk: np.ndarray, ct: np.ndarray) -> np.ndarray:
+    ct = np.ascontiguousarray(ct, dtype=np.uint32).reshape(-1, 2, ctx.L, ctx.N)
+    msg = np.zeros((ct.shape[0], ctx.N), dtype=np.int32)
+    _check(lib().hyena_decrypt(ctx.handle, _np_ptr(np.ascontiguousarray(sk, dtype=np.int8), np.int8),
+                               _np_ptr(ct, np.uint32), ct.shape[0], _np_ptr(msg, np.int32)))
+    return msg
+
+
+def hyena_conv_plan(ctx: Ctx, H: int, W: int, Ci: int, Co: int, k: int = 3, *, stride: int = 1,
+                    depthwise: bool = False, c_n: int = 1, flags: int = 0, ci_req: int = 0,
+                    batch: int = 1) -> ConvDesc:
+    d = ConvDesc(H=H, W=W, Ci=Ci, Co=Co, k=k, stride=stride, depthwise=int(depthwise), c_n=c_n,
+                 flags=flags, ci_req=ci_req, batch=batch)
+    _check(lib().hyena_conv_plan(ctx.handle, ctypes.byref(d)))
+    return d
+
+
+def hyena_pack_input(desc: ConvDesc, N: int, x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.int8)
+    msg = np.zeros((desc.tiles, desc.n_groups, N), dtype=np.int32)
+    _check(lib().hyena_pack_input(ctypes.byref(desc), N, _np_ptr(x, np.int8), _np_ptr(msg, np.int32)))
+    return msg
+
+
+def hyena_unpack_output(desc: ConvDesc, N: int, msg: np.ndarray) -> np.ndarray:
+    msg = np.ascontiguousarray(msg, dtype=np.int32)
+    y = np.zeros((desc.Co, desc.H, desc.W), dtype=np.int32)
+    _check(lib().hyena_unpack_output(ctypes.byref(desc), N, _np_ptr(msg, np.int32), _np_ptr(y, np.int32)))
+    return y
+
+
+# ---------------------------------------------------------------------------
+# device hot path
+# ---------------------------------------------------------------------------
+
+def hyena_encode_weights(ctx: Ctx, desc: ConvDesc, d_w, d_wntt, stream=None) -> None:
+    _check(lib().hyena_encode_weights(ctx.handle, ctypes.byref(desc), _dev_ptr(d_w, "int8"),
+                                      _dev_ptr(d_wntt, "int32"), _stream(stream)))
+
+
+def hyena_ntt(ctx: Ctx, d_poly, stream=None) -> None:
+    P = d_poly.numel() // (ctx.L * ctx.N)
+    if P * ctx.L * ctx.N != d_poly.numel():
+        raise ValueError("tensor size is not a multiple of L*N")
+    _check(lib().hyena_ntt(ctx.handle, _dev_ptr(d_poly, "int32"), P, _stream(stream)))
+
+
+def hyena_intt(ctx: Ctx, d_poly, stream=None) -> None:
+    P = d_poly.numel() // (ctx.L * ctx.N)
+    if P * ctx.L * ctx.N != d_poly.numel():
+        raise ValueError("tensor size is not a multiple of L*N")
+    _check(lib().hyena_intt(ctx.handle, _dev_ptr(d_poly, "int32"), P, _stream(stream)))
+
+
+def hyena_conv(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_wntt, d_out_ntt, stream=None) -> None:
+    _check(lib().hyena_conv(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct_ntt, "int32"),
+                            _dev_ptr(d_wntt, "int32"), _dev_ptr(d_out_ntt, "int32"), _stream(stream)))
+
+
+def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:
+    _check(lib().hyena_wht_pack(ctx.handle, c_n, _dev_ptr(d_in, "int32"), _dev_ptr(d_out, "int32"),
+                                G, _stream(stream)))
+
+
+def wntt_words(ctx: Ctx, desc: ConvDesc) -> int:
+    """uint32 words of the encoded-weight array [Co][w_groups][L][N]."""
+    return desc.Co * desc.w_groups * ctx.L * ctx.N
+
+
+def u32_view(t):
+    """Reinterpret an int32 device tensor's words as unsigned (host numpy side)."""
+    return t.cpu().numpy().view(np.uint32)

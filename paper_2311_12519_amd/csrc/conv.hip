@@ -1,0 +1,403 @@
+// NTT-domain homomorphic convolution for gfx950: weight encoding, the lazy
+// multiply-accumulate over input ciphertexts and the Walsh-Hadamard butterflies.
+//
+// For NTT slot (limb i, coefficient k) the layer is a small dense product over
+// input groups g:
+//   A[row][o] = sum_g ct[row][g] * W[o][g]  (mod q_i),  row = (image, tile, part)
+// (the padded convolution of the "Prior Art on Homomorphic Convolution" section
+// with the Walsh kernel polynomials of "Enabling Output Channel Packing").
+// Products are 62-bit; they are accumulated in 64-bit registers without
+// reduction (the "Lazy Reduction" section). Because q_i is close to 2^31,
+// 2^32 mod q_i is small, so one multiply-add folds the accumulator back to
+// about 2^54 every F products: acc <- hi32(acc) * (2^32 mod q) + lo32(acc).
+// One full reduction per output coefficient follows the sum, before the
+// Walsh-Hadamard recombination (the reduction point the paper puts before the
+// PMult by the +-1 pattern).
+#include <algorithm>
+
+#include "internal.h"
+
+namespace {
+
+__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t q) { return min(x, x - q); }
+
+__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+    return csub(a * w - __umulhi(a, ws) * q, q);
+}
+
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
+    return (uint64_t)a * b + c;  // one v_mad_u64_u32
+}
+
+// Exact reduction of a 64-bit accumulator to [0, q).
+__device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
+    const uint32_t q = lc.q;
+    const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
+    // hi mod q: floor(hi * mu32 / 2^32) is floor(hi / q) or one less
+    const uint32_t hr = csub(hi - __umulhi(hi, lc.mu32) * q, q);
+    // y = hi * 2^32 + lo = hr * r32 + lo (mod q), y < q * 2^32
+    const uint64_t y = mad64(hr, lc.r32, lo);
+    // Montgomery REDC: z = y * 2^-32 mod q in [0, 2q)
+    const uint32_t m = (uint32_t)y * lc.qinv_neg;
+    const uint64_t t = mad64(m, q, y);
+    const uint32_t z = csub((uint32_t)(t >> 32), q);
+    // times 2^32 mod q
+    return shoup(z, lc.r32, lc.r32s, q);
+}
+
+__device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t r32) {
+    return mad64((uint32_t)(acc >> 32), r32, (uint32_t)acc);
+}
+
+struct MacArgs {
+    const uint32_t *ct;   // [rows/2][n_groups][2][L][N]
+    const uint32_t *w;    // [Co][w_groups][L][N]
+    uint32_t *out;        // [rows/2][Co][2][L][N]
+    uint32_t N, L, logN, Co, n_groups, w_groups, rows, ci, c_n;
+    uint32_t depthwise, fuse, n_ot, n_mt, kchunks;
+    LimbTable lt;
+};
+
+// One thread = one NTT slot (limb, k) for MT rows x OT outputs. Blocks are
+// 256 threads along k. The block index is remapped so that all o- and
+// row-tiles of one k-chunk land on the same XCD (blocks are dealt to the 8
+// XCDs round robin) and share its L2 for the ciphertext and weight reads.
+template <int MT, int OT>
+__global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
+    const uint32_t nb = gridDim.x;
+    const uint32_t xcd = blockIdx.x & 7u, local = blockIdx.x >> 3;
+    const uint32_t per = (nb + 7) >> 3;  // logical blocks per XCD (ceil)
+    // XCD x gets logical blocks [x*per, ...), limited by nb
+    const uint32_t full = nb - (per - 1) * 8;  // XCDs that get `per` blocks
+    uint32_t logical;
+    if (xcd < full) logical = xcd * per + local;
+    else logical = full * per + (xcd - full) * (per - 1) + local;
+    const uint32_t mt = logical % a.n_mt;
+    const uint32_t ot = (logical / a.n_mt) % a.n_ot;
+    const uint32_t kc = logical / (a.n_mt * a.n_ot);
+    const uint32_t limb = kc / a.kchunks;
+    const uint32_t k = (kc % a.kchunks) * 256 + threadIdx.x;
+    const LimbConst lc = a.lt.c[limb];
+    const uint32_t r32 = lc.r32;
+    const size_t LN = (size_t)a.L * a.N;
+    const size_t slot = (size_t)limb * a.N + k;
+    const uint32_t row0 = mt * MT, o0 = ot * OT;
+
+    uint32_t g0 = 0, g1 = a.n_groups;
+    if (a.depthwise) {
+        g0 = o0 / a.ci;
+        g1 = g0 + 1;
+    }
+    const uint32_t *ctp[MT];
+#pragma unroll
+    for (int r = 0; r < MT; r++) {
+        const uint32_t row = min(row0 + r, a.rows - 1);
+        ctp[r] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN + slot;
+    }
+    const uint32_t *wp[OT];
+#pragma unroll
+    for (int j = 0; j < OT; j++) {
+        const uint32_t o = min(o0 + j, a.Co - 1);
+        wp[j] = a.w + (size_t)o * a.w_groups * LN + slot;
+    }
+    uint64_t acc[MT][OT];
+#pragma unroll
+    for (int r = 0; r < MT; r++)
+#pragma unroll
+        for (int j = 0; j < OT; j++) acc[r][j] = 0;
+
+    const uint32_t F = lc.fold;
+    uint32_t g = g0;
+    while (g < g1) {
+        const uint32_t gend = min(g1, g + F);
+        for (; g < gend; g++) {
+            uint32_t x[MT], w[OT];
+            const size_t gc = (size_t)g * 2 * LN;
+            const size_t gw = a.depthwise ? 0 : (size_t)g * LN;
+#pragma unroll
+            for (int r = 0; r < MT; r++) x[r] = ctp[r][gc];
+#pragma unroll
+            for (int j = 0; j < OT; j++) w[j] = wp[j][gw];
+#pragma unroll
+            for (int r = 0; r < MT; r++)
+#pragma unroll
+                for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
+        }
+#pragma unroll
+        for (int r = 0; r < MT; r++)
+#pragma unroll
+            for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
+    }
+
+    const uint32_t q = lc.q;
+#pragma unroll
+    for (int r = 0; r < MT; r++) {
+        uint32_t y[OT];
+#pragma unroll
+        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
+        if (a.fuse) {
+            // Walsh-Hadamard butterflies over each aligned group of c_n outputs
+#pragma unroll
+            for (int h = 1; h < OT; h <<= 1) {
+                if ((uint32_t)h >= a.c_n) break;
+#pragma unroll
+                for (int j = 0; j < OT; j++) {
+                    if (j & h) continue;
+                    const uint32_t u = y[j], v = y[j + h];
+                    y[j] = csub(u + v, q);
+                    y[j + h] = csub(u - v + q, q);
+                }
+            }
+        }
+        const uint32_t row = row0 + r;
+        if (row >= a.rows) break;
+        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN + slot;
+#pragma unroll
+        for (int j = 0; j < OT; j++) {
+            if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN] = y[j];
+        }
+    }
+}
+
+// Standalone Walsh-Hadamard recombination: out[G][b] = sum_j H[b][j] in[G][j].
+// One thread per (G, word of a [2][L][N] block); c_n <= 64 residues in registers.
+template <int CN>
+__global__ void __launch_bounds__(256) wht_kernel(const uint32_t *in, uint32_t *out,
+                                                  size_t G, uint32_t N, uint32_t L, LimbTable lt) {
+    const size_t words = (size_t)2 * L * N;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= G * words) return;
+    const size_t gg = idx / words, wi = idx % words;
+    const uint32_t q = lt.c[(wi / N) % L].q;
+    const uint32_t *src = in + gg * CN * words + wi;
+    uint32_t y[CN];
+#pragma unroll
+    for (int j = 0; j < CN; j++) y[j] = src[(size_t)j * words];
+#pragma unroll
+    for (int h = 1; h < CN; h <<= 1)
+#pragma unroll
+        for (int j = 0; j < CN; j++) {
+            if (j & h) continue;
+            const uint32_t u = y[j], v = y[j + h];
+            y[j] = csub(u + v, q);
+            y[j + h] = csub(u - v + q, q);
+        }
+    uint32_t *dst = out + gg * CN * words + wi;
+#pragma unroll
+    for (int j = 0; j < CN; j++) dst[(size_t)j * words] = y[j];
+}
+
+__global__ void fill_zero_kernel(uint32_t *p, size_t n) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i < n; i += (size_t)gridDim.x * 256) p[i] = 0;
+}
+
+// Scatter the taps of every Walsh kernel polynomial into a zeroed
+// [Co][w_groups][L][N] array (coefficient domain). Thread per (o, tap):
+//   value = c_n^{-1} * sum_b H[j][b] f[G*c_n+b][ch][di][dj]  mod q_i,
+//   exponent O - c'*Bt - di*Wp - dj,  o = G*c_n + j,  ch = g*ci + c'.
+struct EncArgs {
+    const int8_t *w;
+    uint32_t *out;
+    uint32_t N, L, Co, Ci, k, ci, Bt, Wp, O, n_groups, w_groups, c_n, depthwise;
+    uint32_t cninv[HYENA_MAX_LIMBS];
+    LimbTable lt;
+};
+
+__global__ void encode_scatter_kernel(EncArgs a) {
+    const uint32_t kk = a.k * a.k;
+    // standard: thread per (o, input channel, di, dj), value sums the c_n
+    // Walsh terms at one position; depthwise: thread per (o, b, di, dj), the
+    // c_n terms of a Walsh kernel sit at the c_n channel positions of the group
+    const uint32_t inner = a.depthwise ? a.c_n : a.Ci;
+    const size_t total = (size_t)a.Co * inner * kk;
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const uint32_t o = (uint32_t)(idx / ((size_t)inner * kk));
+    const uint32_t rem = (uint32_t)(idx % ((size_t)inner * kk));
+    const uint32_t cw = rem / kk, di = (rem % kk) / a.k, dj = rem % a.k;
+    const uint32_t G = o / a.c_n, j = o % a.c_n;
+    int32_t gsum = 0;
+    uint32_t ch;
+    if (a.depthwise) {
+        const uint32_t b = cw;
+        const int sgn = (__popc(j & b) & 1) ? -1 : 1;
+        ch = G * a.c_n + b;
+        gsum = sgn * (int32_t)a.w[((size_t)ch * a.k + di) * a.k + dj];
+    } else {
+        ch = cw;
+        for (uint32_t b = 0; b < a.c_n; b++) {
+            const int sgn = (__popc(j & b) & 1) ? -1 : 1;
+            gsum += sgn * (int32_t)a.w[(((size_t)(G * a.c_n + b) * a.Ci + cw) * a.k + di) * a.k + dj];
+        }
+    }
+    if (gsum == 0) return;
+    const uint32_t g = ch / a.ci, cp = ch % a.ci;
+    const uint32_t e = a.O - cp * a.Bt - di * a.Wp - dj;
+    const uint32_t gslot = a.depthwise ? 0 : g;
+    for (uint32_t i = 0; i < a.L; i++) {
+        const uint32_t q = a.lt.c[i].q;
+        const int64_t v = (int64_t)gsum % (int64_t)q;
+        const uint32_t vr = (uint32_t)(v < 0 ? v + q : v);
+        const uint32_t val = (uint32_t)((uint64_t)vr * a.cninv[i] % q);
+        a.out[(((size_t)o * a.w_groups + gslot) * a.L + i) * a.N + e] = val;
+    }
+}
+
+template <int MT, int OT>
+hipError_t launch_mac(const MacArgs &base, hipStream_t s) {
+    MacArgs a = base;
+    a.n_ot = (a.Co + OT - 1) / OT;
+    a.n_mt = (a.rows + MT - 1) / MT;
+    a.kchunks = a.N / 256;
+    const size_t nb = (size_t)a.n_ot * a.n_mt * a.kchunks * a.L;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mac_kernel<MT, OT>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
+                      hipStream_t s) {
+    const size_t n = G * 2 * (size_t)c->L * c->N;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (cn) {
+        case 2: hipLaunchKernelGGL(wht_kernel<2>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 4: hipLaunchKernelGGL(wht_kernel<4>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 8: hipLaunchKernelGGL(wht_kernel<8>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 16: hipLaunchKernelGGL(wht_kernel<16>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 32: hipLaunchKernelGGL(wht_kernel<32>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 64: hipLaunchKernelGGL(wht_kernel<64>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Tile choice of the MAC: rows x outputs per thread.
+struct MacTile {
+    int mt, ot;
+};
+
+static MacTile default_tile(const hyena_conv_desc *d) {
+    const uint32_t rows = 2 * d->batch * d->tiles;
+    if (d->depthwise) {
+        // outputs of one tile must share the input group
+        int ot = 1;
+        while (ot < 8 && d->ci % (2 * ot) == 0 && d->Co % (2 * ot) == 0) ot *= 2;
+        if (ot < (int)d->c_n) ot = (int)d->c_n;
+        return {rows >= 4 ? 4 : 2, ot};
+    }
+    if (rows >= 8) return {8, 8};
+    if (rows >= 4) return {4, 8};
+    return {2, 16};
+}
+
+static hipError_t dispatch_mac(const MacArgs &a, MacTile t, hipStream_t s) {
+#define HY_CASE(M, O) \
+    if (t.mt == M && t.ot == O) return launch_mac<M, O>(a, s);
+    HY_CASE(2, 1) HY_CASE(2, 2) HY_CASE(2, 4) HY_CASE(2, 8) HY_CASE(2, 16)
+    HY_CASE(4, 1) HY_CASE(4, 2) HY_CASE(4, 4) HY_CASE(4, 8) HY_CASE(4, 16)
+    HY_CASE(8, 1) HY_CASE(8, 2) HY_CASE(8, 4) HY_CASE(8, 8)
+    HY_CASE(16, 4) HY_CASE(16, 8)
+#undef HY_CASE
+    return hipErrorInvalidValue;
+}
+
+int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
+                uint32_t *out, int mt, int ot, bool per_channel, hipStream_t s) {
+    if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
+    if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
+    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
+    MacTile t = default_tile(d);
+    if (mt > 0) t.mt = mt;
+    if (ot > 0) t.ot = ot;
+    const uint32_t cn = d->c_n ? d->c_n : 1;
+    if (d->depthwise && (d->ci % (uint32_t)t.ot != 0 && t.ot != 1))
+        return set_error(HYENA_EINVAL, "hyena_conv: depthwise output tile must divide ci");
+    MacArgs a{};
+    a.ct = ct;
+    a.w = w;
+    a.out = out;
+    a.N = c->N;
+    a.L = c->L;
+    a.logN = c->logN;
+    a.Co = d->Co;
+    a.n_groups = d->n_groups;
+    a.w_groups = d->w_groups;
+    a.rows = 2 * (d->batch ? d->batch : 1) * d->tiles;
+    a.ci = d->ci;
+    a.c_n = cn;
+    a.depthwise = d->depthwise;
+    a.lt = c->lt;
+    const bool fuse_in_mac = cn > 1 && (uint32_t)t.ot >= cn && (uint32_t)t.ot % cn == 0;
+    a.fuse = (per_channel && fuse_in_mac) ? 1 : 0;
+    hipError_t e = dispatch_mac(a, t, s);
+    if (e == hipErrorInvalidValue) return set_error(HYENA_EINVAL, "hyena_conv: unsupported MAC tile");
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
+    if (cn > 1 && per_channel && !fuse_in_mac) {
+        const size_t G = (size_t)a.rows / 2 * d->Co / cn;
+        e = launch_wht(c, cn, out, out, G, s);
+        if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
+    }
+    return HYENA_OK;
+}
+
+extern "C" int hyena_conv(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
+                          const uint32_t *d_wntt, uint32_t *d_out_ntt, hyena_stream_t s) {
+    if (!d) return set_error(HYENA_EINVAL, "hyena_conv: NULL descriptor");
+    // without HYENA_FUSE_WHT the output holds the Walsh components
+    const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
+    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, 0, 0, per_channel, (hipStream_t)s);
+}
+
+extern "C" int hyena_wht_pack(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
+                              hyena_stream_t s) {
+    if (!c || (G && (!in || !out))) return set_error(HYENA_EINVAL, "hyena_wht_pack: NULL argument");
+    if (cn == 0 || (cn & (cn - 1)) || cn > 64) return set_error(HYENA_EINVAL, "hyena_wht_pack: c_n must be 1..64, a power of two");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_wht_pack: context was created host-only");
+    if (G == 0) return HYENA_OK;
+    if (cn == 1) {
+        if (in != out) HIP_TRY(hipMemcpyAsync(out, in, G * 2 * (size_t)c->L * c->N * 4, hipMemcpyDeviceToDevice, (hipStream_t)s));
+        return HYENA_OK;
+    }
+    hipError_t e = launch_wht(c, cn, in, out, G, (hipStream_t)s);
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_wht_pack: ") + hipGetErrorString(e));
+    return HYENA_OK;
+}
+
+extern "C" int hyena_encode_weights(const hyena_ctx *c, const hyena_conv_desc *d, const int8_t *d_w,
+                                    uint32_t *d_wntt, hyena_stream_t s) {
+    if (!c || !d || !d_w || !d_wntt) return set_error(HYENA_EINVAL, "hyena_encode_weights: NULL argument");
+    if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_encode_weights: descriptor not planned");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_encode_weights: context was created host-only");
+    const hipStream_t st = (hipStream_t)s;
+    const size_t polys = (size_t)d->Co * d->w_groups;
+    const size_t words = polys * c->L * c->N;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<size_t>((words + 255) / 256, 65536)), dim3(256), 0,
+                       st, d_wntt, words);
+    EncArgs a{};
+    a.w = d_w;
+    a.out = d_wntt;
+    a.N = c->N;
+    a.L = c->L;
+    a.Co = d->Co;
+    a.Ci = d->Ci;
+    a.k = d->k;
+    a.ci = d->ci;
+    a.Bt = d->Bt;
+    a.Wp = d->Wp;
+    a.O = d->O;
+    a.n_groups = d->n_groups;
+    a.w_groups = d->w_groups;
+    a.c_n = d->c_n ? d->c_n : 1;
+    a.depthwise = d->depthwise;
+    a.lt = c->lt;
+    for (uint32_t i = 0; i < c->L; i++) a.cninv[i] = h_powmod(a.c_n, c->q[i] - 2, c->q[i]);
+    const size_t taps = (size_t)d->Co * (d->depthwise ? a.c_n : d->Ci) * d->k * d->k;
+    hipLaunchKernelGGL(encode_scatter_kernel, dim3((unsigned)((taps + 255) / 256)), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_encode_weights: ") + hipGetErrorString(e));
+    return launch_ntt(c, d_wntt, polys, false, st);
+}

@@ -1,0 +1,69 @@
+// Internal declarations of the gfx950 Hyena library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hyena.h"
+
+#define HYENA_MAX_LIMBS 16
+
+// Per-limb constants, passed to kernels by value.
+struct LimbConst {
+    uint32_t q;        // prime modulus, 2^29 < q < 2^31
+    uint32_t r32;      // 2^32 mod q
+    uint32_t mu32;     // floor(2^32 / q)
+    uint32_t qinv_neg; // -q^{-1} mod 2^32 (Montgomery)
+    uint32_t r32s;     // Shoup companion of r32: floor(r32 * 2^32 / q)
+    uint32_t ninv;     // N^{-1} mod q
+    uint32_t ninvs;    // Shoup companion of ninv
+    uint32_t fold;     // products that fit between two folds of a lazy accumulator
+    uint32_t w1n;      // last inverse-NTT twiddle psi^-brv(1) times N^{-1}
+    uint32_t w1ns;     // its Shoup companion
+};
+
+struct LimbTable {
+    LimbConst c[HYENA_MAX_LIMBS];
+};
+
+struct hyena_ctx {
+    uint32_t N = 0, L = 0, logN = 0, log2_t = 0, flags = 0;
+    int device = 0;
+    std::vector<uint32_t> q, psi;
+    LimbTable lt{};
+    uint32_t fold_min = 1;   // minimum of lt.c[i].fold
+    // host twiddles (for the host-side NTT used by test-setup encryption)
+    std::vector<uint32_t> h_fw, h_fws, h_iw, h_iws;  // [L][N]
+    // device twiddles: forward psi powers in bit-reversed order with Shoup
+    // companions, interleaved as pairs; inverse likewise.  [L][N][2]
+    uint32_t *d_fw = nullptr;
+    uint32_t *d_iw = nullptr;
+};
+
+// error reporting
+int set_error(int code, const std::string &msg);
+#define HIP_TRY(expr)                                                          \
+    do {                                                                       \
+        hipError_t _e = (expr);                                                \
+        if (_e != hipSuccess)                                                  \
+            return set_error(HYENA_EHIP, std::string(#expr) + ": " +          \
+                                             hipGetErrorString(_e));           \
+    } while (0)
+
+// modular helpers (host)
+static inline uint32_t h_mulmod(uint32_t a, uint32_t b, uint32_t q) {
+    return (uint32_t)((uint64_t)a * b % q);
+}
+uint32_t h_powmod(uint32_t b, uint64_t e, uint32_t q);
+static inline uint32_t shoup_companion(uint32_t w, uint32_t q) {
+    return (uint32_t)(((uint64_t)w << 32) / q);
+}
+uint32_t bit_reverse(uint32_t x, uint32_t logn);
+
+// host NTT (same transform as the device one), used by test-setup crypto
+void host_ntt(const hyena_ctx *ctx, uint32_t limb, uint32_t *a);
+void host_intt(const hyena_ctx *ctx, uint32_t limb, uint32_t *a);
+
+// launchers shared by translation units
+int launch_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, bool inverse, hipStream_t s);

@@ -1,0 +1,251 @@
+"""GPU parity: every HIP kernel against the oracle, bit for bit.
+
+Inputs come from the seeded generators and the oracle's encryption; expected
+values come from the oracle only. Outputs are compared on every coefficient of
+every limb and ciphertext part (ring elements are exact integers, so the bar
+is bit equality)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_12519_amd as hy
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def from_dev(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+def rand_res(rng, shape, primes):
+    """uint32 [..., L, N] uniform residues per limb."""
+    out = np.empty(shape, dtype=np.uint32)
+    for i, q in enumerate(primes):
+        out[..., i, :] = rng.integers(0, q, size=shape[:-2] + (shape[-1],))
+    return out
+
+
+_CTX = {}
+
+
+def ctx_for(N, L, bits):
+    key = (N, L, bits)
+    if key not in _CTX:
+        flags = (hy.HYENA_PRIMES_30BIT if bits == 30 else 0) | (hy.HYENA_ALLOW_INSECURE if N < 4096 else 0)
+        _CTX[key] = hy.hyena_create(N, L, flags=flags)
+    return _CTX[key]
+
+
+# ---------------------------------------------------------------- NTT
+
+@pytest.mark.parametrize("N,L,bits", [(1024, 2, 31), (2048, 2, 31), (4096, 2, 30), (8192, 3, 31), (16384, 4, 31)])
+def test_ntt_matches_oracle(dev, N, L, bits):
+    say(f"ntt N={N} L={L}")
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N)
+    a = rand_res(rng, (2, L, N), ctx.primes)
+    for i, q in enumerate(ctx.primes):           # edge residues
+        a[0, i, :4] = [0, q - 1, 1, q - 2]
+    d = to_dev(a)
+    hy.hyena_ntt(ctx, d)
+    got = from_dev(d)
+    for p in range(2):
+        for i, q in enumerate(ctx.primes):
+            assert np.array_equal(got[p, i], orc.ntt(a[p, i], q, ctx.psi[i])), (p, i)
+    hy.hyena_intt(ctx, d)
+    assert np.array_equal(from_dev(d), a)
+
+
+@pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (16384, 4, 31)])
+def test_intt_matches_oracle(dev, N, L, bits):
+    say(f"intt N={N}")
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N + 1)
+    A = rand_res(rng, (1, L, N), ctx.primes)
+    d = to_dev(A)
+    hy.hyena_intt(ctx, d)
+    got = from_dev(d)
+    for i, q in enumerate(ctx.primes):
+        assert np.array_equal(got[0, i], orc.intt(A[0, i], q, ctx.psi[i]))
+
+
+def test_ntt_many_polys_roundtrip_and_empty(dev):
+    import torch
+    ctx = ctx_for(8192, 3, 31)
+    rng = np.random.default_rng(3)
+    a = rand_res(rng, (97, 3, 8192), ctx.primes)
+    d = to_dev(a)
+    hy.hyena_ntt(ctx, d)
+    mid = from_dev(d)
+    k = 57  # spot-check one polynomial in the middle of the launch
+    for i, q in enumerate(ctx.primes):
+        assert np.array_equal(mid[k, i], orc.ntt(a[k, i], q, ctx.psi[i]))
+    hy.hyena_intt(ctx, d)
+    assert np.array_equal(from_dev(d), a)
+    empty = torch.empty(0, dtype=torch.int32, device="cuda")
+    hy.hyena_ntt(ctx, empty)
+
+
+# ---------------------------------------------------------------- weights
+
+@pytest.mark.parametrize("c_n,dw", [(1, False), (2, False), (4, False), (1, True), (2, True)])
+def test_encode_weights_matches_oracle(dev, c_n, dw):
+    import torch
+    say(f"encode c_n={c_n} dw={dw}")
+    N, L = 4096, 2
+    ctx = ctx_for(N, L, 30)
+    lay = wl.Layer("t", 16, 16, 16, 16, 3, depthwise=dw)
+    d = hy.hyena_conv_plan(ctx, 16, 16, 16, 16, 3, depthwise=dw, c_n=c_n)
+    pl = orc.plan(N, 16, 16, 16, 16, 3, dw)
+    w = wl.weights(21, lay)
+    dw_t = torch.from_numpy(w).cuda()
+    out = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, dw_t, out)
+    got = from_dev(out).reshape(16, d.w_groups, L, N)
+    for o in range(16):
+        G, j = divmod(o, c_n)
+        gs = [o // pl.ci] if dw else range(pl.n_groups)
+        for slot, g in enumerate(gs):
+            Kw = orc.walsh_kernel_residues(pl, w, c_n, ctx.primes, G, j, g)
+            for i, q in enumerate(ctx.primes):
+                want = orc.ntt(Kw[i], q, ctx.psi[i])
+                assert np.array_equal(got[o, 0 if dw else slot, i], want), (o, g, i)
+
+
+# ---------------------------------------------------------------- Walsh-Hadamard
+
+@pytest.mark.parametrize("c_n", [2, 4, 8, 64])
+def test_wht_pack_matches_oracle(dev, c_n):
+    N, L = 4096, 2
+    ctx = ctx_for(N, L, 30)
+    G = 3
+    rng = np.random.default_rng(c_n)
+    x = rand_res(rng, (G, c_n, 2, L, N), ctx.primes)
+    x[0, :, 0, 0, 0] = ctx.primes[0] - 1
+    d = to_dev(x)
+    hy.hyena_wht_pack(ctx, c_n, d, d, G)          # in place
+    got = from_dev(d)
+    H = orc.walsh_matrix(c_n)
+    for i, q in enumerate(ctx.primes):
+        want = np.einsum("bj,Gjpn->Gbpn", H, x[:, :, :, i, :].astype(np.int64)) % q
+        assert np.array_equal(got[:, :, :, i, :], want.astype(np.uint32))
+
+
+# ---------------------------------------------------------------- end to end
+
+def run_layer(ctx, lay, c_n, seed, batch=1, fuse=True, ci_req=0, check_decrypt=True):
+    """Oracle-encrypted inputs -> GPU ntt, conv, (wht), intt -> compare with
+    oracle products on every coefficient, then decrypt and compare with the
+    plaintext convolution."""
+    import torch
+    N, L = ctx.N, ctx.L
+    flags = hy.HYENA_FUSE_WHT if fuse else 0
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, depthwise=lay.depthwise, c_n=c_n,
+                           flags=flags, batch=batch, ci_req=ci_req)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, lay.depthwise, ci_req or None)
+    w = wl.weights(seed, lay)
+    s = orc.keygen(N, wl.crypto_seed(seed))
+    xs, cts = [], []
+    for b in range(batch):
+        x = wl.activations(seed + 100 * b, lay.Ci, lay.H, lay.W)
+        ct = orc.encrypt(ctx.primes, 20, s, orc.pack_input(pl, x).reshape(-1, N), wl.crypto_seed(seed) + b)
+        xs.append(x)
+        cts.append(ct.reshape(pl.tiles, pl.n_groups, 2, L, N))
+    ct_all = np.stack(cts)
+    d_ct = to_dev(ct_all)
+    d_w = torch.from_numpy(w).cuda()
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    d_out = torch.empty(batch * pl.tiles * lay.Co * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, d_w, d_wn)
+    hy.hyena_ntt(ctx, d_ct)
+    hy.hyena_conv(ctx, d, d_ct, d_wn, d_out)
+    if not fuse and c_n > 1:
+        hy.hyena_wht_pack(ctx, c_n, d_out, d_out, batch * pl.tiles * lay.Co // c_n)
+    hy.hyena_intt(ctx, d_out)
+    got = from_dev(d_out).reshape(batch, pl.tiles, lay.Co, 2, L, N)
+    for b in range(batch):
+        want = orc.conv_products(pl, cts[b], w, ctx.primes).reshape(pl.tiles, lay.Co, 2, L, N)
+        bad = np.argwhere(got[b] != want)
+        assert bad.size == 0, f"image {b}: {len(bad)} mismatches, first at {bad[:3].tolist()}"
+        if check_decrypt:
+            dec = hy.hyena_decrypt(ctx, s, got[b].reshape(-1, 2, L, N)).reshape(pl.tiles, lay.Co, N)
+            y = hy.hyena_unpack_output(d, N, dec)
+            assert np.array_equal(y, orc.direct_conv(xs[b], w, lay.k, lay.depthwise))
+
+
+CONFIGS = [
+    # id, (N, L, bits), layer, c_n
+    ("single16", (4096, 2, 30), wl.WORKLOADS[1].layers[0], 1),
+    ("resnet32", (8192, 3, 31), wl.WORKLOADS[2].layers[0], 1),
+    ("resnet56_cn4", (16384, 4, 31), wl.WORKLOADS[3].layers[0], 4),
+    ("resnet14_cn64", (16384, 4, 31), wl.WORKLOADS[3].layers[1], 64),
+]
+
+
+@pytest.mark.parametrize("name,params,lay,c_n", CONFIGS, ids=[c[0] for c in CONFIGS])
+def test_workload_layers_end_to_end(dev, name, params, lay, c_n):
+    say(f"e2e {name}")
+    run_layer(ctx_for(*params), lay, c_n, seed=1000 + len(name))
+
+
+VARIANTS = [
+    ("tiles_halo", (4096, 2, 30), wl.Layer("t", 70, 70, 3, 8, 3), 1, 1, True, 0),
+    ("short_group", (4096, 2, 30), wl.Layer("t", 12, 12, 37, 8, 3), 2, 1, True, 0),
+    ("depthwise", (8192, 3, 31), wl.Layer("t", 28, 28, 32, 32, 3, depthwise=True), 1, 1, True, 0),
+    ("depthwise_cn2", (8192, 3, 31), wl.Layer("t", 14, 14, 64, 64, 3, depthwise=True), 2, 1, True, 0),
+    ("pointwise", (8192, 3, 31), wl.Layer("t", 14, 14, 64, 40, 1), 8, 1, True, 0),
+    ("unfused_cn4", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 16, 3), 4, 1, False, 0),
+    ("batch3_cn2", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 16, 3), 2, 3, True, 0),
+    ("ci_lowered", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 8, 3), 1, 1, True, 5),
+    ("cn32_unfusable", (8192, 3, 31), wl.Layer("t", 14, 14, 32, 32, 3), 32, 1, True, 0),
+]
+
+
+@pytest.mark.parametrize("name,params,lay,c_n,batch,fuse,ci_req", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_layer_variants_end_to_end(dev, name, params, lay, c_n, batch, fuse, ci_req):
+    say(f"variant {name}")
+    run_layer(ctx_for(*params), lay, c_n, seed=2000 + len(name), batch=batch, fuse=fuse, ci_req=ci_req)
+
+
+def test_vgg_conv1_2_full_size_sampled(dev):
+    """VGG-16 conv1_2 (224x224, 64 -> 64, 7 row tiles) at N = 8192, two images,
+    in the default launch configuration; sampled output ciphertexts are checked
+    against the oracle on every coefficient."""
+    import torch
+    say("vgg conv1_2 full size")
+    ctx = ctx_for(8192, 3, 31)
+    lay = wl.vgg16_layers()[1]
+    N, L, batch = 8192, 3, 2
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, 3, batch=batch, flags=hy.HYENA_FUSE_WHT)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, 3)
+    rng = np.random.default_rng(12)
+    ct = rand_res(rng, (batch, pl.tiles, pl.n_groups, 2, L, N), ctx.primes)
+    w = wl.weights(4001, lay)
+    d_ct = to_dev(ct)
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    d_out = torch.empty(batch * pl.tiles * lay.Co * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, torch.from_numpy(w).cuda(), d_wn)
+    hy.hyena_ntt(ctx, d_ct)
+    hy.hyena_conv(ctx, d, d_ct, d_wn, d_out)
+    hy.hyena_intt(ctx, d_out)
+    got = from_dev(d_out).reshape(batch, pl.tiles, lay.Co, 2, L, N)
+    sel = [(0, 0), (3, 17), (6, 63)]
+    for b in range(batch):
+        want = orc.conv_products(pl, ct[b], w, ctx.primes, outputs=sel)
+        for u, (tau, o) in enumerate(sel):
+            assert np.array_equal(got[b, tau, o], want[u]), (b, tau, o)

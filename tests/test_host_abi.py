@@ -1,0 +1,153 @@
+"""CPU tests of the C ABI: exported symbols and the host-side calls
+(parameters, key generation, encryption, decryption, planning, packing)
+against the oracle. No GPU is touched: contexts are created host-only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_12519_amd as hy
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOST = hy.HYENA_HOST_ONLY
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*(hyena_\w+)\s*\(", src, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hy.lib()
+    names = _declared_symbols()
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_no_internal_symbols_exported():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", hy.LIB_PATH], capture_output=True, text=True).stdout
+    syms = [l.split()[-1] for l in out.splitlines() if " T " in l]
+    assert syms and all(s.startswith("hyena_") for s in syms), syms
+
+
+@pytest.mark.parametrize("N,L,bits,flags", [(4096, 2, 30, hy.HYENA_PRIMES_30BIT), (8192, 3, 31, 0),
+                                            (16384, 4, 31, 0)])
+def test_params_match_oracle(N, L, bits, flags):
+    ctx = hy.hyena_create(N, L, flags=flags | HOST)
+    assert ctx.primes == orc.ntt_primes(N, L, bits)
+    assert ctx.psi == [orc.find_psi(q, N) for q in ctx.primes]
+
+
+def test_security_ceiling_enforced():
+    with pytest.raises(hy.HyenaError) as e:
+        hy.hyena_create(4096, 4, flags=HOST)       # 124 bits > 109
+    assert e.value.code == hy.HYENA_EUNSUPPORTED
+    hy.hyena_create(4096, 4, flags=HOST | hy.HYENA_ALLOW_INSECURE)
+    hy.hyena_create(8192, 7, flags=HOST)           # 217 bits <= 218
+
+
+def test_bad_primes_rejected():
+    with pytest.raises(hy.HyenaError):
+        hy.hyena_create(4096, 1, primes=[2147352577 + 2], flags=HOST)  # not prime
+    with pytest.raises(hy.HyenaError):
+        hy.hyena_create(8192, 1, primes=[1073668097], flags=HOST)      # 1 mod 8192 only
+
+
+@pytest.mark.parametrize("N,L,flags", [(4096, 2, hy.HYENA_PRIMES_30BIT), (8192, 3, 0)])
+def test_keygen_encrypt_bit_exact_with_oracle(N, L, flags):
+    ctx = hy.hyena_create(N, L, flags=flags | HOST)
+    sk = hy.hyena_keygen(ctx, 4242)
+    assert np.array_equal(sk, orc.keygen(N, 4242))
+    rng = np.random.default_rng(0)
+    m = rng.integers(-(1 << 19) + 1, (1 << 19) + 1, size=(3, N))
+    ct = hy.hyena_encrypt(ctx, sk, m, 777)
+    assert np.array_equal(ct, orc.encrypt(ctx.primes, 20, orc.keygen(N, 4242), m, 777))
+
+
+def test_decrypt_matches_oracle_on_noisy_ciphertexts():
+    N, L = 4096, 3
+    ctx = hy.hyena_create(N, L, flags=HOST)
+    s = orc.keygen(N, 5)
+    pl = orc.plan(N, 16, 16, 16, 4, 3)
+    x = wl.activations(1, 16, 16, 16)
+    w = wl.weights(2, wl.Layer("t", 16, 16, 16, 4, 3))
+    ct = orc.encrypt(ctx.primes, 20, s, orc.pack_input(pl, x).reshape(-1, N), 3)
+    Y = orc.conv_products(pl, ct.reshape(pl.tiles, pl.n_groups, 2, L, N), w, ctx.primes)
+    assert np.array_equal(hy.hyena_decrypt(ctx, s, Y), orc.decrypt(ctx.primes, 20, s, Y))
+
+
+def test_decrypt_rejects_noncanonical_residue():
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    ct = np.zeros((1, 2, 2, 4096), dtype=np.uint32)
+    ct[0, 0, 1, 7] = ctx.primes[1]
+    with pytest.raises(hy.HyenaError):
+        hy.hyena_decrypt(ctx, np.zeros(4096, np.int8), ct)
+
+
+def _all_layers():
+    out = []
+    for w in wl.WORKLOADS.values():
+        for l in w.layers:
+            out.append((w.N, w.L, w.prime_bits, l))
+    return out
+
+
+@pytest.mark.parametrize("N,L,bits,layer", _all_layers(), ids=lambda v: getattr(v, "name", str(v)))
+def test_plan_matches_oracle(N, L, bits, layer):
+    ctx = hy.hyena_create(N, L, flags=HOST | (hy.HYENA_PRIMES_30BIT if bits == 30 else 0))
+    d = hy.hyena_conv_plan(ctx, layer.H, layer.W, layer.Ci, layer.Co, layer.k, stride=layer.stride,
+                           depthwise=layer.depthwise)
+    p = orc.plan(N, layer.H, layer.W, layer.Ci, layer.Co, layer.k, layer.depthwise)
+    assert (d.pad, d.Wp, d.R, d.tiles, d.ci, d.Bt, d.O, d.n_groups) == (
+        p.pad, p.Wp, p.R, p.tiles, p.ci, p.Bt, p.O, p.n_groups)
+    assert d.n_in == p.tiles * p.n_groups and d.n_out == p.tiles * p.Co
+
+
+@pytest.mark.parametrize("shape", [(4096, 16, 16, 16, 16, 3), (1024, 40, 40, 3, 2, 3), (1024, 9, 9, 10, 3, 1)])
+def test_pack_unpack_match_oracle(shape):
+    N, H, W, Ci, Co, k = shape
+    ctx = hy.hyena_create(N, 2, flags=HOST | hy.HYENA_ALLOW_INSECURE)
+    d = hy.hyena_conv_plan(ctx, H, W, Ci, Co, k)
+    p = orc.plan(N, H, W, Ci, Co, k)
+    x = wl.activations(9, Ci, H, W)
+    msg = hy.hyena_pack_input(d, N, x)
+    assert np.array_equal(msg, orc.pack_input(p, x))
+    rng = np.random.default_rng(1)
+    out = rng.integers(-1000, 1000, size=(p.tiles, Co, N)).astype(np.int32)
+    assert np.array_equal(hy.hyena_unpack_output(d, N, out), orc.unpack_output(p, out))
+
+
+def test_plan_noise_and_shape_errors():
+    ctx1 = hy.hyena_create(4096, 1, flags=HOST)
+    with pytest.raises(hy.HyenaError) as e:
+        hy.hyena_conv_plan(ctx1, 16, 16, 16, 16, 3)
+    assert e.value.code == hy.HYENA_ENOISE
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    for kw in (dict(c_n=3), dict(c_n=32), dict(k=5)):
+        args = dict(H=16, W=16, Ci=16, Co=16, k=3)
+        args.update(kw)
+        with pytest.raises(hy.HyenaError) as e:
+            hy.hyena_conv_plan(ctx, args.pop("H"), args.pop("W"), args.pop("Ci"), args.pop("Co"),
+                               args.pop("k"), **args)
+        assert e.value.code == hy.HYENA_EINVAL
+    # |y| bound: 3x3 over 1024 channels of 4-bit values exceeds t/2 = 2^19
+    ctxb = hy.hyena_create(16384, 4, flags=HOST)
+    with pytest.raises(hy.HyenaError) as e:
+        hy.hyena_conv_plan(ctxb, 8, 8, 1024, 8, 3)
+    assert e.value.code == hy.HYENA_ENOISE
+
+
+def test_device_calls_refused_on_host_only_context():
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    rc = hy.lib().hyena_ntt(ctx.handle, ctypes.c_void_p(0), 0, ctypes.c_void_p(0))
+    assert rc == hy.HYENA_EINVAL
