@@ -1,0 +1,317 @@
+"""Throughput of the Hyena HE-convolution hot path on one MI355X.
+
+Workload: the 13 convolution layers of VGG-16 at 224x224 (widths 64, 128,
+256, 512, 512; 3x3, pad 1) for a batch of 8 images, BFV ring N = 8192 with
+three RNS primes below 2^31, plaintext modulus 2^20. One step is the whole
+server-side path for every (image, layer): forward NTT of the input
+ciphertexts, the multiply-accumulate over input ciphertexts with lazy
+reduction, the Walsh-Hadamard recombination (c_n = 1 here: every VGG layer at
+N = 8192 packs at most 32 channels, and the paper's choice is c_n <= 2; the
+butterflies are exercised by the tests) and the inverse NTT of the output
+ciphertexts. Weights are encoded once, before timing (the paper's offline
+weight preparation). Inputs are uniform residues drawn on the GPU from a
+seeded generator (distributed as fresh ciphertexts), resident in HBM before
+the timed region.
+
+Two schedules of the same arithmetic are timed:
+  plain   - per image and layer: ntt, conv, intt through the C ABI;
+  batched - per layer, all 8 images in one launch of each kernel, so each
+            encoded-weight word is read once per batch instead of per image.
+Before timing, one step is checked against the oracle on sampled output
+ciphertexts (every coefficient of both parts and all limbs).
+
+Prints one JSON line (rank 0, N=1 GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# VALU issue rate of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--images", type=int, default=8)
+    ap.add_argument("--layers", type=int, default=13, help="first n VGG layers (13 = all)")
+    ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+class Layer:
+    pass
+
+
+def lazy_fold_interval(primes):
+    """Products the MAC adds between two folds of its 64-bit accumulator
+    (one mad per fold): after a fold the accumulator is below 2^32 (r + 1),
+    r = 2^32 mod q, and each product is at most (q - 1)^2."""
+    f = 15
+    for q in primes:
+        r = (1 << 32) % q
+        f = min(f, ((1 << 64) - 1 - ((r + 1) << 32)) // ((q - 1) ** 2))
+    return max(1, f)
+
+
+def setup(args, hy, wl, torch):
+    N, L = 8192, 3
+    ctx = hy.hyena_create(N, L)
+    layers = []
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    for li, lay in enumerate(wl.vgg16_layers()[: args.layers]):
+        o = Layer()
+        o.lay = lay
+        o.desc_b = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=1,
+                                      flags=hy.HYENA_FUSE_WHT, batch=args.images)
+        o.desc_1 = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=1,
+                                      flags=hy.HYENA_FUSE_WHT, batch=1)
+        d = o.desc_b
+        seed = wl.layer_seed(4, li)
+        o.w = wl.weights(seed, lay)
+        o.d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device=dev)
+        hy.hyena_encode_weights(ctx, d, torch.from_numpy(o.w).to(dev), o.d_wn)
+        in_words = d.n_in * 2 * L * N
+        out_words = d.n_out * 2 * L * N
+        o.ct0 = torch.empty((args.images, in_words), dtype=torch.int32, device=dev)
+        v = o.ct0.view(args.images, d.n_in, 2, L, N)
+        g.manual_seed(seed)
+        for i, q in enumerate(ctx.primes):
+            v[:, :, :, i, :] = torch.randint(0, q, v[:, :, :, i, :].shape, generator=g, device=dev,
+                                             dtype=torch.int64).to(torch.int32)
+        o.ct = o.ct0.clone()
+        o.out = torch.empty((args.images, out_words), dtype=torch.int32, device=dev)
+        o.macs = d.n_groups * lay.Co * d.tiles * 2 * L * N   # coeff-MACs per image
+        o.in_words, o.out_words = in_words, out_words
+        layers.append(o)
+    torch.cuda.synchronize()
+    return ctx, layers
+
+
+def step_batched(ctx, layers, hy, ev=None):
+    for o in layers:
+        if ev is not None:
+            ev.rec("ntt")
+        hy.hyena_ntt(ctx, o.ct)
+        if ev is not None:
+            ev.rec("ntt_end")
+            ev.rec("mac")
+        hy.hyena_conv(ctx, o.desc_b, o.ct, o.d_wn, o.out)
+        if ev is not None:
+            ev.rec("mac_end")
+            ev.rec("intt")
+        hy.hyena_intt(ctx, o.out)
+        if ev is not None:
+            ev.rec("intt_end")
+
+
+def step_plain(ctx, layers, hy, images):
+    for o in layers:
+        for b in range(images):
+            hy.hyena_ntt(ctx, o.ct[b])
+            hy.hyena_conv(ctx, o.desc_1, o.ct[b], o.d_wn, o.out[b])
+            hy.hyena_intt(ctx, o.out[b])
+
+
+class Events:
+    """HIP events on torch's current stream, the stream every call runs on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.marks = []
+
+    def rec(self, name):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.marks.append((name, e))
+
+    def totals(self):
+        self.torch.cuda.synchronize()
+        out, open_ = {}, {}
+        for name, e in self.marks:
+            if name.endswith("_end"):
+                k = name[:-4]
+                out.setdefault(k, []).append(open_.pop(k).elapsed_time(e))
+            else:
+                open_[name] = e
+        return out
+
+
+def check(ctx, layers, hy, orc, torch, images):
+    """One batched step from pristine inputs; sampled outputs vs the oracle."""
+    N, L = ctx.N, ctx.L
+    for o in layers:
+        o.ct.copy_(o.ct0)
+    step_batched(ctx, layers, hy)
+    torch.cuda.synchronize()
+    checked = 0
+    for li, o in enumerate(layers):
+        d = o.desc_b
+        pl = orc.plan(N, o.lay.H, o.lay.W, o.lay.Ci, o.lay.Co, o.lay.k)
+        b = li % images
+        ct = o.ct0[b].cpu().numpy().view(np.uint32).reshape(pl.tiles, pl.n_groups, 2, L, N)
+        sel = [(0, 0), (pl.tiles - 1, o.lay.Co - 1)]
+        want = orc.conv_products(pl, ct, o.w, ctx.primes, outputs=sel)
+        got = o.out[b].cpu().numpy().view(np.uint32).reshape(pl.tiles, o.lay.Co, 2, L, N)
+        for u, (tau, oc) in enumerate(sel):
+            if not np.array_equal(got[tau, oc], want[u]):
+                raise SystemExit(f"parity failure: layer {o.lay.name} image {b} output {(tau, oc)}")
+            checked += 1
+    return checked
+
+
+def cpu_baseline(ctx, layers, orc, seconds):
+    """The oracle (sparse-tap schoolbook, OpenMP) on a bounded sample: whole
+    output ciphertexts of successive layers, until about `seconds` of CPU time."""
+    import ctypes  # noqa: F401
+    N, L = ctx.N, ctx.L
+    rng = np.random.default_rng(0)
+    done_macs, spent, outs = 0, 0.0, 0
+    names = []
+    li = 0
+    while spent < seconds and li < 64:
+        o = layers[li % len(layers)]
+        li += 1
+        pl = orc.plan(N, o.lay.H, o.lay.W, o.lay.Ci, o.lay.Co, o.lay.k)
+        ct = np.empty((pl.tiles, pl.n_groups, 2, L, N), dtype=np.uint32)
+        for i, q in enumerate(ctx.primes):
+            ct[:, :, :, i, :] = rng.integers(0, q, size=(pl.tiles, pl.n_groups, 2, N))
+        n_out = 8
+        sel = [(int(rng.integers(pl.tiles)), int(rng.integers(o.lay.Co))) for _ in range(n_out)]
+        t0 = time.perf_counter()
+        orc.conv_products(pl, ct, o.w, ctx.primes, outputs=sel)
+        spent += time.perf_counter() - t0
+        done_macs += n_out * pl.n_groups * 2 * L * N
+        outs += n_out
+        names.append(o.lay.name)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": done_macs / spent, "unit": "coeff-MAC/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{outs} output ciphertexts (all coefficients, 2 parts x {L} limbs) of VGG layers "
+                      f"{sorted(set(names))}, {spent:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2311_12519_amd as hy
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    hy.lib()
+    log("setup ...")
+    ctx, layers = setup(args, hy, wl, torch)
+    n_img = args.images
+    total_macs = sum(o.macs for o in layers) * n_img
+    n_layer_runs = len(layers) * n_img
+
+    checked = 0
+    if not args.no_check:
+        import oracle as orc
+        log("parity check on sampled outputs ...")
+        checked = check(ctx, layers, hy, orc, torch, n_img)
+        log(f"parity ok: {checked} output ciphertexts bit-exact")
+
+    res = {}
+    modes = ["plain", "batched"] if args.mode == "both" else [args.mode]
+    for mode in modes:
+        fn = (lambda: step_batched(ctx, layers, hy)) if mode == "batched" else \
+             (lambda: step_plain(ctx, layers, hy, n_img))
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = Events(torch) if mode == "batched" else None
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            if ev is not None:
+                step_batched(ctx, layers, hy, ev)
+            else:
+                fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[mode] = {"ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt,
+                     "layers_per_s": n_layer_runs / dt}
+        if ev is not None:
+            res[mode]["kernels_ms"] = {k: sum(v) / args.steps for k, v in ev.totals().items()}
+        log(f"{mode}: {dt * 1e3:.2f} ms/step, {total_macs / dt / 1e12:.3f} T coeff-MAC/s")
+
+    head = res.get("batched", res.get("plain"))
+    out = {
+        "metric": "HE-conv coeff-MACs/s + layers/s at N=8192, batched/tuned vs plain; bit-exact",
+        "value": head["coeff_macs_per_s"],
+        "unit": "coeff-MAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"VGG-16 {len(layers)} conv layers at 224x224, {n_img} images, "
+                               f"N=8192, 3 primes < 2^31, t=2^20, c_n=1",
+                   "images": n_img, "layers": len(layers), "N": 8192, "L": 3},
+        "layers_per_s": head["layers_per_s"],
+        "parity_checked_outputs": checked,
+        "schedules": res,
+    }
+    if "batched" in res and "plain" in res:
+        out["speedup_batched_vs_plain"] = res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"]
+    if "batched" in res and "kernels_ms" in res["batched"]:
+        km = res["batched"]["kernels_ms"]
+        mac_ms = km["mac"]
+        # algorithmic HBM bytes of the MAC launches: encoded weights once,
+        # input ciphertexts once, output ciphertexts once
+        w_bytes = sum(o.d_wn.numel() * 4 for o in layers)
+        io_bytes = sum((o.in_words + o.out_words) * 4 for o in layers) * n_img
+        mac_gbs = (w_bytes + io_bytes) / (mac_ms * 1e-3) / 1e9
+        fold = lazy_fold_interval(ctx.primes)
+        instr = total_macs * (1 + 1 / fold)
+        out["roofline"] = {"bound": "alu", "kernel": "mac_kernel",
+                           "achieved": instr / (mac_ms * 1e-3) / 1e12,
+                           "peak": VALU_PEAK_TOPS, "unit": "T VALU-op/s",
+                           "frac": instr / (mac_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
+                           "traffic": None,
+                           "hbm_algorithmic_GBs": mac_gbs,
+                           "hbm_frac": mac_gbs / HBM_PEAK_GBS}
+        ntt_bytes = sum(o.in_words * 4 * 2 for o in layers) * n_img
+        intt_bytes = sum(o.out_words * 4 * 2 for o in layers) * n_img
+        out["kernels"] = {
+            "ntt": {"ms": km["ntt"], "GBs": ntt_bytes / (km["ntt"] * 1e-3) / 1e9},
+            "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": total_macs / (mac_ms * 1e-3) / 1e12},
+            "intt": {"ms": km["intt"], "GBs": intt_bytes / (km["intt"] * 1e-3) / 1e9},
+        }
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(ctx, layers, orc, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -223,6 +223,26 @@ int hyena_conv(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                uint32_t *d_out_ntt, hyena_stream_t stream);
 
 /*
+ * Schedules of the multiply-accumulate. Every schedule computes the same
+ * result as hyena_conv (bit for bit); they differ in speed only, and are what
+ * the autotuner searches. hyena_conv_schedules reports how many exist;
+ * hyena_conv_schedule_info fills info[6] = {uses_lds, mt, ot, wr, wo, stages}:
+ * each thread accumulates mt rows (image, tile, ciphertext part) by ot
+ * outputs of one NTT slot; LDS schedules run 4 waves in a wr x wo grid with a
+ * `stages`-deep global->LDS copy pipeline. hyena_conv_default_schedule gives
+ * the schedule hyena_conv uses for a planned descriptor. hyena_conv_tiled is
+ * hyena_conv with an explicit schedule (EINVAL if it does not exist or does
+ * not fit the layer: depthwise layers need a register-only schedule whose ot
+ * divides ci).
+ */
+int hyena_conv_schedules(int *count);
+int hyena_conv_schedule_info(int sched, int *info);
+int hyena_conv_default_schedule(const hyena_conv_desc *desc);
+int hyena_conv_tiled(const hyena_ctx *ctx, const hyena_conv_desc *desc,
+                     const uint32_t *d_ct_ntt, const uint32_t *d_wntt,
+                     uint32_t *d_out_ntt, int sched, hyena_stream_t stream);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -68,6 +68,10 @@ _SIGS = {
     "hyena_intt": [_P, _P, _sz, _P],
     "hyena_conv": [_P, _P, _P, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
+    "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
+    "hyena_conv_schedules": [_P],
+    "hyena_conv_schedule_info": [ctypes.c_int, _P],
+    "hyena_conv_default_schedule": [_P],
 }
 
 
@@ -99,7 +103,10 @@ def _register_extra(L):
         "hyena_batch_capture": [_P, _P, _P, _P, _P],
         "hyena_batch_replay": [_P, _P],
         "hyena_batch_info": [_P, _P],
-        "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, ctypes.c_int, _P],
+        "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
+        "hyena_conv_schedules": [_P],
+        "hyena_conv_schedule_info": [ctypes.c_int, _P],
+        "hyena_conv_default_schedule": [_P],
         "hyena_mlp_forward": [_P, _P, _P, _u32, _P],
         "hyena_mlp_backward": [_P, _P, _P, _P, _u32, _P, _P],
         "hyena_mlp_adam": [_P, _P, _P, _P, _u32, ctypes.c_float, ctypes.c_float,
@@ -255,6 +262,28 @@ def hyena_conv(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_wntt, d_out_ntt, stream=Non
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:
     _check(lib().hyena_wht_pack(ctx.handle, c_n, _dev_ptr(d_in, "int32"), _dev_ptr(d_out, "int32"),
                                 G, _stream(stream)))
+
+
+def hyena_conv_tiled(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_wntt, d_out_ntt, sched: int, stream=None) -> None:
+    _check(lib().hyena_conv_tiled(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct_ntt, "int32"),
+                                  _dev_ptr(d_wntt, "int32"), _dev_ptr(d_out_ntt, "int32"), sched,
+                                  _stream(stream)))
+
+
+def hyena_conv_schedules() -> list:
+    """[(uses_lds, mt, ot, wr, wo, stages)] indexed by schedule id."""
+    n = ctypes.c_int()
+    _check(lib().hyena_conv_schedules(ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        info = (ctypes.c_int * 6)()
+        _check(lib().hyena_conv_schedule_info(i, info))
+        out.append(tuple(info))
+    return out
+
+
+def hyena_conv_default_schedule(desc: ConvDesc) -> int:
+    return lib().hyena_conv_default_schedule(ctypes.byref(desc))
 
 
 def wntt_words(ctx: Ctx, desc: ConvDesc) -> int:

@@ -62,12 +62,14 @@ struct MacArgs {
 // 256 threads along k. The block index is remapped so that all o- and
 // row-tiles of one k-chunk land on the same XCD (blocks are dealt to the 8
 // XCDs round robin) and share its L2 for the ciphertext and weight reads.
+// Row and output base addresses are block-uniform (scalar registers); each
+// lane adds its slot. The loads of input group g+1 are issued before the
+// multiply-adds of group g so that memory latency overlaps the arithmetic.
 template <int MT, int OT>
 __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
     const uint32_t nb = gridDim.x;
     const uint32_t xcd = blockIdx.x & 7u, local = blockIdx.x >> 3;
-    const uint32_t per = (nb + 7) >> 3;  // logical blocks per XCD (ceil)
-    // XCD x gets logical blocks [x*per, ...), limited by nb
+    const uint32_t per = (nb + 7) >> 3;        // logical blocks per XCD (ceil)
     const uint32_t full = nb - (per - 1) * 8;  // XCDs that get `per` blocks
     uint32_t logical;
     if (xcd < full) logical = xcd * per + local;
@@ -76,11 +78,10 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
     const uint32_t ot = (logical / a.n_mt) % a.n_ot;
     const uint32_t kc = logical / (a.n_mt * a.n_ot);
     const uint32_t limb = kc / a.kchunks;
-    const uint32_t k = (kc % a.kchunks) * 256 + threadIdx.x;
+    const uint32_t slot = limb * a.N + (kc % a.kchunks) * 256 + threadIdx.x;  // < L*N
     const LimbConst lc = a.lt.c[limb];
     const uint32_t r32 = lc.r32;
     const size_t LN = (size_t)a.L * a.N;
-    const size_t slot = (size_t)limb * a.N + k;
     const uint32_t row0 = mt * MT, o0 = ot * OT;
 
     uint32_t g0 = 0, g1 = a.n_groups;
@@ -88,45 +89,59 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
         g0 = o0 / a.ci;
         g1 = g0 + 1;
     }
-    const uint32_t *ctp[MT];
+    // uniform bases
+    const uint32_t *ctb[MT];
 #pragma unroll
     for (int r = 0; r < MT; r++) {
         const uint32_t row = min(row0 + r, a.rows - 1);
-        ctp[r] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN + slot;
+        ctb[r] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN;
     }
-    const uint32_t *wp[OT];
+    const uint32_t *wb[OT];
 #pragma unroll
     for (int j = 0; j < OT; j++) {
         const uint32_t o = min(o0 + j, a.Co - 1);
-        wp[j] = a.w + (size_t)o * a.w_groups * LN + slot;
+        wb[j] = a.w + (size_t)o * a.w_groups * LN;
     }
+    const size_t gstride_ct = 2 * LN;
+    const size_t gstride_w = a.depthwise ? 0 : LN;
+
     uint64_t acc[MT][OT];
 #pragma unroll
     for (int r = 0; r < MT; r++)
 #pragma unroll
         for (int j = 0; j < OT; j++) acc[r][j] = 0;
 
+    // two register sets, ping-pong: group g+1 loads while group g computes
+    uint32_t xa[MT], wa[OT], xb[MT], wb2[OT];
+    auto load = [&](uint32_t (&x)[MT], uint32_t (&w)[OT], uint32_t g) {
+        const size_t oc = (size_t)g * gstride_ct, ow = (size_t)g * gstride_w;
+#pragma unroll
+        for (int r = 0; r < MT; r++) x[r] = ctb[r][oc + slot];
+#pragma unroll
+        for (int j = 0; j < OT; j++) w[j] = wb[j][ow + slot];
+    };
     const uint32_t F = lc.fold;
-    uint32_t g = g0;
-    while (g < g1) {
-        const uint32_t gend = min(g1, g + F);
-        for (; g < gend; g++) {
-            uint32_t x[MT], w[OT];
-            const size_t gc = (size_t)g * 2 * LN;
-            const size_t gw = a.depthwise ? 0 : (size_t)g * LN;
-#pragma unroll
-            for (int r = 0; r < MT; r++) x[r] = ctp[r][gc];
-#pragma unroll
-            for (int j = 0; j < OT; j++) w[j] = wp[j][gw];
-#pragma unroll
-            for (int r = 0; r < MT; r++)
-#pragma unroll
-                for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
-        }
+    uint32_t since = 0;
+    auto compute = [&](const uint32_t (&x)[MT], const uint32_t (&w)[OT]) {
 #pragma unroll
         for (int r = 0; r < MT; r++)
 #pragma unroll
-            for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
+            for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
+        if (++since >= F) {
+            since = 0;
+#pragma unroll
+            for (int r = 0; r < MT; r++)
+#pragma unroll
+                for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
+        }
+    };
+    load(xa, wa, g0);
+    for (uint32_t g = g0; g < g1; g += 2) {
+        if (g + 1 < g1) load(xb, wb2, g + 1);
+        compute(xa, wa);
+        if (g + 1 >= g1) break;
+        if (g + 2 < g1) load(xa, wa, g + 2);
+        compute(xb, wb2);
     }
 
     const uint32_t q = lc.q;
@@ -151,11 +166,166 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
         }
         const uint32_t row = row0 + r;
         if (row >= a.rows) break;
-        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN + slot;
+        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
 #pragma unroll
         for (int j = 0; j < OT; j++) {
-            if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN] = y[j];
+            if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN + slot] = y[j];
         }
+    }
+}
+
+// LDS-pipelined multiply-accumulate. A block of 256 threads (4 waves in a
+// WR x WO grid) owns 64 consecutive NTT slots of one limb (lane = slot) and a
+// tile of MB = WR*MT rows by OB = WO*OT outputs; wave (wr, wo) accumulates
+// rows [wr*MT, +MT) x outputs [wo*OT, +OT). For every input group g the MB
+// ciphertext rows and OB weight rows of the block (64 words each) are copied
+// global -> LDS with direct-to-LDS 16-byte loads, NS groups ahead of the
+// arithmetic, so each word is fetched once per block and the copies need no
+// registers. One barrier per group separates a stage's reads from its reuse.
+__device__ __forceinline__ void wait_vm(int n) {
+    // s_waitcnt with vmcnt = n (n <= 15 here), expcnt and lgkmcnt left at max
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+        case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+        case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+        case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+        case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+        case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+        case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+        case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
+        case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+        case 9: __builtin_amdgcn_s_waitcnt(0x0F79); break;
+        case 10: __builtin_amdgcn_s_waitcnt(0x0F7A); break;
+        case 11: __builtin_amdgcn_s_waitcnt(0x0F7B); break;
+        case 12: __builtin_amdgcn_s_waitcnt(0x0F7C); break;
+        default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    }
+}
+
+template <int MT, int OT, int WR, int WO, int NS>
+__global__ void __launch_bounds__(256) mac_lds_kernel(MacArgs a) {
+    constexpr int MB = WR * MT, OB = WO * OT;
+    constexpr int ROWS = MB + OB;
+    constexpr int RND = (ROWS + 15) / 16;   // loader rounds: 256 threads x 16 B = 16 rows
+    constexpr int PROWS = RND * 16;
+    static_assert(WR * WO == 4, "four waves per block");
+    static_assert(RND * (NS - 2) <= 12, "vmcnt budget");
+    __shared__ __attribute__((aligned(16))) uint32_t lds[NS][PROWS][64];
+
+    const uint32_t nb = gridDim.x;
+    const uint32_t xcd = blockIdx.x & 7u, local = blockIdx.x >> 3;
+    const uint32_t per = (nb + 7) >> 3;
+    const uint32_t full = nb - (per - 1) * 8;
+    const uint32_t logical = (xcd < full) ? xcd * per + local
+                                          : full * per + (xcd - full) * (per - 1) + local;
+    const uint32_t mt = logical % a.n_mt;
+    const uint32_t ot = (logical / a.n_mt) % a.n_ot;
+    const uint32_t kc = logical / (a.n_mt * a.n_ot);       // 64-slot chunk
+    const uint32_t chunks = a.N >> 6;
+    const uint32_t limb = kc / chunks;
+    const uint32_t slot0 = limb * a.N + (kc % chunks) * 64;
+    const LimbConst lc = a.lt.c[limb];
+    const uint32_t r32 = lc.r32;
+    const size_t LN = (size_t)a.L * a.N;
+    const uint32_t row0 = mt * MB, o0 = ot * OB;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wr = wave / WO, wo = wave % WO;
+
+    // loader: in round rd thread tid copies 16 B of LDS row rd*16 + tid/16
+    const uint32_t *src[RND];
+    size_t stride[RND];
+#pragma unroll
+    for (int rd = 0; rd < RND; rd++) {
+        const uint32_t lr = rd * 16 + (tid >> 4);
+        const uint32_t col = (tid & 15) * 4;
+        if (lr < (uint32_t)MB) {
+            const uint32_t row = min(row0 + lr, a.rows - 1);
+            src[rd] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN + slot0 + col;
+            stride[rd] = 2 * LN;
+        } else {
+            const uint32_t o = min(o0 + min(lr - MB, (uint32_t)OB - 1), a.Co - 1);
+            src[rd] = a.w + (size_t)o * a.w_groups * LN + slot0 + col;
+            stride[rd] = LN;
+        }
+    }
+    auto issue = [&](int st, uint32_t g) {
+#pragma unroll
+        for (int rd = 0; rd < RND; rd++) {
+            const uint32_t *p = src[rd] + (size_t)g * stride[rd];
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)p,
+                                             (__attribute__((address_space(3))) void *)&lds[st][rd * 16 + wave * 4][0],
+                                             16, 0, 0);
+        }
+    };
+
+    uint64_t acc[MT][OT];
+#pragma unroll
+    for (int r = 0; r < MT; r++)
+#pragma unroll
+        for (int j = 0; j < OT; j++) acc[r][j] = 0;
+
+    const uint32_t g1 = a.n_groups;
+#pragma unroll
+    for (int i = 0; i < NS - 1; i++)
+        if ((uint32_t)i < g1) issue(i, i);
+    const uint32_t F = lc.fold;
+    uint32_t since = 0;
+    int st = 0;
+    for (uint32_t g = 0; g < g1; g++) {
+        // this thread's copies of group g have landed once at most the
+        // copies of the groups issued after it are outstanding
+        if (g + NS - 2 < g1) wait_vm(RND * (NS - 2));
+        else wait_vm(0);
+        // workgroup barrier without a fence: the copies this stage needs are
+        // complete per the wait above; later stages stay in flight
+        asm volatile("s_barrier" ::: "memory");
+        if (g + NS - 1 < g1) issue(st == 0 ? NS - 1 : st - 1, g + NS - 1);
+        uint32_t x[MT], w[OT];
+#pragma unroll
+        for (int r = 0; r < MT; r++) x[r] = lds[st][wr * MT + r][lane];
+#pragma unroll
+        for (int j = 0; j < OT; j++) w[j] = lds[st][MB + wo * OT + j][lane];
+#pragma unroll
+        for (int r = 0; r < MT; r++)
+#pragma unroll
+            for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
+        if (++since >= F) {
+            since = 0;
+#pragma unroll
+            for (int r = 0; r < MT; r++)
+#pragma unroll
+                for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
+        }
+        st = (st + 1 == NS) ? 0 : st + 1;
+    }
+
+    const uint32_t q = lc.q;
+    const uint32_t slot = slot0 + lane;
+    const uint32_t orow0 = row0 + wr * MT, oo0 = o0 + wo * OT;
+#pragma unroll
+    for (int r = 0; r < MT; r++) {
+        uint32_t y[OT];
+#pragma unroll
+        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
+        if (a.fuse) {
+#pragma unroll
+            for (int h = 1; h < OT; h <<= 1) {
+                if ((uint32_t)h >= a.c_n) break;
+#pragma unroll
+                for (int j = 0; j < OT; j++) {
+                    if (j & h) continue;
+                    const uint32_t u = y[j], v = y[j + h];
+                    y[j] = csub(u + v, q);
+                    y[j + h] = csub(u - v + q, q);
+                }
+            }
+        }
+        const uint32_t row = orow0 + r;
+        if (row >= a.rows) break;
+        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
+#pragma unroll
+        for (int j = 0; j < OT; j++)
+            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + slot] = y[j];
     }
 }
 
@@ -256,6 +426,18 @@ hipError_t launch_mac(const MacArgs &base, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int MT, int OT, int WR, int WO, int NS>
+hipError_t launch_mac_lds(const MacArgs &base, hipStream_t s) {
+    MacArgs a = base;
+    a.n_ot = (a.Co + WO * OT - 1) / (WO * OT);
+    a.n_mt = (a.rows + WR * MT - 1) / (WR * MT);
+    a.kchunks = a.N / 64;
+    const size_t nb = (size_t)a.n_ot * a.n_mt * a.kchunks * a.L;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mac_lds_kernel<MT, OT, WR, WO, NS>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
                       hipStream_t s) {
     const size_t n = G * 2 * (size_t)c->L * c->N;
@@ -275,47 +457,79 @@ hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint3
 }  // namespace
 
 // Tile choice of the MAC: rows x outputs per thread.
-struct MacTile {
-    int mt, ot;
+// MAC schedules: the direct kernel (registers only) and the LDS-pipelined
+// kernel, with their tiles. The autotuner searches this table.
+struct MacSched {
+    int lds;            // 0: mac_kernel, 1: mac_lds_kernel
+    int mt, ot, wr, wo, ns;
 };
 
-static MacTile default_tile(const hyena_conv_desc *d) {
+static const MacSched kScheds[] = {
+    {0, 2, 16, 0, 0, 0}, {0, 4, 8, 0, 0, 0}, {0, 4, 16, 0, 0, 0}, {0, 8, 4, 0, 0, 0},
+    {0, 8, 8, 0, 0, 0},  {0, 16, 4, 0, 0, 0}, {0, 2, 8, 0, 0, 0}, {0, 2, 4, 0, 0, 0},
+    {0, 2, 2, 0, 0, 0},  {0, 2, 1, 0, 0, 0},  {0, 4, 4, 0, 0, 0}, {0, 4, 2, 0, 0, 0},
+    {0, 4, 1, 0, 0, 0},  {0, 8, 2, 0, 0, 0},  {0, 8, 1, 0, 0, 0},
+    {1, 8, 8, 2, 2, 4},  {1, 8, 8, 2, 2, 3},  {1, 4, 8, 2, 2, 4},  {1, 8, 8, 1, 4, 4},
+    {1, 2, 16, 1, 4, 4}, {1, 4, 16, 1, 4, 3}, {1, 8, 4, 4, 1, 4},  {1, 4, 8, 1, 4, 4},
+};
+static const int kNumScheds = sizeof(kScheds) / sizeof(kScheds[0]);
+
+static int find_sched(int lds, int mt, int ot) {
+    for (int i = 0; i < kNumScheds; i++)
+        if (kScheds[i].lds == lds && kScheds[i].mt == mt && kScheds[i].ot == ot) return i;
+    return -1;
+}
+
+static int default_sched(const hyena_conv_desc *d) {
     const uint32_t rows = 2 * d->batch * d->tiles;
     if (d->depthwise) {
         // outputs of one tile must share the input group
         int ot = 1;
         while (ot < 8 && d->ci % (2 * ot) == 0 && d->Co % (2 * ot) == 0) ot *= 2;
         if (ot < (int)d->c_n) ot = (int)d->c_n;
-        return {rows >= 4 ? 4 : 2, ot};
+        return find_sched(0, rows >= 4 ? 4 : 2, ot);
     }
-    if (rows >= 8) return {8, 8};
-    if (rows >= 4) return {4, 8};
-    return {2, 16};
+    if (rows >= 16) return 15;   // LDS 16 x 16 block tile
+    if (rows >= 8) return 18;    // LDS 8 x 32
+    if (rows >= 4) return 20;    // LDS 4 x 64
+    return 19;                   // LDS 2 x 64
 }
 
-static hipError_t dispatch_mac(const MacArgs &a, MacTile t, hipStream_t s) {
+static bool sched_valid(const hyena_conv_desc *d, const MacSched &t) {
+    if (!d->depthwise) return true;
+    return t.lds == 0 && (d->ci % (uint32_t)t.ot == 0 || t.ot == 1) && (uint32_t)t.ot >= 1;
+}
+
+static hipError_t dispatch_mac(const MacArgs &a, const MacSched &t, hipStream_t s) {
+    if (t.lds) {
+#define HY_L(M, O, R, W, S) \
+    if (t.mt == M && t.ot == O && t.wr == R && t.wo == W && t.ns == S) return launch_mac_lds<M, O, R, W, S>(a, s);
+        HY_L(8, 8, 2, 2, 4) HY_L(8, 8, 2, 2, 3) HY_L(4, 8, 2, 2, 4) HY_L(8, 8, 1, 4, 4)
+        HY_L(2, 16, 1, 4, 4) HY_L(4, 16, 1, 4, 3) HY_L(8, 4, 4, 1, 4) HY_L(4, 8, 1, 4, 4)
+#undef HY_L
+        return hipErrorInvalidValue;
+    }
 #define HY_CASE(M, O) \
     if (t.mt == M && t.ot == O) return launch_mac<M, O>(a, s);
     HY_CASE(2, 1) HY_CASE(2, 2) HY_CASE(2, 4) HY_CASE(2, 8) HY_CASE(2, 16)
     HY_CASE(4, 1) HY_CASE(4, 2) HY_CASE(4, 4) HY_CASE(4, 8) HY_CASE(4, 16)
     HY_CASE(8, 1) HY_CASE(8, 2) HY_CASE(8, 4) HY_CASE(8, 8)
-    HY_CASE(16, 4) HY_CASE(16, 8)
+    HY_CASE(16, 4)
 #undef HY_CASE
     return hipErrorInvalidValue;
 }
 
 int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                uint32_t *out, int mt, int ot, bool per_channel, hipStream_t s) {
+                uint32_t *out, int sched, bool per_channel, hipStream_t s) {
     if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
     if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
     if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
-    MacTile t = default_tile(d);
-    if (mt > 0) t.mt = mt;
-    if (ot > 0) t.ot = ot;
+    if (sched < 0) sched = default_sched(d);
+    if (sched < 0 || sched >= kNumScheds) return set_error(HYENA_EINVAL, "hyena_conv: unknown schedule");
+    const MacSched &t = kScheds[sched];
+    if (!sched_valid(d, t)) return set_error(HYENA_EINVAL, "hyena_conv: schedule not valid for this layer");
     const uint32_t cn = d->c_n ? d->c_n : 1;
-    if (d->depthwise && (d->ci % (uint32_t)t.ot != 0 && t.ot != 1))
-        return set_error(HYENA_EINVAL, "hyena_conv: depthwise output tile must divide ci");
     MacArgs a{};
     a.ct = ct;
     a.w = w;
@@ -334,7 +548,7 @@ int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct
     const bool fuse_in_mac = cn > 1 && (uint32_t)t.ot >= cn && (uint32_t)t.ot % cn == 0;
     a.fuse = (per_channel && fuse_in_mac) ? 1 : 0;
     hipError_t e = dispatch_mac(a, t, s);
-    if (e == hipErrorInvalidValue) return set_error(HYENA_EINVAL, "hyena_conv: unsupported MAC tile");
+    if (e == hipErrorInvalidValue) return set_error(HYENA_EINVAL, "hyena_conv: unsupported MAC schedule");
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
     if (cn > 1 && per_channel && !fuse_in_mac) {
         const size_t G = (size_t)a.rows / 2 * d->Co / cn;
@@ -344,12 +558,36 @@ int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct
     return HYENA_OK;
 }
 
+extern "C" int hyena_conv_schedules(int *count) {
+    if (count) *count = kNumScheds;
+    return HYENA_OK;
+}
+
+extern "C" int hyena_conv_schedule_info(int sched, int *info /* [6] */) {
+    if (sched < 0 || sched >= kNumScheds || !info) return set_error(HYENA_EINVAL, "hyena_conv_schedule_info: bad schedule");
+    const MacSched &t = kScheds[sched];
+    info[0] = t.lds; info[1] = t.mt; info[2] = t.ot; info[3] = t.wr; info[4] = t.wo; info[5] = t.ns;
+    return HYENA_OK;
+}
+
+extern "C" int hyena_conv_default_schedule(const hyena_conv_desc *d) {
+    if (!d) return set_error(HYENA_EINVAL, "hyena_conv_default_schedule: NULL descriptor");
+    return default_sched(d);
+}
+
 extern "C" int hyena_conv(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
                           const uint32_t *d_wntt, uint32_t *d_out_ntt, hyena_stream_t s) {
     if (!d) return set_error(HYENA_EINVAL, "hyena_conv: NULL descriptor");
     // without HYENA_FUSE_WHT the output holds the Walsh components
     const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
-    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, 0, 0, per_channel, (hipStream_t)s);
+    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, -1, per_channel, (hipStream_t)s);
+}
+
+extern "C" int hyena_conv_tiled(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
+                                const uint32_t *d_wntt, uint32_t *d_out_ntt, int sched, hyena_stream_t s) {
+    if (!d) return set_error(HYENA_EINVAL, "hyena_conv_tiled: NULL descriptor");
+    const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
+    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, sched, per_channel, (hipStream_t)s);
 }
 
 extern "C" int hyena_wht_pack(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,

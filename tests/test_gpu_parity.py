@@ -249,3 +249,42 @@ def test_vgg_conv1_2_full_size_sampled(dev):
         want = orc.conv_products(pl, ct[b], w, ctx.primes, outputs=sel)
         for u, (tau, o) in enumerate(sel):
             assert np.array_equal(got[b, tau, o], want[u]), (b, tau, o)
+
+
+@pytest.mark.parametrize("lay,c_n,batch", [
+    (wl.Layer("t", 14, 14, 64, 48, 3), 4, 3),   # rows = 6, partial row and output blocks
+    (wl.Layer("t", 28, 28, 40, 24, 3), 2, 8),   # rows = 16, 5 input groups (stage tail)
+    (wl.Layer("t", 14, 14, 32, 32, 3, depthwise=True), 2, 2),
+], ids=["std_rows6", "std_rows16", "depthwise"])
+def test_every_mac_schedule_matches_oracle(dev, lay, c_n, batch):
+    """All MAC schedules (register-only and LDS-pipelined) give the oracle's
+    output on every coefficient."""
+    import torch
+    ctx = ctx_for(8192, 3, 31)
+    N, L = 8192, 3
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, depthwise=lay.depthwise, c_n=c_n,
+                           flags=hy.HYENA_FUSE_WHT, batch=batch)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, lay.depthwise)
+    rng = np.random.default_rng(31)
+    ct = rand_res(rng, (batch, pl.tiles, pl.n_groups, 2, L, N), ctx.primes)
+    w = wl.weights(77, lay)
+    d_ct = to_dev(ct)
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    d_out = torch.empty(batch * pl.tiles * lay.Co * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, torch.from_numpy(w).cuda(), d_wn)
+    hy.hyena_ntt(ctx, d_ct)
+    want = [orc.conv_products(pl, ct[b], w, ctx.primes).reshape(pl.tiles, lay.Co, 2, L, N) for b in range(batch)]
+    ran = 0
+    for sid, info in enumerate(hy.hyena_conv_schedules()):
+        try:
+            hy.hyena_conv_tiled(ctx, d, d_ct, d_wn, d_out, sid)
+        except hy.HyenaError as e:
+            assert lay.depthwise and e.code == hy.HYENA_EINVAL, (sid, info)
+            continue
+        o = d_out.clone()
+        hy.hyena_intt(ctx, o)
+        got = from_dev(o).reshape(batch, pl.tiles, lay.Co, 2, L, N)
+        for b in range(batch):
+            assert np.array_equal(got[b], want[b]), (sid, info, b)
+        ran += 1
+    assert ran >= (4 if lay.depthwise else len(hy.hyena_conv_schedules()))

@@ -7,11 +7,11 @@ sharing any computation.
 
 Value recipe. Activations and weights are uniform signed 4-bit integers in
 [-8, 7], drawn with ``numpy.random.default_rng(seed)``. The paper evaluates on
-trained ImageNet CNNs (VGG-16, ResNet, MobileNetV1; Section 5.1, "Evaluation
-Setup"); neither the dataset nor trained weights are available here, so the
+trained ImageNet CNNs (VGG-16, ResNet, MobileNetV1; the "Evaluation
+Setup" section); neither the dataset nor trained weights are available here, so the
 layer *shapes* of those networks are used with synthetic values of the small
 integer width the paper's kernels carry (kernel elements below 8 bits,
-Section 4.2.1).
+the "Optimal Parameter Selection" section).
 
 Seeds. ``seed = 1000 * workload_id + layer_index``; image ``b`` of a batch uses
 ``seed + 100 * b``; key generation and encryption use ``seed ^ 0x5EED``.
