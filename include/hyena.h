@@ -207,6 +207,18 @@ int hyena_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t s
 int hyena_intt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
 
 /*
+ * NTT schedules (threads per polynomial and butterfly stages per register
+ * pass). Every schedule gives the same result as hyena_ntt / hyena_intt; they
+ * differ in speed and are searched by the autotuner. hyena_ntt_schedules
+ * reports the ids [first, first + count) that exist for ring degree N;
+ * hyena_ntt_sched runs the forward (inverse = 0) or inverse transform with
+ * schedule `sched` (-1 = default). Errors: EINVAL for a schedule of another N.
+ */
+int hyena_ntt_schedules(uint32_t N, int *first, int *count);
+int hyena_ntt_sched(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, int inverse, int sched,
+                    hyena_stream_t stream);
+
+/*
  * The homomorphic convolution in the NTT domain (Sections 3.2, 4.1, 4.2.2):
  *   A[b][tau][G][j][p][i][k] = sum_g ct[b][tau][g][p][i][k] * W[G][j][g][i][k]  mod q_i
  * accumulated lazily in 64 bits with one reduction per output coefficient.
@@ -251,6 +263,51 @@ int hyena_conv_tiled(const hyena_ctx *ctx, const hyena_conv_desc *desc,
  */
 int hyena_wht_pack(const hyena_ctx *ctx, uint32_t c_n, const uint32_t *d_in,
                    uint32_t *d_out, size_t G, hyena_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched path: many layers (and images) per step.
+ *
+ * A step runs, for every layer: the forward NTT of its input ciphertexts (in
+ * place), the multiply-accumulate with the Walsh-Hadamard recombination, and
+ * the inverse NTT of its outputs, leaving d_out in the coefficient domain
+ * exactly as the per-layer calls (hyena_ntt, hyena_conv with HYENA_FUSE_WHT,
+ * hyena_intt) would. Layers are independent (the nonlinear layers between
+ * convolutions are evaluated by the other party, outside this computation).
+ * A second run transforms d_ct again: refill it before a run whose result
+ * matters.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const hyena_conv_desc *desc;  /* planned; desc->batch images share the weights */
+    uint32_t *d_ct;               /* device [batch][tiles][n_groups][2][L][N], coefficient domain */
+    const uint32_t *d_wntt;       /* device, from hyena_encode_weights */
+    uint32_t *d_out;              /* device [batch][tiles][Co][2][L][N]; must not alias d_ct */
+} hyena_layer_io;
+
+typedef struct hyena_batch hyena_batch;
+
+#define HYENA_BATCH_PERSISTENT 0x1u /* layers sharing an LDS schedule run in one persistent launch */
+#define HYENA_BATCH_GRAPH 0x2u      /* the step is captured once into a hipGraph and replayed */
+#define HYENA_BATCH_TUNE 0x4u       /* MAC schedule per layer and NTT schedule per direction chosen
+                                       by timing; choices cached in the file named by the
+                                       environment variable HYENA_TUNE_CACHE when set */
+
+/*
+ * Build a batched step over n_layers layers. Copies the descriptors and keeps
+ * the buffer pointers (the caller keeps the buffers alive until
+ * hyena_batch_destroy). With HYENA_BATCH_TUNE the schedules are timed on the
+ * given buffers (their contents are left unchanged). Allocates small device
+ * tables. Errors: EINVAL, EHIP, ENOMEM.
+ */
+int hyena_batch_create(const hyena_ctx *ctx, const hyena_layer_io *layers, uint32_t n_layers,
+                       uint32_t flags, hyena_batch **out);
+/* Enqueue one step on stream (with HYENA_BATCH_GRAPH: replay the graph,
+ * capturing it on the first call). Calls on one batch must not overlap. */
+int hyena_batch_run(hyena_batch *b, hyena_stream_t stream);
+/* info[] = {ntt forward schedule, ntt inverse schedule, kernel launches per
+ * step, n_layers, persistent launches, MAC schedule of layer 0, 1, ...};
+ * entries beyond the end are -1. */
+int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info);
+void hyena_batch_destroy(hyena_batch *b);
 
 #ifdef __cplusplus
 }

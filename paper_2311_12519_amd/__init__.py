@@ -30,6 +30,9 @@ HYENA_ALLOW_INSECURE = 0x1
 HYENA_HOST_ONLY = 0x2
 HYENA_PRIMES_30BIT = 0x100
 HYENA_FUSE_WHT = 0x1
+HYENA_BATCH_PERSISTENT = 0x1
+HYENA_BATCH_GRAPH = 0x2
+HYENA_BATCH_TUNE = 0x4
 
 _ERRNAMES = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOISE", -4: "EHIP", -5: "ENOMEM"}
 
@@ -45,6 +48,12 @@ class ConvDesc(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in (
         "H", "W", "Ci", "Co", "k", "stride", "depthwise", "c_n", "flags", "ci_req", "batch",
         "pad", "Wp", "R", "tiles", "ci", "Bt", "O", "n_groups", "n_in", "n_out", "w_groups")]
+
+
+class LayerIO(ctypes.Structure):
+    """Mirror of hyena_layer_io."""
+    _fields_ = [("desc", ctypes.c_void_p), ("d_ct", ctypes.c_void_p), ("d_wntt", ctypes.c_void_p),
+                ("d_out", ctypes.c_void_p)]
 
 
 _lib = None
@@ -72,6 +81,8 @@ _SIGS = {
     "hyena_conv_schedules": [_P],
     "hyena_conv_schedule_info": [ctypes.c_int, _P],
     "hyena_conv_default_schedule": [_P],
+    "hyena_ntt_schedules": [_u32, _P, _P],
+    "hyena_ntt_sched": [_P, _P, _sz, ctypes.c_int, ctypes.c_int, _P],
 }
 
 
@@ -97,12 +108,10 @@ def lib() -> ctypes.CDLL:
 def _register_extra(L):
     """Signatures of the batched-path and cost-model entry points, if present."""
     extra = {
-        "hyena_batch_create": [_P, _P, _u32, _u32, _P, _P],
+        "hyena_batch_create": [_P, _P, _u32, _u32, _P],
         "hyena_batch_destroy": [_P],
-        "hyena_batch_run": [_P, _P, _P, _P, _P],
-        "hyena_batch_capture": [_P, _P, _P, _P, _P],
-        "hyena_batch_replay": [_P, _P],
-        "hyena_batch_info": [_P, _P],
+        "hyena_batch_run": [_P, _P],
+        "hyena_batch_info": [_P, _P, _sz],
         "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
         "hyena_conv_schedules": [_P],
         "hyena_conv_schedule_info": [ctypes.c_int, _P],
@@ -254,6 +263,19 @@ def hyena_intt(ctx: Ctx, d_poly, stream=None) -> None:
     _check(lib().hyena_intt(ctx.handle, _dev_ptr(d_poly, "int32"), P, _stream(stream)))
 
 
+def hyena_ntt_schedules(N: int) -> list:
+    first, count = ctypes.c_int(), ctypes.c_int()
+    _check(lib().hyena_ntt_schedules(N, ctypes.byref(first), ctypes.byref(count)))
+    return list(range(first.value, first.value + count.value))
+
+
+def hyena_ntt_sched(ctx: Ctx, d_poly, inverse: bool, sched: int, stream=None) -> None:
+    P = d_poly.numel() // (ctx.L * ctx.N)
+    if P * ctx.L * ctx.N != d_poly.numel():
+        raise ValueError("tensor size is not a multiple of L*N")
+    _check(lib().hyena_ntt_sched(ctx.handle, _dev_ptr(d_poly, "int32"), P, int(inverse), sched, _stream(stream)))
+
+
 def hyena_conv(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_wntt, d_out_ntt, stream=None) -> None:
     _check(lib().hyena_conv(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct_ntt, "int32"),
                             _dev_ptr(d_wntt, "int32"), _dev_ptr(d_out_ntt, "int32"), _stream(stream)))
@@ -294,3 +316,55 @@ def wntt_words(ctx: Ctx, desc: ConvDesc) -> int:
 def u32_view(t):
     """Reinterpret an int32 device tensor's words as unsigned (host numpy side)."""
     return t.cpu().numpy().view(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# batched path
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """Owns a hyena_batch handle and keeps the descriptors and buffers alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.hyena_batch_destroy(h)
+            self.handle = None
+
+
+def hyena_batch_create(ctx: Ctx, layers, flags: int = 0) -> Batch:
+    """layers: list of (ConvDesc, d_ct, d_wntt, d_out) with int32 device tensors."""
+    arr = (LayerIO * len(layers))()
+    keep = []
+    for i, (desc, d_ct, d_wn, d_out) in enumerate(layers):
+        arr[i].desc = ctypes.cast(ctypes.pointer(desc), ctypes.c_void_p)
+        arr[i].d_ct = _dev_ptr(d_ct, "int32")
+        arr[i].d_wntt = _dev_ptr(d_wn, "int32")
+        arr[i].d_out = _dev_ptr(d_out, "int32")
+        keep.append((desc, d_ct, d_wn, d_out))
+    out = ctypes.c_void_p()
+    _check(lib().hyena_batch_create(ctx.handle, arr, len(layers), flags, ctypes.byref(out)))
+    return Batch(out, (ctx, keep))
+
+
+def hyena_batch_run(b: Batch, stream=None) -> None:
+    _check(lib().hyena_batch_run(b.handle, _stream(stream)))
+
+
+def hyena_batch_info(b: Batch) -> dict:
+    n = 5 + 256
+    info = (ctypes.c_int * n)()
+    _check(lib().hyena_batch_info(b.handle, info, n))
+    nl = info[3]
+    return {"ntt_fwd": info[0], "ntt_inv": info[1], "launches": info[2], "layers": nl,
+            "persistent_launches": info[4], "mac_sched": [info[5 + i] for i in range(nl)]}
+
+
+def hyena_batch_destroy(b: Batch) -> None:
+    if b.handle:
+        lib().hyena_batch_destroy(b.handle)
+        b.handle = None

@@ -1,0 +1,453 @@
+// Batched execution of many convolution layers (and images) per step.
+//
+// One step is: forward NTT of every layer's input ciphertexts (segmented
+// launches over all layers), the multiply-accumulate of every layer, and the
+// inverse NTT of every layer's outputs. Layers whose multiply-accumulate uses
+// the same LDS schedule share one persistent launch: a grid sized to the
+// chip's occupancy pulls (layer, tile) work items from eight per-XCD queues
+// (each queue a contiguous slice of the item list, so neighbouring tiles of one
+// slot chunk stay in one L2) and steals from the other queues when its own is
+// empty; uneven layers balance dynamically. The step can be captured once into
+// a hipGraph and replayed. An autotuner times the candidate MAC schedules per
+// layer and the NTT schedules per direction, and keeps the choices in a text
+// cache (HYENA_TUNE_CACHE) so later runs reuse them.
+//
+// Every layer's inputs are independent here: the nonlinear layers between
+// convolutions run under MPC in the paper's protocol and are not part of this
+// server-side computation.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "mac.h"
+
+// schedule table and validity (conv.hip)
+int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
+                uint32_t *out, int sched, bool per_channel, hipStream_t s);
+int conv_sched_info(int sched, int *info);
+int conv_num_scheds();
+bool conv_sched_valid(const hyena_conv_desc *d, int sched);
+int conv_default_sched(const hyena_conv_desc *d);
+MacArgs conv_make_args(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
+                       uint32_t *out, int sched, bool per_channel, bool *needs_wht);
+hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
+                           hipStream_t s);
+
+namespace {
+
+template <int MT, int OT, int WR, int WO, int NS>
+__global__ void __launch_bounds__(256)
+mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
+                      uint32_t *__restrict__ counters, uint32_t total) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
+    __shared__ uint32_t item_s, layer_s;
+    const uint32_t home = blockIdx.x & 7u;
+    uint32_t qi = home;  // queue currently drawn from (thread 0 only)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t it = total;
+            for (int tries = 0; tries < 8; tries++) {
+                const uint32_t lo = (uint32_t)(((uint64_t)total * qi) >> 3);
+                const uint32_t hi = (uint32_t)(((uint64_t)total * (qi + 1)) >> 3);
+                const uint32_t k = atomicAdd(&counters[qi], 1u);
+                if (lo + k < hi) {
+                    it = lo + k;
+                    break;
+                }
+                qi = (qi + 1) & 7u;
+            }
+            uint32_t l = 0;
+            if (it < total)
+                while (l + 1 < n_layers && it >= first[l + 1]) l++;
+            item_s = it;
+            layer_s = l;
+        }
+        __syncthreads();
+        // uniform across the block: lets the layer's arguments load as scalars
+        const uint32_t it = __builtin_amdgcn_readfirstlane(item_s);
+        const uint32_t l = __builtin_amdgcn_readfirstlane(layer_s);
+        __syncthreads();
+        if (it >= total) break;
+        mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, uint32_t);
+
+PersistentFn persistent_fn(const int *info) {
+#define HY_P(M, O, R, W, S)                                                          \
+    if (info[1] == M && info[2] == O && info[3] == R && info[4] == W && info[5] == S) \
+        return mac_persistent_kernel<M, O, R, W, S>;
+    HY_P(8, 8, 2, 2, 4) HY_P(8, 8, 2, 2, 3) HY_P(4, 8, 2, 2, 4) HY_P(8, 8, 1, 4, 4)
+    HY_P(2, 16, 1, 4, 4) HY_P(4, 16, 1, 4, 3) HY_P(8, 4, 4, 1, 4) HY_P(4, 8, 1, 4, 4)
+#undef HY_P
+    return nullptr;
+}
+
+uint32_t mac_blocks(const MacArgs &a) { return a.n_ot * a.n_mt * a.kchunks * a.L; }
+
+// ------------------------------------------------------------------ tuning cache
+
+std::string cache_path() {
+    const char *p = std::getenv("HYENA_TUNE_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+std::map<std::string, int> load_cache() {
+    std::map<std::string, int> m;
+    const std::string path = cache_path();
+    if (path.empty()) return m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos) continue;
+        m[line.substr(0, tab)] = std::atoi(line.c_str() + tab + 1);
+    }
+    return m;
+}
+
+void save_cache(const std::map<std::string, int> &m) {
+    const std::string path = cache_path();
+    if (path.empty()) return;
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        for (auto &kv : m) f << kv.first << '\t' << kv.second << '\n';
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string s = p.gcnArchName;
+    return s.substr(0, s.find(':'));
+}
+
+}  // namespace
+
+struct hyena_batch {
+    const hyena_ctx *ctx = nullptr;
+    uint32_t flags = 0;
+    std::vector<hyena_conv_desc> desc;
+    std::vector<hyena_layer_io> io;
+    std::vector<int> mac_sched;
+    int ntt_fwd = -1, ntt_inv = -1;
+    // persistent groups
+    struct Group {
+        int sched;
+        std::vector<uint32_t> layers;
+        MacArgs *d_args = nullptr;
+        uint32_t *d_first = nullptr;
+        uint32_t total = 0;
+        uint32_t grid = 0;
+    };
+    std::vector<Group> groups;
+    std::vector<uint32_t> solo;   // layers launched on their own
+    uint32_t *d_counters = nullptr;
+    uint32_t n_counters = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int launches = 0;
+};
+
+static int issue_step(hyena_batch *b, hipStream_t s) {
+    const hyena_ctx *c = b->ctx;
+    std::vector<uint32_t *> in_ptrs, out_ptrs;
+    std::vector<size_t> in_P, out_P;
+    for (size_t l = 0; l < b->io.size(); l++) {
+        const hyena_conv_desc &d = b->desc[l];
+        in_ptrs.push_back(b->io[l].d_ct);
+        in_P.push_back((size_t)d.batch * d.n_in * 2);
+        out_ptrs.push_back(b->io[l].d_out);
+        out_P.push_back((size_t)d.batch * d.n_out * 2);
+    }
+    int launches = 0;
+    int rc = launch_ntt_segs(c, in_ptrs.data(), in_P.data(), (uint32_t)in_ptrs.size(), false, b->ntt_fwd, s);
+    if (rc) return rc;
+    launches += (int)((in_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
+    if (b->n_counters) {
+        hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, b->d_counters, b->n_counters);
+        launches++;
+    }
+    for (size_t gi = 0; gi < b->groups.size(); gi++) {
+        auto &g = b->groups[gi];
+        int info[6];
+        conv_sched_info(g.sched, info);
+        PersistentFn fn = persistent_fn(info);
+        hipLaunchKernelGGL(fn, dim3(g.grid), dim3(256), 0, s, (const MacArgs *)g.d_args,
+                           (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi, g.total);
+        launches++;
+        // layers whose Walsh group is wider than the fused epilogue
+        for (uint32_t l : g.layers) {
+            bool wht = false;
+            conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, g.sched, true, &wht);
+            if (wht) {
+                const hyena_conv_desc &d = b->desc[l];
+                const hipError_t e = conv_launch_wht(c, d.c_n, b->io[l].d_out, b->io[l].d_out,
+                                                     (size_t)d.batch * d.tiles * d.Co / d.c_n, s);
+                if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_batch_run: ") + hipGetErrorString(e));
+                launches++;
+            }
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_batch_run: ") + hipGetErrorString(e));
+    for (uint32_t l : b->solo) {
+        rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, b->mac_sched[l], true, s);
+        if (rc) return rc;
+        launches++;
+    }
+    rc = launch_ntt_segs(c, out_ptrs.data(), out_P.data(), (uint32_t)out_ptrs.size(), true, b->ntt_inv, s);
+    if (rc) return rc;
+    launches += (int)((out_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
+    b->launches = launches;
+    return HYENA_OK;
+}
+
+// time `fn` (enqueued on s) with events: best of `reps` after one warm-up
+template <class F>
+static float time_best(hipStream_t s, int reps, F fn) {
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    fn();
+    float best = 1e30f;
+    for (int r = 0; r < reps; r++) {
+        (void)hipEventRecord(e0, s);
+        fn();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+static std::string layer_key(const hyena_ctx *c, const std::string &arch, const hyena_conv_desc &d) {
+    std::ostringstream k;
+    k << arch << "|mac|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt << "|" << d.H << "x" << d.W << "|"
+      << d.Ci << ">" << d.Co << "|k" << d.k << "|dw" << d.depthwise << "|cn" << d.c_n << "|ci" << d.ci << "|b"
+      << d.batch << "|t" << d.tiles;
+    return k.str();
+}
+
+static int tune(hyena_batch *b) {
+    const hyena_ctx *c = b->ctx;
+    const std::string arch = arch_name(c->device);
+    auto cache = load_cache();
+    bool dirty = false;
+    hipStream_t s;
+    HIP_TRY(hipStreamCreate(&s));
+    const int ns = conv_num_scheds();
+    for (size_t l = 0; l < b->desc.size(); l++) {
+        const hyena_conv_desc &d = b->desc[l];
+        const std::string key = layer_key(c, arch, d);
+        auto it = cache.find(key);
+        if (it != cache.end() && it->second >= 0 && it->second < ns && conv_sched_valid(&d, it->second)) {
+            b->mac_sched[l] = it->second;
+            continue;
+        }
+        float best = 1e30f;
+        int best_s = conv_default_sched(&d);
+        for (int sid = 0; sid < ns; sid++) {
+            if (!conv_sched_valid(&d, sid)) continue;
+            int info[6];
+            conv_sched_info(sid, info);
+            if (!d.depthwise && !info[0] && info[1] * info[2] < 16) continue;  // tiny register tiles
+            int rc = HYENA_OK;
+            const float ms = time_best(s, 2, [&] {
+                if (!rc) rc = conv_launch(c, &d, b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, sid, true, s);
+            });
+            if (rc) continue;
+            if (ms < best) {
+                best = ms;
+                best_s = sid;
+            }
+        }
+        b->mac_sched[l] = best_s;
+        cache[key] = best_s;
+        dirty = true;
+    }
+    // NTT schedules per direction over every layer's inputs (a forward and an
+    // inverse transform in a row leave the data unchanged)
+    std::vector<uint32_t *> ptrs;
+    std::vector<size_t> P;
+    size_t polys = 0;
+    for (size_t l = 0; l < b->desc.size(); l++) {
+        ptrs.push_back(b->io[l].d_ct);
+        P.push_back((size_t)b->desc[l].batch * b->desc[l].n_in * 2);
+        polys += P.back();
+    }
+    std::ostringstream nk;
+    nk << arch << "|ntt|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt << "|polys" << (polys >= 4096 ? 4096 : polys);
+    const std::string kf = nk.str() + "|fwd", ki = nk.str() + "|inv";
+    if (cache.count(kf) && cache.count(ki)) {
+        b->ntt_fwd = cache[kf];
+        b->ntt_inv = cache[ki];
+    } else {
+        int first = 0, count = 0;
+        hyena_ntt_schedules(c->N, &first, &count);
+        float bf = 1e30f, bi = 1e30f;
+        for (int sid = first; sid < first + count; sid++) {
+            const float tf = time_best(s, 2, [&] {
+                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), false, sid, s);
+                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), true, -1, s);
+            });
+            const float ti = time_best(s, 2, [&] {
+                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), false, -1, s);
+                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), true, sid, s);
+            });
+            if (tf < bf) { bf = tf; b->ntt_fwd = sid; }
+            if (ti < bi) { bi = ti; b->ntt_inv = sid; }
+        }
+        cache[kf] = b->ntt_fwd;
+        cache[ki] = b->ntt_inv;
+        dirty = true;
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (dirty) save_cache(cache);
+    return HYENA_OK;
+}
+
+static int build_groups(hyena_batch *b) {
+    const hyena_ctx *c = b->ctx;
+    std::map<int, std::vector<uint32_t>> by_sched;
+    for (uint32_t l = 0; l < b->desc.size(); l++) {
+        int info[6];
+        conv_sched_info(b->mac_sched[l], info);
+        if ((b->flags & HYENA_BATCH_PERSISTENT) && info[0] && persistent_fn(info))
+            by_sched[b->mac_sched[l]].push_back(l);
+        else
+            b->solo.push_back(l);
+    }
+    int n_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+    b->n_counters = 8 * (uint32_t)by_sched.size();
+    if (b->n_counters) HIP_TRY(hipMalloc((void **)&b->d_counters, sizeof(uint32_t) * b->n_counters));
+    for (auto &kv : by_sched) {
+        hyena_batch::Group g;
+        g.sched = kv.first;
+        // biggest layers first so the tail of the queue holds the short items
+        g.layers = kv.second;
+        std::vector<MacArgs> args;
+        std::vector<uint32_t> first;
+        uint32_t total = 0;
+        for (uint32_t l : g.layers) {
+            bool wht = false;
+            MacArgs a = conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, g.sched,
+                                       true, &wht);
+            args.push_back(a);
+            first.push_back(total);
+            total += mac_blocks(a);
+        }
+        first.push_back(total);
+        g.total = total;
+        int info[6];
+        conv_sched_info(g.sched, info);
+        int per_cu = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)persistent_fn(info), 256, 0));
+        g.grid = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
+        if (g.grid > total) g.grid = std::max<uint32_t>(total, 1);
+        HIP_TRY(hipMalloc((void **)&g.d_args, sizeof(MacArgs) * args.size()));
+        HIP_TRY(hipMalloc((void **)&g.d_first, sizeof(uint32_t) * first.size()));
+        HIP_TRY(hipMemcpy(g.d_args, args.data(), sizeof(MacArgs) * args.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(g.d_first, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
+        b->groups.push_back(g);
+    }
+    return HYENA_OK;
+}
+
+extern "C" void hyena_batch_destroy(hyena_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto &g : b->groups) {
+        if (g.d_args) (void)hipFree(g.d_args);
+        if (g.d_first) (void)hipFree(g.d_first);
+    }
+    if (b->d_counters) (void)hipFree(b->d_counters);
+    delete b;
+}
+
+extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *layers, uint32_t n_layers,
+                                  uint32_t flags, hyena_batch **out) {
+    if (!c || !layers || !out || n_layers == 0) return set_error(HYENA_EINVAL, "hyena_batch_create: bad argument");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_batch_create: context was created host-only");
+    *out = nullptr;
+    auto *b = new (std::nothrow) hyena_batch();
+    if (!b) return set_error(HYENA_ENOMEM, "hyena_batch_create: out of host memory");
+    b->ctx = c;
+    b->flags = flags;
+    for (uint32_t l = 0; l < n_layers; l++) {
+        const hyena_layer_io &io = layers[l];
+        if (!io.desc || !io.d_ct || !io.d_wntt || !io.d_out || !io.desc->Bt) {
+            delete b;
+            return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
+                                               " has a NULL buffer or an unplanned descriptor");
+        }
+        b->desc.push_back(*io.desc);
+        if (b->desc.back().batch == 0) b->desc.back().batch = 1;
+        b->io.push_back(io);
+        b->mac_sched.push_back(conv_default_sched(io.desc));
+    }
+    b->ntt_fwd = b->ntt_inv = ntt_default_schedule(c->logN);
+    int rc = HYENA_OK;
+    if (flags & HYENA_BATCH_TUNE) rc = tune(b);
+    if (!rc) rc = build_groups(b);
+    if (rc) {
+        hyena_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return HYENA_OK;
+}
+
+extern "C" int hyena_batch_run(hyena_batch *b, hyena_stream_t stream) {
+    if (!b) return set_error(HYENA_EINVAL, "hyena_batch_run: NULL batch");
+    const hipStream_t s = (hipStream_t)stream;
+    if (!(b->flags & HYENA_BATCH_GRAPH)) return issue_step(b, s);
+    if (!b->exec) {
+        // capture on a private stream (the null stream cannot be captured)
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreate(&cs));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = HYENA_OK;
+        if (e == hipSuccess) rc = issue_step(b, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || e2 != hipSuccess)
+            return set_error(HYENA_EHIP, std::string("hyena_batch_run: capture failed: ") +
+                                             hipGetErrorString(e != hipSuccess ? e : e2));
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, s));
+    return HYENA_OK;
+}
+
+extern "C" int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info) {
+    if (!b || !info) return set_error(HYENA_EINVAL, "hyena_batch_info: NULL argument");
+    std::vector<int> v = {b->ntt_fwd, b->ntt_inv, b->launches, (int)b->desc.size(), (int)b->groups.size()};
+    for (int s : b->mac_sched) v.push_back(s);
+    for (size_t i = 0; i < n_info; i++) info[i] = i < v.size() ? v[i] : -1;
+    return HYENA_OK;
+}

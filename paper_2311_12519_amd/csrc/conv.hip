@@ -15,48 +15,9 @@
 // PMult by the +-1 pattern).
 #include <algorithm>
 
-#include "internal.h"
+#include "mac.h"
 
 namespace {
-
-__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t q) { return min(x, x - q); }
-
-__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
-    return csub(a * w - __umulhi(a, ws) * q, q);
-}
-
-__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
-    return (uint64_t)a * b + c;  // one v_mad_u64_u32
-}
-
-// Exact reduction of a 64-bit accumulator to [0, q).
-__device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
-    const uint32_t q = lc.q;
-    const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
-    // hi mod q: floor(hi * mu32 / 2^32) is floor(hi / q) or one less
-    const uint32_t hr = csub(hi - __umulhi(hi, lc.mu32) * q, q);
-    // y = hi * 2^32 + lo = hr * r32 + lo (mod q), y < q * 2^32
-    const uint64_t y = mad64(hr, lc.r32, lo);
-    // Montgomery REDC: z = y * 2^-32 mod q in [0, 2q)
-    const uint32_t m = (uint32_t)y * lc.qinv_neg;
-    const uint64_t t = mad64(m, q, y);
-    const uint32_t z = csub((uint32_t)(t >> 32), q);
-    // times 2^32 mod q
-    return shoup(z, lc.r32, lc.r32s, q);
-}
-
-__device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t r32) {
-    return mad64((uint32_t)(acc >> 32), r32, (uint32_t)acc);
-}
-
-struct MacArgs {
-    const uint32_t *ct;   // [rows/2][n_groups][2][L][N]
-    const uint32_t *w;    // [Co][w_groups][L][N]
-    uint32_t *out;        // [rows/2][Co][2][L][N]
-    uint32_t N, L, logN, Co, n_groups, w_groups, rows, ci, c_n;
-    uint32_t depthwise, fuse, n_ot, n_mt, kchunks;
-    LimbTable lt;
-};
 
 // One thread = one NTT slot (limb, k) for MT rows x OT outputs. Blocks are
 // 256 threads along k. The block index is remapped so that all o- and
@@ -171,161 +132,6 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
         for (int j = 0; j < OT; j++) {
             if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN + slot] = y[j];
         }
-    }
-}
-
-// LDS-pipelined multiply-accumulate. A block of 256 threads (4 waves in a
-// WR x WO grid) owns 64 consecutive NTT slots of one limb (lane = slot) and a
-// tile of MB = WR*MT rows by OB = WO*OT outputs; wave (wr, wo) accumulates
-// rows [wr*MT, +MT) x outputs [wo*OT, +OT). For every input group g the MB
-// ciphertext rows and OB weight rows of the block (64 words each) are copied
-// global -> LDS with direct-to-LDS 16-byte loads, NS groups ahead of the
-// arithmetic, so each word is fetched once per block and the copies need no
-// registers. One barrier per group separates a stage's reads from its reuse.
-__device__ __forceinline__ void wait_vm(int n) {
-    // s_waitcnt with vmcnt = n (n <= 15 here), expcnt and lgkmcnt left at max
-    switch (n) {
-        case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-        case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
-        case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
-        case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
-        case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
-        case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
-        case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
-        case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
-        case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
-        case 9: __builtin_amdgcn_s_waitcnt(0x0F79); break;
-        case 10: __builtin_amdgcn_s_waitcnt(0x0F7A); break;
-        case 11: __builtin_amdgcn_s_waitcnt(0x0F7B); break;
-        case 12: __builtin_amdgcn_s_waitcnt(0x0F7C); break;
-        default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
-    }
-}
-
-template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256) mac_lds_kernel(MacArgs a) {
-    constexpr int MB = WR * MT, OB = WO * OT;
-    constexpr int ROWS = MB + OB;
-    constexpr int RND = (ROWS + 15) / 16;   // loader rounds: 256 threads x 16 B = 16 rows
-    constexpr int PROWS = RND * 16;
-    static_assert(WR * WO == 4, "four waves per block");
-    static_assert(RND * (NS - 2) <= 12, "vmcnt budget");
-    __shared__ __attribute__((aligned(16))) uint32_t lds[NS][PROWS][64];
-
-    const uint32_t nb = gridDim.x;
-    const uint32_t xcd = blockIdx.x & 7u, local = blockIdx.x >> 3;
-    const uint32_t per = (nb + 7) >> 3;
-    const uint32_t full = nb - (per - 1) * 8;
-    const uint32_t logical = (xcd < full) ? xcd * per + local
-                                          : full * per + (xcd - full) * (per - 1) + local;
-    const uint32_t mt = logical % a.n_mt;
-    const uint32_t ot = (logical / a.n_mt) % a.n_ot;
-    const uint32_t kc = logical / (a.n_mt * a.n_ot);       // 64-slot chunk
-    const uint32_t chunks = a.N >> 6;
-    const uint32_t limb = kc / chunks;
-    const uint32_t slot0 = limb * a.N + (kc % chunks) * 64;
-    const LimbConst lc = a.lt.c[limb];
-    const uint32_t r32 = lc.r32;
-    const size_t LN = (size_t)a.L * a.N;
-    const uint32_t row0 = mt * MB, o0 = ot * OB;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t wr = wave / WO, wo = wave % WO;
-
-    // loader: in round rd thread tid copies 16 B of LDS row rd*16 + tid/16
-    const uint32_t *src[RND];
-    size_t stride[RND];
-#pragma unroll
-    for (int rd = 0; rd < RND; rd++) {
-        const uint32_t lr = rd * 16 + (tid >> 4);
-        const uint32_t col = (tid & 15) * 4;
-        if (lr < (uint32_t)MB) {
-            const uint32_t row = min(row0 + lr, a.rows - 1);
-            src[rd] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN + slot0 + col;
-            stride[rd] = 2 * LN;
-        } else {
-            const uint32_t o = min(o0 + min(lr - MB, (uint32_t)OB - 1), a.Co - 1);
-            src[rd] = a.w + (size_t)o * a.w_groups * LN + slot0 + col;
-            stride[rd] = LN;
-        }
-    }
-    auto issue = [&](int st, uint32_t g) {
-#pragma unroll
-        for (int rd = 0; rd < RND; rd++) {
-            const uint32_t *p = src[rd] + (size_t)g * stride[rd];
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)p,
-                                             (__attribute__((address_space(3))) void *)&lds[st][rd * 16 + wave * 4][0],
-                                             16, 0, 0);
-        }
-    };
-
-    uint64_t acc[MT][OT];
-#pragma unroll
-    for (int r = 0; r < MT; r++)
-#pragma unroll
-        for (int j = 0; j < OT; j++) acc[r][j] = 0;
-
-    const uint32_t g1 = a.n_groups;
-#pragma unroll
-    for (int i = 0; i < NS - 1; i++)
-        if ((uint32_t)i < g1) issue(i, i);
-    const uint32_t F = lc.fold;
-    uint32_t since = 0;
-    int st = 0;
-    for (uint32_t g = 0; g < g1; g++) {
-        // this thread's copies of group g have landed once at most the
-        // copies of the groups issued after it are outstanding
-        if (g + NS - 2 < g1) wait_vm(RND * (NS - 2));
-        else wait_vm(0);
-        // workgroup barrier without a fence: the copies this stage needs are
-        // complete per the wait above; later stages stay in flight
-        asm volatile("s_barrier" ::: "memory");
-        if (g + NS - 1 < g1) issue(st == 0 ? NS - 1 : st - 1, g + NS - 1);
-        uint32_t x[MT], w[OT];
-#pragma unroll
-        for (int r = 0; r < MT; r++) x[r] = lds[st][wr * MT + r][lane];
-#pragma unroll
-        for (int j = 0; j < OT; j++) w[j] = lds[st][MB + wo * OT + j][lane];
-#pragma unroll
-        for (int r = 0; r < MT; r++)
-#pragma unroll
-            for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
-        if (++since >= F) {
-            since = 0;
-#pragma unroll
-            for (int r = 0; r < MT; r++)
-#pragma unroll
-                for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
-        }
-        st = (st + 1 == NS) ? 0 : st + 1;
-    }
-
-    const uint32_t q = lc.q;
-    const uint32_t slot = slot0 + lane;
-    const uint32_t orow0 = row0 + wr * MT, oo0 = o0 + wo * OT;
-#pragma unroll
-    for (int r = 0; r < MT; r++) {
-        uint32_t y[OT];
-#pragma unroll
-        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
-        if (a.fuse) {
-#pragma unroll
-            for (int h = 1; h < OT; h <<= 1) {
-                if ((uint32_t)h >= a.c_n) break;
-#pragma unroll
-                for (int j = 0; j < OT; j++) {
-                    if (j & h) continue;
-                    const uint32_t u = y[j], v = y[j + h];
-                    y[j] = csub(u + v, q);
-                    y[j + h] = csub(u - v + q, q);
-                }
-            }
-        }
-        const uint32_t row = orow0 + r;
-        if (row >= a.rows) break;
-        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
-#pragma unroll
-        for (int j = 0; j < OT; j++)
-            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + slot] = y[j];
     }
 }
 
@@ -519,16 +325,9 @@ static hipError_t dispatch_mac(const MacArgs &a, const MacSched &t, hipStream_t 
     return hipErrorInvalidValue;
 }
 
-int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                uint32_t *out, int sched, bool per_channel, hipStream_t s) {
-    if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
-    if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
-    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
-    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
-    if (sched < 0) sched = default_sched(d);
-    if (sched < 0 || sched >= kNumScheds) return set_error(HYENA_EINVAL, "hyena_conv: unknown schedule");
+MacArgs conv_make_args(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
+                       uint32_t *out, int sched, bool per_channel, bool *needs_wht) {
     const MacSched &t = kScheds[sched];
-    if (!sched_valid(d, t)) return set_error(HYENA_EINVAL, "hyena_conv: schedule not valid for this layer");
     const uint32_t cn = d->c_n ? d->c_n : 1;
     MacArgs a{};
     a.ct = ct;
@@ -547,12 +346,52 @@ int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct
     a.lt = c->lt;
     const bool fuse_in_mac = cn > 1 && (uint32_t)t.ot >= cn && (uint32_t)t.ot % cn == 0;
     a.fuse = (per_channel && fuse_in_mac) ? 1 : 0;
+    if (t.lds) {
+        a.n_ot = (a.Co + t.wo * t.ot - 1) / (t.wo * t.ot);
+        a.n_mt = (a.rows + t.wr * t.mt - 1) / (t.wr * t.mt);
+        a.kchunks = a.N / 64;
+    } else {
+        a.n_ot = (a.Co + t.ot - 1) / t.ot;
+        a.n_mt = (a.rows + t.mt - 1) / t.mt;
+        a.kchunks = a.N / 256;
+    }
+    if (needs_wht) *needs_wht = cn > 1 && per_channel && !fuse_in_mac;
+    return a;
+}
+
+int conv_num_scheds() { return kNumScheds; }
+bool conv_sched_valid(const hyena_conv_desc *d, int sched) {
+    return sched >= 0 && sched < kNumScheds && sched_valid(d, kScheds[sched]);
+}
+int conv_default_sched(const hyena_conv_desc *d) { return default_sched(d); }
+int conv_sched_info(int sched, int *info) {
+    const MacSched &t = kScheds[sched];
+    info[0] = t.lds; info[1] = t.mt; info[2] = t.ot; info[3] = t.wr; info[4] = t.wo; info[5] = t.ns;
+    return HYENA_OK;
+}
+hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
+                           hipStream_t s) {
+    return launch_wht(c, cn, in, out, G, s);
+}
+
+int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
+                uint32_t *out, int sched, bool per_channel, hipStream_t s) {
+    if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
+    if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
+    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
+    if (sched < 0) sched = default_sched(d);
+    if (sched < 0 || sched >= kNumScheds) return set_error(HYENA_EINVAL, "hyena_conv: unknown schedule");
+    const MacSched &t = kScheds[sched];
+    if (!sched_valid(d, t)) return set_error(HYENA_EINVAL, "hyena_conv: schedule not valid for this layer");
+    bool wht = false;
+    const MacArgs a = conv_make_args(c, d, ct, w, out, sched, per_channel, &wht);
     hipError_t e = dispatch_mac(a, t, s);
     if (e == hipErrorInvalidValue) return set_error(HYENA_EINVAL, "hyena_conv: unsupported MAC schedule");
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
-    if (cn > 1 && per_channel && !fuse_in_mac) {
-        const size_t G = (size_t)a.rows / 2 * d->Co / cn;
-        e = launch_wht(c, cn, out, out, G, s);
+    if (wht) {
+        const size_t G = (size_t)a.rows / 2 * d->Co / a.c_n;
+        e = launch_wht(c, a.c_n, out, out, G, s);
         if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
     }
     return HYENA_OK;

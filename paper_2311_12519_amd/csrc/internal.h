@@ -8,6 +8,7 @@
 #include "hyena.h"
 
 #define HYENA_MAX_LIMBS 16
+#define HYENA_MAX_SEGS 48
 
 // Per-limb constants, passed to kernels by value.
 struct LimbConst {
@@ -33,6 +34,7 @@ struct hyena_ctx {
     std::vector<uint32_t> q, psi;
     LimbTable lt{};
     uint32_t fold_min = 1;   // minimum of lt.c[i].fold
+    bool lazy_ntt = false;   // every q_i < 2^30: NTT butterflies may run lazily
     // host twiddles (for the host-side NTT used by test-setup encryption)
     std::vector<uint32_t> h_fw, h_fws, h_iw, h_iws;  // [L][N]
     // device twiddles: forward psi powers in bit-reversed order with Shoup
@@ -67,3 +69,7 @@ void host_intt(const hyena_ctx *ctx, uint32_t limb, uint32_t *a);
 
 // launchers shared by translation units
 int launch_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, bool inverse, hipStream_t s);
+int launch_ntt_sched(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, int sched, hipStream_t s);
+int launch_ntt_segs(const hyena_ctx *c, uint32_t *const *ptrs, const size_t *P, uint32_t nseg, bool inv,
+                    int sched, hipStream_t s);
+int ntt_default_schedule(uint32_t logN);

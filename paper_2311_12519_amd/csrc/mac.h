@@ -1,0 +1,223 @@
+// Multiply-accumulate building blocks shared by the per-layer launches and
+// the persistent batched kernel (device code; included by conv.hip and
+// batch.hip only).
+#pragma once
+#include "internal.h"
+
+// Arguments of one layer's multiply-accumulate (also stored in device memory
+// as the per-layer table of the persistent kernel).
+struct MacArgs {
+    const uint32_t *ct;   // [rows/2][n_groups][2][L][N]
+    const uint32_t *w;    // [Co][w_groups][L][N]
+    uint32_t *out;        // [rows/2][Co][2][L][N]
+    uint32_t N, L, logN, Co, n_groups, w_groups, rows, ci, c_n;
+    uint32_t depthwise, fuse, n_ot, n_mt, kchunks;
+    LimbTable lt;
+};
+
+namespace {
+
+__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t q) { return min(x, x - q); }
+
+__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+    return csub(a * w - __umulhi(a, ws) * q, q);
+}
+
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
+    return (uint64_t)a * b + c;  // one v_mad_u64_u32
+}
+
+// Exact reduction of a 64-bit accumulator to [0, q).
+__device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
+    const uint32_t q = lc.q;
+    const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
+    // hi mod q: floor(hi * mu32 / 2^32) is floor(hi / q) or one less
+    const uint32_t hr = csub(hi - __umulhi(hi, lc.mu32) * q, q);
+    // y = hi * 2^32 + lo = hr * r32 + lo (mod q), y < q * 2^32
+    const uint64_t y = mad64(hr, lc.r32, lo);
+    // Montgomery REDC: z = y * 2^-32 mod q in [0, 2q)
+    const uint32_t m = (uint32_t)y * lc.qinv_neg;
+    const uint64_t t = mad64(m, q, y);
+    const uint32_t z = csub((uint32_t)(t >> 32), q);
+    // times 2^32 mod q
+    return shoup(z, lc.r32, lc.r32s, q);
+}
+
+__device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t r32) {
+    return mad64((uint32_t)(acc >> 32), r32, (uint32_t)acc);
+}
+
+
+
+
+// LDS-pipelined multiply-accumulate. A block of 256 threads (4 waves in a
+// WR x WO grid) owns 64 consecutive NTT slots of one limb (lane = slot) and a
+// tile of MB = WR*MT rows by OB = WO*OT outputs; wave (wr, wo) accumulates
+// rows [wr*MT, +MT) x outputs [wo*OT, +OT). For every input group g the MB
+// ciphertext rows and OB weight rows of the block (64 words each) are copied
+// global -> LDS with direct-to-LDS 16-byte loads, NS groups ahead of the
+// arithmetic, so each word is fetched once per block and the copies need no
+// registers. One barrier per group separates a stage's reads from its reuse.
+__device__ __forceinline__ void wait_vm(int n) {
+    // s_waitcnt with vmcnt = n (n <= 15 here), expcnt and lgkmcnt left at max
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+        case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+        case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+        case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+        case 4: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+        case 5: __builtin_amdgcn_s_waitcnt(0x0F75); break;
+        case 6: __builtin_amdgcn_s_waitcnt(0x0F76); break;
+        case 7: __builtin_amdgcn_s_waitcnt(0x0F77); break;
+        case 8: __builtin_amdgcn_s_waitcnt(0x0F78); break;
+        case 9: __builtin_amdgcn_s_waitcnt(0x0F79); break;
+        case 10: __builtin_amdgcn_s_waitcnt(0x0F7A); break;
+        case 11: __builtin_amdgcn_s_waitcnt(0x0F7B); break;
+        case 12: __builtin_amdgcn_s_waitcnt(0x0F7C); break;
+        default: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    }
+}
+
+template <int MT, int OT, int WR, int WO, int NS>
+struct MacLdsShape {
+    static constexpr int MB = WR * MT, OB = WO * OT;
+    static constexpr int ROWS = MB + OB;
+    static constexpr int RND = (ROWS + 15) / 16;   // loader rounds: 256 threads x 16 B = 16 rows
+    static constexpr int PROWS = RND * 16;
+    static constexpr int LDS_WORDS = NS * PROWS * 64;
+};
+
+// One logical block (64-slot chunk x row tile x output tile) of a layer.
+template <int MT, int OT, int WR, int WO, int NS>
+__device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical, uint32_t *lds_flat) {
+    using S = MacLdsShape<MT, OT, WR, WO, NS>;
+    constexpr int MB = S::MB, OB = S::OB, RND = S::RND, PROWS = S::PROWS;
+    static_assert(WR * WO == 4, "four waves per block");
+    static_assert(RND * (NS - 2) <= 12, "vmcnt budget");
+    uint32_t(*lds)[PROWS][64] = reinterpret_cast<uint32_t(*)[PROWS][64]>(lds_flat);
+    const uint32_t mt = logical % a.n_mt;
+    const uint32_t ot = (logical / a.n_mt) % a.n_ot;
+    const uint32_t kc = logical / (a.n_mt * a.n_ot);       // 64-slot chunk
+    const uint32_t chunks = a.N >> 6;
+    const uint32_t limb = kc / chunks;
+    const uint32_t slot0 = limb * a.N + (kc % chunks) * 64;
+    const LimbConst lc = a.lt.c[limb];
+    const uint32_t r32 = lc.r32;
+    const size_t LN = (size_t)a.L * a.N;
+    const uint32_t row0 = mt * MB, o0 = ot * OB;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t wr = wave / WO, wo = wave % WO;
+
+    // loader: in round rd thread tid copies 16 B of LDS row rd*16 + tid/16
+    const uint32_t *src[RND];
+    size_t stride[RND];
+#pragma unroll
+    for (int rd = 0; rd < RND; rd++) {
+        const uint32_t lr = rd * 16 + (tid >> 4);
+        const uint32_t col = (tid & 15) * 4;
+        if (lr < (uint32_t)MB) {
+            const uint32_t row = min(row0 + lr, a.rows - 1);
+            src[rd] = a.ct + ((size_t)(row >> 1) * a.n_groups * 2 + (row & 1)) * LN + slot0 + col;
+            stride[rd] = 2 * LN;
+        } else {
+            const uint32_t o = min(o0 + min(lr - MB, (uint32_t)OB - 1), a.Co - 1);
+            src[rd] = a.w + (size_t)o * a.w_groups * LN + slot0 + col;
+            stride[rd] = LN;
+        }
+    }
+    auto issue = [&](int st, uint32_t g) {
+#pragma unroll
+        for (int rd = 0; rd < RND; rd++) {
+            const uint32_t *p = src[rd] + (size_t)g * stride[rd];
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)p,
+                                             (__attribute__((address_space(3))) void *)&lds[st][rd * 16 + wave * 4][0],
+                                             16, 0, 0);
+        }
+    };
+
+    uint64_t acc[MT][OT];
+#pragma unroll
+    for (int r = 0; r < MT; r++)
+#pragma unroll
+        for (int j = 0; j < OT; j++) acc[r][j] = 0;
+
+    const uint32_t g1 = a.n_groups;
+#pragma unroll
+    for (int i = 0; i < NS - 1; i++)
+        if ((uint32_t)i < g1) issue(i, i);
+    const uint32_t F = lc.fold;
+    uint32_t since = 0;
+    int st = 0;
+    for (uint32_t g = 0; g < g1; g++) {
+        // this thread's copies of group g have landed once at most the
+        // copies of the groups issued after it are outstanding
+        if (g + NS - 2 < g1) wait_vm(RND * (NS - 2));
+        else wait_vm(0);
+        // workgroup barrier without a fence: the copies this stage needs are
+        // complete per the wait above; later stages stay in flight
+        asm volatile("s_barrier" ::: "memory");
+        if (g + NS - 1 < g1) issue(st == 0 ? NS - 1 : st - 1, g + NS - 1);
+        uint32_t x[MT], w[OT];
+#pragma unroll
+        for (int r = 0; r < MT; r++) x[r] = lds[st][wr * MT + r][lane];
+#pragma unroll
+        for (int j = 0; j < OT; j++) w[j] = lds[st][MB + wo * OT + j][lane];
+#pragma unroll
+        for (int r = 0; r < MT; r++)
+#pragma unroll
+            for (int j = 0; j < OT; j++) acc[r][j] = mad64(x[r], w[j], acc[r][j]);
+        if (++since >= F) {
+            since = 0;
+#pragma unroll
+            for (int r = 0; r < MT; r++)
+#pragma unroll
+                for (int j = 0; j < OT; j++) acc[r][j] = fold(acc[r][j], r32);
+        }
+        st = (st + 1 == NS) ? 0 : st + 1;
+    }
+
+    const uint32_t q = lc.q;
+    const uint32_t slot = slot0 + lane;
+    const uint32_t orow0 = row0 + wr * MT, oo0 = o0 + wo * OT;
+#pragma unroll
+    for (int r = 0; r < MT; r++) {
+        uint32_t y[OT];
+#pragma unroll
+        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
+        if (a.fuse) {
+#pragma unroll
+            for (int h = 1; h < OT; h <<= 1) {
+                if ((uint32_t)h >= a.c_n) break;
+#pragma unroll
+                for (int j = 0; j < OT; j++) {
+                    if (j & h) continue;
+                    const uint32_t u = y[j], v = y[j + h];
+                    y[j] = csub(u + v, q);
+                    y[j + h] = csub(u - v + q, q);
+                }
+            }
+        }
+        const uint32_t row = orow0 + r;
+        if (row >= a.rows) break;
+        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
+#pragma unroll
+        for (int j = 0; j < OT; j++)
+            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + slot] = y[j];
+    }
+}
+
+template <int MT, int OT, int WR, int WO, int NS>
+__global__ void __launch_bounds__(256) mac_lds_kernel(MacArgs a) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
+    // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous
+    // range of logical blocks so that the tiles of one slot chunk share an L2
+    const uint32_t nb = gridDim.x;
+    const uint32_t xcd = blockIdx.x & 7u, local = blockIdx.x >> 3;
+    const uint32_t per = (nb + 7) >> 3;
+    const uint32_t full = nb - (per - 1) * 8;
+    const uint32_t logical = (xcd < full) ? xcd * per + local
+                                          : full * per + (xcd - full) * (per - 1) + local;
+    mac_lds_block<MT, OT, WR, WO, NS>(a, logical, lds);
+}
+
+}  // namespace

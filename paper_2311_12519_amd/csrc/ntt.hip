@@ -29,22 +29,53 @@ __device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, u
     return csub(a * w - qh * q, q);
 }
 
-__device__ __forceinline__ uint32_t lds_idx(uint32_t j) { return j + (j >> 5); }
+// Shoup product left in [0, 2q) (no final correction).
+__device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
+    return a * w - __umulhi(a, ws) * q;
+}
 
-template <int LOGN>
-struct Sched;
-// pass widths (stages per pass); the first entry is the register radix
-template <> struct Sched<10> { static constexpr int LOGT = 6, NP = 3; static constexpr int e[3] = {4, 3, 3}; };
-template <> struct Sched<11> { static constexpr int LOGT = 7, NP = 3; static constexpr int e[3] = {4, 4, 3}; };
-template <> struct Sched<12> { static constexpr int LOGT = 8, NP = 3; static constexpr int e[3] = {4, 4, 4}; };
-template <> struct Sched<13> { static constexpr int LOGT = 8, NP = 3; static constexpr int e[3] = {5, 4, 4}; };
-template <> struct Sched<14> { static constexpr int LOGT = 9, NP = 3; static constexpr int e[3] = {5, 5, 4}; };
+// (lo, hi) -> (lo + w hi, lo - w hi). Exact variant (any q < 2^31): all values
+// stay canonical in [0, q). Lazy variant (Harvey's butterfly, q < 2^30):
+// values in [0, 4q) between stages.
+template <bool LAZY>
+__device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t ws, uint32_t q) {
+    if (LAZY) {
+        const uint32_t x = min(lo, lo - 2 * q);           // [0, 2q)
+        const uint32_t t = shoup_lazy(hi, w, ws, q);      // [0, 2q)
+        lo = x + t;                                       // [0, 4q)
+        hi = x - t + 2 * q;                               // (0, 4q)
+    } else {
+        const uint32_t t = shoup(hi, w, ws, q);
+        const uint32_t d = lo - t;
+        hi = min(d, d + q);       // lo - t wraps above 2q exactly when lo < t
+        lo = csub(lo + t, q);
+    }
+}
+
+// (lo, hi) -> (lo + hi, w (lo - hi)). Exact: canonical in and out. Lazy:
+// [0, 2q) in and out.
+template <bool LAZY>
+__device__ __forceinline__ void gs_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t ws, uint32_t q) {
+    if (LAZY) {
+        const uint32_t s = lo + hi;                       // [0, 4q)
+        const uint32_t t = lo - hi + 2 * q;               // (0, 4q)
+        lo = min(s, s - 2 * q);
+        hi = shoup_lazy(t, w, ws, q);
+    } else {
+        const uint32_t s = lo + hi;
+        const uint32_t d = lo - hi;
+        lo = csub(s, q);
+        hi = shoup(min(d, d + q), w, ws, q);
+    }
+}
+
+__device__ __forceinline__ uint32_t lds_idx(uint32_t j) { return j + (j >> 5); }
 
 // One pass of forward stages [s0, s0+e) on the thread's E registers.
 // Group gi of the pass holds indices b*(N>>s0) + o + r*(N>>(s0+e)), r < 2^e,
 // with o = gi mod (N>>(s0+e)), b = gi div (N>>(s0+e)); thread tid owns groups
 // gi = tid + k*T, k < E>>e, stored at registers x[k*2^e + r].
-template <int LOGN, int LOGT, int E_LOG, int S0, int EP>
+template <int LOGN, int LOGT, int E_LOG, int S0, int EP, bool LAZY>
 __device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint2 *__restrict__ tw,
                                          uint32_t q, uint32_t tid) {
     constexpr int GE = 1 << EP;
@@ -53,7 +84,8 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint2 
 #pragma unroll
     for (int kg = 0; kg < NG; kg++) {
         const uint32_t gi = tid + (uint32_t)kg * (1u << LOGT);
-        const uint32_t b = gi / OSPAN;
+        // the first pass has one block (b = 0): its twiddles are uniform
+        const uint32_t b = (S0 == 0) ? 0u : gi / OSPAN;
 #pragma unroll
         for (int u = 0; u < EP; u++) {
             const int half = GE >> (u + 1);
@@ -62,12 +94,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint2 
                 if (r & half) continue;
                 const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
                 const uint2 w = tw[widx];
-                uint32_t &lo = x[kg * GE + r];
-                uint32_t &hi = x[kg * GE + r + half];
-                const uint32_t t = shoup(hi, w.x, w.y, q);
-                const uint32_t s = lo + t;
-                hi = csub(lo - t + q, q);
-                lo = csub(s, q);
+                ct_bfly<LAZY>(x[kg * GE + r], x[kg * GE + r + half], w.x, w.y, q);
             }
         }
     }
@@ -101,37 +128,46 @@ __device__ __forceinline__ void from_lds(uint32_t (&x)[1 << E_LOG], const uint32
     }
 }
 
-template <int LOGN>
-__global__ void __launch_bounds__(1 << Sched<LOGN>::LOGT)
-ntt_fwd_kernel(uint32_t *__restrict__ poly, const uint2 *__restrict__ tw_all, LimbTable lt, uint32_t L) {
-    constexpr int LOGT = Sched<LOGN>::LOGT;
+// Forward transform of one limb-polynomial a (N residues) by the block:
+// passes of E0, E1, E2 (, E3) stages; E0 = LOGN - LOGT is the register radix
+// (every thread holds 2^E0 residues).
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint2 *__restrict__ tw,
+                                             uint32_t q, uint32_t *lds) {
     constexpr int E_LOG = LOGN - LOGT;
-    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << E_LOG;
-    constexpr int E0 = Sched<LOGN>::e[0], E1 = Sched<LOGN>::e[1], E2 = Sched<LOGN>::e[2];
-    static_assert(E0 + E1 + E2 == LOGN, "schedule must cover every stage");
-    static_assert(E0 == E_LOG, "first pass uses the full register radix");
-    __shared__ uint32_t lds[N + N / 32];
+    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
+    static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
+    static_assert(E0 == E_LOG && E1 <= E_LOG && E2 <= E_LOG && E3 <= E_LOG, "pass wider than the registers");
     const uint32_t tid = threadIdx.x;
-    const uint32_t limb = blockIdx.x % L;
-    uint32_t *a = poly + (size_t)blockIdx.x * N;
-    const uint2 *tw = tw_all + (size_t)limb * N;
-    const uint32_t q = lt.c[limb].q;
     uint32_t x[E];
     // pass 0: stages [0, E0); group of thread tid: indices tid + r*T
 #pragma unroll
     for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
-    fwd_pass<LOGN, LOGT, E_LOG, 0, E0>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, 0, E0, LAZY>(x, tw, q, tid);
     to_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
-    fwd_pass<LOGN, LOGT, E_LOG, E0, E1>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, E0, E1, LAZY>(x, tw, q, tid);
     __syncthreads();
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-    fwd_pass<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, LAZY>(x, tw, q, tid);
+    if constexpr (E3 > 0) {
+        __syncthreads();
+        to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
+        __syncthreads();
+        from_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
+        fwd_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, LAZY>(x, tw, q, tid);
+    }
+    if (LAZY) {
+#pragma unroll
+        for (int r = 0; r < E; r++) x[r] = csub(min(x[r], x[r] - 2 * q), q);  // [0, 4q) -> [0, q)
+    }
+    constexpr int SL = E3 > 0 ? E0 + E1 + E2 : E0 + E1;
+    constexpr int EL = E3 > 0 ? E3 : E2;
     __syncthreads();
-    to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
+    to_lds<LOGN, LOGT, E_LOG, SL, EL>(x, lds, tid);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; r++) a[tid + r * T] = lds[lds_idx(tid + r * T)];
@@ -141,7 +177,7 @@ ntt_fwd_kernel(uint32_t *__restrict__ poly, const uint2 *__restrict__ tw_all, Li
 // ones (len = 1, 2, ..., N/2). Stage with m = 2^s blocks (s from LOGN-1 down
 // to 0) pairs j and j + (N >> (s+1)) in block j >> (LOGN - s) with twiddle
 // psi^-brv(m + block). Passes are the forward passes taken in reverse.
-template <int LOGN, int LOGT, int E_LOG, int S0, int EP, bool LAST>
+template <int LOGN, int LOGT, int E_LOG, int S0, int EP, bool LAST, bool LAZY>
 __device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint2 *__restrict__ tw,
                                          const LimbConst &lc, uint32_t tid) {
     constexpr int GE = 1 << EP;
@@ -151,93 +187,206 @@ __device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint2 
 #pragma unroll
     for (int kg = 0; kg < NG; kg++) {
         const uint32_t gi = tid + (uint32_t)kg * (1u << LOGT);
-        const uint32_t b = gi / OSPAN;
+        const uint32_t b = (S0 == 0) ? 0u : gi / OSPAN;
 #pragma unroll
         for (int u = EP - 1; u >= 0; u--) {
             const int half = GE >> (u + 1);
 #pragma unroll
             for (int r = 0; r < GE; r++) {
                 if (r & half) continue;
-                const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
-                const uint2 w = tw[widx];
                 uint32_t &lo = x[kg * GE + r];
                 uint32_t &hi = x[kg * GE + r + half];
-                const uint32_t s = csub(lo + hi, q);
-                const uint32_t d = csub(lo - hi + q, q);
                 if (LAST && S0 + u == 0) {
-                    // last stage: fold N^{-1} into both outputs
-                    (void)w;
-                    lo = shoup(s, lc.ninv, lc.ninvs, q);
-                    hi = shoup(d, lc.w1n, lc.w1ns, q);
+                    // last stage (one block, twiddle psi^-brv(1)): fold N^{-1}
+                    // into both outputs and leave them canonical
+                    const uint32_t s = lo + hi;
+                    const uint32_t d = LAZY ? lo - hi + 2 * q : lo - hi;
+                    const uint32_t dd = LAZY ? d : min(d, d + q);
+                    lo = shoup(LAZY ? s : csub(s, q), lc.ninv, lc.ninvs, q);
+                    hi = shoup(dd, lc.w1n, lc.w1ns, q);
                 } else {
-                    lo = s;
-                    hi = shoup(d, w.x, w.y, q);
+                    const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
+                    const uint2 w = tw[widx];
+                    gs_bfly<LAZY>(lo, hi, w.x, w.y, q);
                 }
             }
         }
     }
 }
 
-template <int LOGN>
-__global__ void __launch_bounds__(1 << Sched<LOGN>::LOGT)
-ntt_inv_kernel(uint32_t *__restrict__ poly, const uint2 *__restrict__ tw_all, LimbTable lt, uint32_t L) {
-    constexpr int LOGT = Sched<LOGN>::LOGT;
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uint2 *__restrict__ tw,
+                                             const LimbConst &lc, uint32_t *lds) {
     constexpr int E_LOG = LOGN - LOGT;
-    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << E_LOG;
-    constexpr int E0 = Sched<LOGN>::e[0], E1 = Sched<LOGN>::e[1], E2 = Sched<LOGN>::e[2];
-    __shared__ uint32_t lds[N + N / 32];
+    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
+    static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
     const uint32_t tid = threadIdx.x;
-    const uint32_t limb = blockIdx.x % L;
-    uint32_t *a = poly + (size_t)blockIdx.x * N;
-    const uint2 *tw = tw_all + (size_t)limb * N;
-    const LimbConst lc = lt.c[limb];
     uint32_t x[E];
 #pragma unroll
     for (int r = 0; r < E; r++) lds[lds_idx(tid + r * T)] = a[tid + r * T];
     __syncthreads();
+    if constexpr (E3 > 0) {
+        from_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
+        inv_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, false, LAZY>(x, tw, lc, tid);
+        __syncthreads();
+        to_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
+        __syncthreads();
+    }
     from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-    inv_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, false>(x, tw, lc, tid);
+    inv_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, false, LAZY>(x, tw, lc, tid);
     __syncthreads();
     to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
-    inv_pass<LOGN, LOGT, E_LOG, E0, E1, false>(x, tw, lc, tid);
+    inv_pass<LOGN, LOGT, E_LOG, E0, E1, false, LAZY>(x, tw, lc, tid);
     __syncthreads();
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
-    inv_pass<LOGN, LOGT, E_LOG, 0, E0, true>(x, tw, lc, tid);
+    inv_pass<LOGN, LOGT, E_LOG, 0, E0, true, LAZY>(x, tw, lc, tid);
 #pragma unroll
     for (int r = 0; r < E; r++) a[tid + r * T] = x[r];
 }
 
-template <int LOGN>
-hipError_t launch(uint32_t *d, size_t P, const hyena_ctx *c, bool inv, hipStream_t s) {
-    const dim3 grid((unsigned)(P * c->L)), block(1u << Sched<LOGN>::LOGT);
-    if (inv)
-        hipLaunchKernelGGL(ntt_inv_kernel<LOGN>, grid, block, 0, s, d, (const uint2 *)c->d_iw, c->lt, c->L);
-    else
-        hipLaunchKernelGGL(ntt_fwd_kernel<LOGN>, grid, block, 0, s, d, (const uint2 *)c->d_fw, c->lt, c->L);
+// Polynomial p of a launch: a contiguous [P][L][N] array (segments == 1) or
+// the concatenation of several such arrays (one per layer of a batch).
+struct NttSegs {
+    uint32_t *ptr[HYENA_MAX_SEGS];
+    uint32_t first[HYENA_MAX_SEGS + 1];  // prefix sums of limb-polynomial counts
+    uint32_t n;
+};
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY, bool INV>
+__global__ void __launch_bounds__(1 << LOGT)
+ntt_kernel(NttSegs sg, const uint2 *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN;
+    __shared__ uint32_t lds[N + N / 32];
+    // blocks of one segment hold limb-polynomials in [P][L][N] order; every
+    // segment starts at limb 0, so the limb is the block's index within it mod L
+    uint32_t s = 0;
+    while (s + 1 < sg.n && blockIdx.x >= sg.first[s + 1]) s++;
+    const uint32_t local = blockIdx.x - sg.first[s];
+    uint32_t *a = sg.ptr[s] + (size_t)local * N;
+    const uint32_t limb = local % L;
+    const uint2 *tw = tw_all + (size_t)limb * N;
+    if (INV) ntt_inv_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb], lds);
+    else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lds);
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_sched(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
+    const dim3 grid(sg.first[sg.n]), block(1u << LOGT);
+    const uint2 *tw = (const uint2 *)(inv ? c->d_iw : c->d_fw);
+    if (c->lazy_ntt) {  // Harvey's lazy butterflies need 4q < 2^32
+        if (inv) hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, true, true>), grid, block, 0, s, sg, tw, c->lt, c->L);
+        else hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, true, false>), grid, block, 0, s, sg, tw, c->lt, c->L);
+    } else {
+        if (inv) hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, false, true>), grid, block, 0, s, sg, tw, c->lt, c->L);
+        else hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, false, false>), grid, block, 0, s, sg, tw, c->lt, c->L);
+    }
     return hipGetLastError();
+}
+
+// NTT schedules per ring degree: threads per polynomial and stages per pass.
+struct NttSched {
+    int logn, logt, e0, e1, e2, e3;
+};
+const NttSched kNtt[] = {
+    {10, 6, 4, 3, 3, 0},
+    {11, 7, 4, 4, 3, 0},
+    {12, 8, 4, 4, 4, 0}, {12, 7, 5, 5, 2, 0}, {12, 6, 6, 3, 3, 0},
+    {13, 8, 5, 4, 4, 0}, {13, 9, 4, 4, 4, 1}, {13, 7, 6, 6, 1, 0},
+    {14, 9, 5, 5, 4, 0}, {14, 10, 4, 4, 4, 2}, {14, 8, 6, 6, 2, 0},
+};
+const int kNumNtt = sizeof(kNtt) / sizeof(kNtt[0]);
+
+hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hipStream_t s) {
+    switch (i) {
+        case 0: return launch_sched<10, 6, 4, 3, 3, 0>(d, c, inv, s);
+        case 1: return launch_sched<11, 7, 4, 4, 3, 0>(d, c, inv, s);
+        case 2: return launch_sched<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 3: return launch_sched<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 4: return launch_sched<12, 6, 6, 3, 3, 0>(d, c, inv, s);
+        case 5: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 6: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 7: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
+        case 8: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 9: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 10: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-int launch_ntt(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, hipStream_t s) {
-    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
-    if (P == 0) return HYENA_OK;
-    if (P * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
-    hipError_t e;
-    switch (c->logN) {
-        case 10: e = launch<10>(d, P, c, inv, s); break;
-        case 11: e = launch<11>(d, P, c, inv, s); break;
-        case 12: e = launch<12>(d, P, c, inv, s); break;
-        case 13: e = launch<13>(d, P, c, inv, s); break;
-        case 14: e = launch<14>(d, P, c, inv, s); break;
-        default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
+int ntt_default_schedule(uint32_t logN) {
+    switch (logN) {
+        case 10: return 0;
+        case 11: return 1;
+        case 12: return 2;
+        case 13: return 5;
+        case 14: return 9;
+        default: return -1;
     }
-    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
+}
+
+int launch_ntt_segs(const hyena_ctx *c, uint32_t *const *ptrs, const size_t *P, uint32_t nseg, bool inv,
+                    int sched, hipStream_t s) {
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
+    if (sched < 0) sched = ntt_default_schedule(c->logN);
+    if (sched < 0 || sched >= kNumNtt || kNtt[sched].logn != (int)c->logN)
+        return set_error(HYENA_EINVAL, "hyena_ntt: schedule does not exist for this N");
+    // launches of at most HYENA_MAX_SEGS segments and 2^31 blocks each
+    uint32_t i = 0;
+    while (i < nseg) {
+        NttSegs sg{};
+        uint64_t total = 0;
+        while (i < nseg && sg.n < HYENA_MAX_SEGS) {
+            const uint64_t blocks = (uint64_t)P[i] * c->L;
+            if (blocks == 0) { i++; continue; }
+            if (total + blocks > 0x7fffffffull) {
+                if (sg.n == 0) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
+                break;
+            }
+            if (!ptrs[i]) return set_error(HYENA_EINVAL, "hyena_ntt: NULL polynomial array");
+            sg.ptr[sg.n] = ptrs[i];
+            sg.first[sg.n] = (uint32_t)total;
+            total += blocks;
+            sg.n++;
+            i++;
+        }
+        if (sg.n == 0) break;
+        sg.first[sg.n] = (uint32_t)total;
+        const hipError_t e = launch_idx(sched, sg, c, inv, s);
+        if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
+    }
     return HYENA_OK;
+}
+
+int launch_ntt_sched(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, int sched, hipStream_t s) {
+    return launch_ntt_segs(c, &d, &P, 1, inv, sched, s);
+}
+
+int launch_ntt(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, hipStream_t s) {
+    return launch_ntt_sched(c, d, P, inv, -1, s);
+}
+
+extern "C" int hyena_ntt_schedules(uint32_t N, int *first, int *count) {
+    int f = -1, n = 0;
+    for (int i = 0; i < kNumNtt; i++)
+        if ((1u << kNtt[i].logn) == N) {
+            if (f < 0) f = i;
+            n++;
+        }
+    if (first) *first = f;
+    if (count) *count = n;
+    return n ? HYENA_OK : set_error(HYENA_EUNSUPPORTED, "hyena_ntt_schedules: unsupported N");
+}
+
+extern "C" int hyena_ntt_sched(const hyena_ctx *c, uint32_t *d_poly, size_t P, int inverse, int sched,
+                               hyena_stream_t s) {
+    if (!c || (P && !d_poly)) return set_error(HYENA_EINVAL, "hyena_ntt_sched: NULL argument");
+    return launch_ntt_sched(c, d_poly, P, inverse != 0, sched, (hipStream_t)s);
 }
 
 extern "C" int hyena_ntt(const hyena_ctx *c, uint32_t *d_poly, size_t P, hyena_stream_t s) {

@@ -107,6 +107,9 @@ static void build_tables(hyena_ctx *c) {
         unsigned __int128 f = room / ((unsigned __int128)(q - 1) * (q - 1));
         lc.fold = (uint32_t)(f > 15 ? 15 : (f < 1 ? 1 : f));
     }
+    c->lazy_ntt = true;
+    for (uint32_t i = 0; i < c->L; i++)
+        if (c->q[i] >= (1u << 30)) c->lazy_ntt = false;
     c->fold_min = 15;
     for (uint32_t i = 0; i < c->L; i++)
         if (c->lt.c[i].fold < c->fold_min) c->fold_min = c->lt.c[i].fold;

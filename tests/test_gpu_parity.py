@@ -53,7 +53,8 @@ def ctx_for(N, L, bits):
 
 # ---------------------------------------------------------------- NTT
 
-@pytest.mark.parametrize("N,L,bits", [(1024, 2, 31), (2048, 2, 31), (4096, 2, 30), (8192, 3, 31), (16384, 4, 31)])
+@pytest.mark.parametrize("N,L,bits", [(1024, 2, 31), (2048, 2, 31), (4096, 2, 30), (8192, 3, 31), (16384, 4, 31),
+                                     (8192, 3, 30), (16384, 2, 30)])
 def test_ntt_matches_oracle(dev, N, L, bits):
     say(f"ntt N={N} L={L}")
     ctx = ctx_for(N, L, bits)
@@ -71,7 +72,7 @@ def test_ntt_matches_oracle(dev, N, L, bits):
     assert np.array_equal(from_dev(d), a)
 
 
-@pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (16384, 4, 31)])
+@pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (16384, 4, 31), (8192, 3, 30)])
 def test_intt_matches_oracle(dev, N, L, bits):
     say(f"intt N={N}")
     ctx = ctx_for(N, L, bits)
@@ -213,6 +214,7 @@ VARIANTS = [
     ("batch3_cn2", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 16, 3), 2, 3, True, 0),
     ("ci_lowered", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 8, 3), 1, 1, True, 5),
     ("cn32_unfusable", (8192, 3, 31), wl.Layer("t", 14, 14, 32, 32, 3), 32, 1, True, 0),
+    ("primes30_batch8", (8192, 3, 30), wl.Layer("t", 28, 28, 64, 32, 3), 1, 8, True, 0),
 ]
 
 
@@ -288,3 +290,19 @@ def test_every_mac_schedule_matches_oracle(dev, lay, c_n, batch):
             assert np.array_equal(got[b], want[b]), (sid, info, b)
         ran += 1
     assert ran >= (4 if lay.depthwise else len(hy.hyena_conv_schedules()))
+
+
+@pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (8192, 2, 30), (16384, 2, 31)])
+def test_every_ntt_schedule_matches_oracle(dev, N, L, bits):
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N + bits)
+    a = rand_res(rng, (2, L, N), ctx.primes)
+    want = [orc.ntt(a[1, i], q, ctx.psi[i]) for i, q in enumerate(ctx.primes)]
+    for sid in hy.hyena_ntt_schedules(N):
+        d = to_dev(a)
+        hy.hyena_ntt_sched(ctx, d, False, sid)
+        got = from_dev(d)
+        for i in range(L):
+            assert np.array_equal(got[1, i], want[i]), (sid, i)
+        hy.hyena_ntt_sched(ctx, d, True, sid)
+        assert np.array_equal(from_dev(d), a), sid
