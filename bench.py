@@ -13,12 +13,22 @@ weight preparation). Inputs are uniform residues drawn on the GPU from a
 seeded generator (distributed as fresh ciphertexts), resident in HBM before
 the timed region.
 
-Two schedules of the same arithmetic are timed:
-  plain   - per image and layer: ntt, conv, intt through the C ABI;
+Three schedules of the same arithmetic are timed:
+  plain   - per image and layer: ntt, conv, intt through the C ABI with the
+            default kernel schedules;
   batched - per layer, all 8 images in one launch of each kernel, so each
-            encoded-weight word is read once per batch instead of per image.
-Before timing, one step is checked against the oracle on sampled output
-ciphertexts (every coefficient of both parts and all limbs).
+            encoded-weight word is read once per batch instead of per image;
+  tuned   - the batched path object: NTT schedule per direction and MAC
+            schedule per layer picked by the autotuner, every layer's
+            multiply-accumulate in one persistent launch, the whole step
+            captured in a hipGraph and replayed. Phase durations come from HIP
+            events recorded inside the graph.
+Before timing, one step of each schedule is checked against the oracle on
+sampled output ciphertexts (every coefficient of both parts and all limbs).
+`value` is the tuned schedule's throughput.
+
+`--copy-calibration` instead times a plain 1 GiB device copy (the reference
+kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters).
 
 Prints one JSON line (rank 0, N=1 GPU).
 """
@@ -51,7 +61,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--images", type=int, default=8)
     ap.add_argument("--layers", type=int, default=13, help="first n VGG layers (13 = all)")
-    ap.add_argument("--mode", choices=["both", "batched", "plain"], default="both")
+    ap.add_argument("--mode", choices=["all", "plain", "batched", "tuned"], default="all")
+    ap.add_argument("--primes", type=int, choices=[30, 31], default=31,
+                    help="RNS primes below 2^31 (default) or below 2^30")
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -75,7 +88,7 @@ def lazy_fold_interval(primes):
 
 def setup(args, hy, wl, torch):
     N, L = 8192, 3
-    ctx = hy.hyena_create(N, L)
+    ctx = hy.hyena_create(N, L, flags=hy.HYENA_PRIMES_30BIT if args.primes == 30 else 0)
     layers = []
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
@@ -157,12 +170,14 @@ class Events:
         return out
 
 
-def check(ctx, layers, hy, orc, torch, images):
-    """One batched step from pristine inputs; sampled outputs vs the oracle."""
+def check(ctx, layers, orc, torch, images, step):
+    """One step from pristine inputs; sampled outputs vs the oracle."""
     N, L = ctx.N, ctx.L
     for o in layers:
         o.ct.copy_(o.ct0)
-    step_batched(ctx, layers, hy)
+        o.out.fill_(0)
+    torch.cuda.synchronize()
+    step()
     torch.cuda.synchronize()
     checked = 0
     for li, o in enumerate(layers):
@@ -211,6 +226,21 @@ def cpu_baseline(ctx, layers, orc, seconds):
                       f"{sorted(set(names))}, {spent:.1f} s"}
 
 
+def copy_calibration(args, torch):
+    n = 1 << 28  # 1 GiB of int32
+    a = torch.randint(0, 1 << 30, (n,), dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": dt * 1e3,
+                      "GBs": 2 * n * 4 / dt / 1e9}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,44 +252,68 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        copy_calibration(args, torch)
+        return
     hy.lib()
     log("setup ...")
     ctx, layers = setup(args, hy, wl, torch)
     n_img = args.images
     total_macs = sum(o.macs for o in layers) * n_img
     n_layer_runs = len(layers) * n_img
+    orc = None
+    if not args.no_check or not args.no_cpu_baseline:
+        import oracle as orc
 
+    modes = ["plain", "batched", "tuned"] if args.mode == "all" else [args.mode]
+    batch = None
+    if "tuned" in modes:
+        log("autotuning + graph capture ...")
+        flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING
+        batch = hy.hyena_batch_create(ctx, [(o.desc_b, o.ct, o.d_wn, o.out) for o in layers], flags)
+
+    steps = {
+        "plain": lambda: step_plain(ctx, layers, hy, n_img),
+        "batched": lambda: step_batched(ctx, layers, hy),
+        "tuned": lambda: hy.hyena_batch_run(batch),
+    }
     checked = 0
     if not args.no_check:
-        import oracle as orc
-        log("parity check on sampled outputs ...")
-        checked = check(ctx, layers, hy, orc, torch, n_img)
-        log(f"parity ok: {checked} output ciphertexts bit-exact")
+        for mode in modes:
+            checked += check(ctx, layers, orc, torch, n_img, steps[mode])
+        log(f"parity ok: {checked} sampled output ciphertexts bit-exact across {modes}")
 
     res = {}
-    modes = ["plain", "batched"] if args.mode == "both" else [args.mode]
     for mode in modes:
-        fn = (lambda: step_batched(ctx, layers, hy)) if mode == "batched" else \
-             (lambda: step_plain(ctx, layers, hy, n_img))
+        fn = steps[mode]
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
         ev = Events(torch) if mode == "batched" else None
+        phases = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             if ev is not None:
                 step_batched(ctx, layers, hy, ev)
             else:
                 fn()
+            if mode == "tuned":
+                phases.append(hy.hyena_batch_phase_ms(batch))
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         res[mode] = {"ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt,
                      "layers_per_s": n_layer_runs / dt}
         if ev is not None:
             res[mode]["kernels_ms"] = {k: sum(v) / args.steps for k, v in ev.totals().items()}
+        if mode == "tuned":
+            ph = np.array(phases).mean(axis=0)
+            res[mode]["kernels_ms"] = {"ntt": float(ph[0]), "mac": float(ph[1]), "intt": float(ph[2])}
+            info = hy.hyena_batch_info(batch)
+            res[mode]["schedules"] = info
         log(f"{mode}: {dt * 1e3:.2f} ms/step, {total_macs / dt / 1e12:.3f} T coeff-MAC/s")
 
-    head = res.get("batched", res.get("plain"))
+    head_mode = "tuned" if "tuned" in res else ("batched" if "batched" in res else "plain")
+    head = res[head_mode]
     out = {
         "metric": "HE-conv coeff-MACs/s + layers/s at N=8192, batched/tuned vs plain; bit-exact",
         "value": head["coeff_macs_per_s"],
@@ -274,40 +328,38 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"VGG-16 {len(layers)} conv layers at 224x224, {n_img} images, "
-                               f"N=8192, 3 primes < 2^31, t=2^20, c_n=1",
-                   "images": n_img, "layers": len(layers), "N": 8192, "L": 3},
+                               f"N=8192, 3 primes < 2^{args.primes}, t=2^20, c_n=1",
+                   "images": n_img, "layers": len(layers), "N": 8192, "L": 3, "prime_bits": args.primes,
+                   "schedule": head_mode},
         "layers_per_s": head["layers_per_s"],
         "parity_checked_outputs": checked,
         "schedules": res,
     }
-    if "batched" in res and "plain" in res:
-        out["speedup_batched_vs_plain"] = res["plain"]["ms_per_step"] / res["batched"]["ms_per_step"]
-    if "batched" in res and "kernels_ms" in res["batched"]:
-        km = res["batched"]["kernels_ms"]
+    if "plain" in res:
+        for m in ("batched", "tuned"):
+            if m in res:
+                out[f"speedup_{m}_vs_plain"] = res["plain"]["ms_per_step"] / res[m]["ms_per_step"]
+    if "kernels_ms" in head:
+        km = head["kernels_ms"]
         mac_ms = km["mac"]
-        # algorithmic HBM bytes of the MAC launches: encoded weights once,
-        # input ciphertexts once, output ciphertexts once
         w_bytes = sum(o.d_wn.numel() * 4 for o in layers)
         io_bytes = sum((o.in_words + o.out_words) * 4 for o in layers) * n_img
         mac_gbs = (w_bytes + io_bytes) / (mac_ms * 1e-3) / 1e9
-        fold = lazy_fold_interval(ctx.primes)
-        instr = total_macs * (1 + 1 / fold)
-        out["roofline"] = {"bound": "alu", "kernel": "mac_kernel",
-                           "achieved": instr / (mac_ms * 1e-3) / 1e12,
-                           "peak": VALU_PEAK_TOPS, "unit": "T VALU-op/s",
-                           "frac": instr / (mac_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS,
-                           "traffic": None,
-                           "hbm_algorithmic_GBs": mac_gbs,
-                           "hbm_frac": mac_gbs / HBM_PEAK_GBS}
+        ach = total_macs / (mac_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu",
+                           "kernel": "mac_persistent_kernel" if head_mode == "tuned" else "mac_lds_kernel",
+                           "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (one v_mad_u64_u32 per coeff-MAC)",
+                           "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                           "launches_per_step": 1 if head_mode == "tuned" else len(layers),
+                           "hbm_algorithmic_GBs": mac_gbs, "hbm_frac": mac_gbs / HBM_PEAK_GBS}
         ntt_bytes = sum(o.in_words * 4 * 2 for o in layers) * n_img
         intt_bytes = sum(o.out_words * 4 * 2 for o in layers) * n_img
         out["kernels"] = {
             "ntt": {"ms": km["ntt"], "GBs": ntt_bytes / (km["ntt"] * 1e-3) / 1e9},
-            "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": total_macs / (mac_ms * 1e-3) / 1e12},
+            "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": ach},
             "intt": {"ms": km["intt"], "GBs": intt_bytes / (km["intt"] * 1e-3) / 1e9},
         }
     if not args.no_cpu_baseline:
-        import oracle as orc
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ctx, layers, orc, args.cpu_seconds)
     print(json.dumps(out))

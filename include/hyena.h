@@ -290,6 +290,9 @@ typedef struct hyena_batch hyena_batch;
 #define HYENA_BATCH_TUNE 0x4u       /* MAC schedule per layer and NTT schedule per direction chosen
                                        by timing; choices cached in the file named by the
                                        environment variable HYENA_TUNE_CACHE when set */
+#define HYENA_BATCH_TIMING 0x8u     /* record HIP events between the phases of every run for
+                                       hyena_batch_phase_ms (with HYENA_BATCH_GRAPH: one graph
+                                       per phase, events between their launches) */
 
 /*
  * Build a batched step over n_layers layers. Copies the descriptors and keeps
@@ -307,6 +310,10 @@ int hyena_batch_run(hyena_batch *b, hyena_stream_t stream);
  * step, n_layers, persistent launches, MAC schedule of layer 0, 1, ...};
  * entries beyond the end are -1. */
 int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info);
+/* Durations of the last run's phases in ms: ms[0] forward NTTs, ms[1]
+ * multiply-accumulate (incl. counter reset and unfused Walsh kernels), ms[2]
+ * inverse NTTs. Waits for the run. Needs HYENA_BATCH_TIMING. */
+int hyena_batch_phase_ms(const hyena_batch *b, float *ms);
 void hyena_batch_destroy(hyena_batch *b);
 
 #ifdef __cplusplus

@@ -33,6 +33,7 @@ HYENA_FUSE_WHT = 0x1
 HYENA_BATCH_PERSISTENT = 0x1
 HYENA_BATCH_GRAPH = 0x2
 HYENA_BATCH_TUNE = 0x4
+HYENA_BATCH_TIMING = 0x8
 
 _ERRNAMES = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOISE", -4: "EHIP", -5: "ENOMEM"}
 
@@ -112,6 +113,7 @@ def _register_extra(L):
         "hyena_batch_destroy": [_P],
         "hyena_batch_run": [_P, _P],
         "hyena_batch_info": [_P, _P, _sz],
+        "hyena_batch_phase_ms": [_P, _P],
         "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
         "hyena_conv_schedules": [_P],
         "hyena_conv_schedule_info": [ctypes.c_int, _P],
@@ -362,6 +364,12 @@ def hyena_batch_info(b: Batch) -> dict:
     nl = info[3]
     return {"ntt_fwd": info[0], "ntt_inv": info[1], "launches": info[2], "layers": nl,
             "persistent_launches": info[4], "mac_sched": [info[5 + i] for i in range(nl)]}
+
+
+def hyena_batch_phase_ms(b: Batch) -> list:
+    ms = (ctypes.c_float * 3)()
+    _check(lib().hyena_batch_phase_ms(b.handle, ms))
+    return [ms[0], ms[1], ms[2]]
 
 
 def hyena_batch_destroy(b: Batch) -> None:

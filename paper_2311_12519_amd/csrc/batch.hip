@@ -38,41 +38,40 @@ hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, 
 
 namespace {
 
+// Thread 0 draws the next work item: its own XCD's queue first, then the
+// other queues in turn; `total` once every queue is exhausted.
+__device__ __forceinline__ uint32_t draw_item(uint32_t *counters, uint32_t total, uint32_t &qi) {
+    for (int tries = 0; tries < 8; tries++) {
+        const uint32_t lo = (uint32_t)(((uint64_t)total * qi) >> 3);
+        const uint32_t hi = (uint32_t)(((uint64_t)total * (qi + 1)) >> 3);
+        const uint32_t k = atomicAdd(&counters[qi], 1u);
+        if (lo + k < hi) return lo + k;
+        qi = (qi + 1) & 7u;
+    }
+    return total;
+}
+
+// three resident blocks per CU (at most 168 VGPRs), as the per-layer kernel
 template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 3)
 mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
                       uint32_t *__restrict__ counters, uint32_t total) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
-    __shared__ uint32_t item_s, layer_s;
-    const uint32_t home = blockIdx.x & 7u;
-    uint32_t qi = home;  // queue currently drawn from (thread 0 only)
-    for (;;) {
-        if (threadIdx.x == 0) {
-            uint32_t it = total;
-            for (int tries = 0; tries < 8; tries++) {
-                const uint32_t lo = (uint32_t)(((uint64_t)total * qi) >> 3);
-                const uint32_t hi = (uint32_t)(((uint64_t)total * (qi + 1)) >> 3);
-                const uint32_t k = atomicAdd(&counters[qi], 1u);
-                if (lo + k < hi) {
-                    it = lo + k;
-                    break;
-                }
-                qi = (qi + 1) & 7u;
-            }
-            uint32_t l = 0;
-            if (it < total)
-                while (l + 1 < n_layers && it >= first[l + 1]) l++;
-            item_s = it;
-            layer_s = l;
-        }
-        __syncthreads();
+    __shared__ uint32_t item_s[2];
+    uint32_t qi = blockIdx.x & 7u;  // queue drawn from (thread 0 only)
+    if (threadIdx.x == 0) item_s[0] = draw_item(counters, total, qi);
+    __syncthreads();
+    for (uint32_t round = 0;; round ^= 1) {
         // uniform across the block: lets the layer's arguments load as scalars
-        const uint32_t it = __builtin_amdgcn_readfirstlane(item_s);
-        const uint32_t l = __builtin_amdgcn_readfirstlane(layer_s);
-        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(item_s[round]);
         if (it >= total) break;
+        // draw the following item now; its latency hides behind this one
+        if (threadIdx.x == 0) item_s[round ^ 1] = draw_item(counters, total, qi);
+        uint32_t l = 0;
+        while (l + 1 < n_layers && it >= first[l + 1]) l++;
+        l = __builtin_amdgcn_readfirstlane(l);
         mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds);
-        __syncthreads();
+        __syncthreads();  // LDS stages and item_s[round ^ 1] ready for the next round
     }
 }
 
@@ -152,29 +151,22 @@ struct hyena_batch {
         uint32_t grid = 0;
     };
     std::vector<Group> groups;
+    int per_cu = 0;  // persistent blocks per CU
     std::vector<uint32_t> solo;   // layers launched on their own
     uint32_t *d_counters = nullptr;
     uint32_t n_counters = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one graph for the whole step, or one per phase when timing (events
+    // between graph launches; event nodes inside a graph cannot be timed)
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     int launches = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // phase boundaries (HYENA_BATCH_TIMING)
 };
 
-static int issue_step(hyena_batch *b, hipStream_t s) {
+// Enqueue phase `phase` of a step (0: forward NTTs, 1: multiply-accumulate,
+// 2: inverse NTTs) or all of them (phase < 0).
+static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
     const hyena_ctx *c = b->ctx;
-    std::vector<uint32_t *> in_ptrs, out_ptrs;
-    std::vector<size_t> in_P, out_P;
-    for (size_t l = 0; l < b->io.size(); l++) {
-        const hyena_conv_desc &d = b->desc[l];
-        in_ptrs.push_back(b->io[l].d_ct);
-        in_P.push_back((size_t)d.batch * d.n_in * 2);
-        out_ptrs.push_back(b->io[l].d_out);
-        out_P.push_back((size_t)d.batch * d.n_out * 2);
-    }
-    int launches = 0;
-    int rc = launch_ntt_segs(c, in_ptrs.data(), in_P.data(), (uint32_t)in_ptrs.size(), false, b->ntt_fwd, s);
-    if (rc) return rc;
-    launches += (int)((in_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
     if (b->n_counters) {
         hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, b->d_counters, b->n_counters);
         launches++;
@@ -200,17 +192,46 @@ static int issue_step(hyena_batch *b, hipStream_t s) {
             }
         }
     }
-    hipError_t e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_batch_run: ") + hipGetErrorString(e));
     for (uint32_t l : b->solo) {
-        rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, b->mac_sched[l], true, s);
+        const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, b->mac_sched[l],
+                                   true, s);
         if (rc) return rc;
         launches++;
     }
-    rc = launch_ntt_segs(c, out_ptrs.data(), out_P.data(), (uint32_t)out_ptrs.size(), true, b->ntt_inv, s);
-    if (rc) return rc;
-    launches += (int)((out_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
-    b->launches = launches;
+    return HYENA_OK;
+}
+
+static int issue_step(hyena_batch *b, hipStream_t s, int phase = -1) {
+    const hyena_ctx *c = b->ctx;
+    std::vector<uint32_t *> in_ptrs, out_ptrs;
+    std::vector<size_t> in_P, out_P;
+    for (size_t l = 0; l < b->io.size(); l++) {
+        const hyena_conv_desc &d = b->desc[l];
+        in_ptrs.push_back(b->io[l].d_ct);
+        in_P.push_back((size_t)d.batch * d.n_in * 2);
+        out_ptrs.push_back(b->io[l].d_out);
+        out_P.push_back((size_t)d.batch * d.n_out * 2);
+    }
+    int launches = 0, rc = HYENA_OK;
+    if (phase < 0 || phase == 0) {
+        rc = launch_ntt_segs(c, in_ptrs.data(), in_P.data(), (uint32_t)in_ptrs.size(), false, b->ntt_fwd, s);
+        if (rc) return rc;
+        launches += (int)((in_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
+    }
+    if (phase < 0 || phase == 1) {
+        rc = issue_mac_phase(b, s, launches);
+        if (rc) return rc;
+    }
+    if (phase < 0 || phase == 2) {
+        rc = launch_ntt_segs(c, out_ptrs.data(), out_P.data(), (uint32_t)out_ptrs.size(), true, b->ntt_inv, s);
+        if (rc) return rc;
+        launches += (int)((out_ptrs.size() + HYENA_MAX_SEGS - 1) / HYENA_MAX_SEGS);
+    }
+    // launches per step (summed over the three phase calls when run phase by phase)
+    if (phase <= 0) b->launches = launches;
+    else b->launches += launches;
     return HYENA_OK;
 }
 
@@ -252,14 +273,18 @@ static int tune(hyena_batch *b) {
     hipStream_t s;
     HIP_TRY(hipStreamCreate(&s));
     const int ns = conv_num_scheds();
+    const bool persistent = (b->flags & HYENA_BATCH_PERSISTENT) != 0;
+    std::vector<std::vector<float>> times(b->desc.size(), std::vector<float>(ns, -1.f));
+    bool all_cached = true;
     for (size_t l = 0; l < b->desc.size(); l++) {
         const hyena_conv_desc &d = b->desc[l];
-        const std::string key = layer_key(c, arch, d);
+        const std::string key = layer_key(c, arch, d) + (persistent ? "|persistent" : "");
         auto it = cache.find(key);
         if (it != cache.end() && it->second >= 0 && it->second < ns && conv_sched_valid(&d, it->second)) {
             b->mac_sched[l] = it->second;
             continue;
         }
+        all_cached = false;
         float best = 1e30f;
         int best_s = conv_default_sched(&d);
         for (int sid = 0; sid < ns; sid++) {
@@ -272,15 +297,45 @@ static int tune(hyena_batch *b) {
                 if (!rc) rc = conv_launch(c, &d, b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, sid, true, s);
             });
             if (rc) continue;
+            times[l][sid] = ms;
             if (ms < best) {
                 best = ms;
                 best_s = sid;
             }
         }
         b->mac_sched[l] = best_s;
-        cache[key] = best_s;
         dirty = true;
     }
+    if (persistent && !all_cached) {
+        // one persistent launch covers the layers of one LDS schedule: use a
+        // common schedule when it costs at most 5% over the per-layer optimum
+        float opt = 0.f;
+        std::vector<size_t> lds_layers;
+        for (size_t l = 0; l < b->desc.size(); l++) {
+            int info[6];
+            conv_sched_info(b->mac_sched[l], info);
+            if (!info[0]) continue;
+            lds_layers.push_back(l);
+            opt += times[l][b->mac_sched[l]];
+        }
+        int common = -1;
+        float common_t = 1e30f;
+        for (int sid = 0; sid < ns && !lds_layers.empty(); sid++) {
+            int info[6];
+            conv_sched_info(sid, info);
+            if (!info[0]) continue;
+            float t = 0.f;
+            for (size_t l : lds_layers) {
+                if (times[l][sid] < 0) { t = 1e30f; break; }
+                t += times[l][sid];
+            }
+            if (t < common_t) { common_t = t; common = sid; }
+        }
+        if (common >= 0 && common_t <= 1.05f * opt)
+            for (size_t l : lds_layers) b->mac_sched[l] = common;
+    }
+    for (size_t l = 0; l < b->desc.size(); l++)
+        cache[layer_key(c, arch, b->desc[l]) + (persistent ? "|persistent" : "")] = b->mac_sched[l];
     // NTT schedules per direction over every layer's inputs (a forward and an
     // inverse transform in a row leave the data unchanged)
     std::vector<uint32_t *> ptrs;
@@ -360,6 +415,7 @@ static int build_groups(hyena_batch *b) {
         conv_sched_info(g.sched, info);
         int per_cu = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)persistent_fn(info), 256, 0));
+        b->per_cu = per_cu;
         g.grid = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
         if (g.grid > total) g.grid = std::max<uint32_t>(total, 1);
         HIP_TRY(hipMalloc((void **)&g.d_args, sizeof(MacArgs) * args.size()));
@@ -373,13 +429,17 @@ static int build_groups(hyena_batch *b) {
 
 extern "C" void hyena_batch_destroy(hyena_batch *b) {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (int i = 0; i < 3; i++) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    }
     for (auto &g : b->groups) {
         if (g.d_args) (void)hipFree(g.d_args);
         if (g.d_first) (void)hipFree(g.d_first);
     }
     if (b->d_counters) (void)hipFree(b->d_counters);
+    for (auto &e : b->ev)
+        if (e) (void)hipEventDestroy(e);
     delete b;
 }
 
@@ -406,6 +466,9 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
     }
     b->ntt_fwd = b->ntt_inv = ntt_default_schedule(c->logN);
     int rc = HYENA_OK;
+    if (flags & HYENA_BATCH_TIMING)
+        for (auto &e : b->ev)
+            if (!rc && hipEventCreate(&e) != hipSuccess) rc = set_error(HYENA_EHIP, "hyena_batch_create: event");
     if (flags & HYENA_BATCH_TUNE) rc = tune(b);
     if (!rc) rc = build_groups(b);
     if (rc) {
@@ -416,31 +479,68 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
     return HYENA_OK;
 }
 
+static int capture(hyena_batch *b, int phase, int slot) {
+    // capture on a private stream (the null stream cannot be captured)
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreate(&cs));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = HYENA_OK;
+    if (e == hipSuccess) rc = issue_step(b, cs, phase);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || e2 != hipSuccess)
+        return set_error(HYENA_EHIP, std::string("hyena_batch_run: capture failed: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : e2));
+    b->graph[slot] = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec[slot], g, nullptr, nullptr, 0));
+    return HYENA_OK;
+}
+
 extern "C" int hyena_batch_run(hyena_batch *b, hyena_stream_t stream) {
     if (!b) return set_error(HYENA_EINVAL, "hyena_batch_run: NULL batch");
     const hipStream_t s = (hipStream_t)stream;
-    if (!(b->flags & HYENA_BATCH_GRAPH)) return issue_step(b, s);
-    if (!b->exec) {
-        // capture on a private stream (the null stream cannot be captured)
-        hipStream_t cs;
-        HIP_TRY(hipStreamCreate(&cs));
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        int rc = HYENA_OK;
-        if (e == hipSuccess) rc = issue_step(b, cs);
-        hipGraph_t g = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(cs, &g);
-        (void)hipStreamDestroy(cs);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
+    const bool timing = b->ev[0] != nullptr;
+    if (!(b->flags & HYENA_BATCH_GRAPH)) {
+        if (!timing) return issue_step(b, s);
+        for (int p = 0; p < 3; p++) {
+            HIP_TRY(hipEventRecord(b->ev[p], s));
+            const int rc = issue_step(b, s, p);
+            if (rc) return rc;
         }
-        if (e != hipSuccess || e2 != hipSuccess)
-            return set_error(HYENA_EHIP, std::string("hyena_batch_run: capture failed: ") +
-                                             hipGetErrorString(e != hipSuccess ? e : e2));
-        b->graph = g;
-        HIP_TRY(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+        HIP_TRY(hipEventRecord(b->ev[3], s));
+        return HYENA_OK;
     }
-    HIP_TRY(hipGraphLaunch(b->exec, s));
+    if (!timing) {
+        if (!b->exec[0]) {
+            const int rc = capture(b, -1, 0);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec[0], s));
+        return HYENA_OK;
+    }
+    for (int p = 0; p < 3; p++)
+        if (!b->exec[p]) {
+            const int rc = capture(b, p, p);
+            if (rc) return rc;
+        }
+    for (int p = 0; p < 3; p++) {
+        HIP_TRY(hipEventRecord(b->ev[p], s));
+        HIP_TRY(hipGraphLaunch(b->exec[p], s));
+    }
+    HIP_TRY(hipEventRecord(b->ev[3], s));
+    return HYENA_OK;
+}
+
+extern "C" int hyena_batch_phase_ms(const hyena_batch *b, float *ms) {
+    if (!b || !ms) return set_error(HYENA_EINVAL, "hyena_batch_phase_ms: NULL argument");
+    if (!b->ev[0]) return set_error(HYENA_EINVAL, "hyena_batch_phase_ms: batch built without HYENA_BATCH_TIMING");
+    HIP_TRY(hipEventSynchronize(b->ev[3]));
+    for (int i = 0; i < 3; i++) HIP_TRY(hipEventElapsedTime(&ms[i], b->ev[i], b->ev[i + 1]));
     return HYENA_OK;
 }
 

@@ -207,7 +207,7 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
 }
 
 template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256) mac_lds_kernel(MacArgs a) {
+__global__ void __launch_bounds__(256, 3) mac_lds_kernel(MacArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
     // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous
     // range of logical blocks so that the tiles of one slot chunk share an L2

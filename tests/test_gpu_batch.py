@@ -65,7 +65,9 @@ def _check(items, bufs, tag):
 
 
 @pytest.mark.parametrize("flags", [0, hy.HYENA_BATCH_PERSISTENT, hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH,
-                                   hy.HYENA_BATCH_GRAPH])
+                                   hy.HYENA_BATCH_GRAPH,
+                                   hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING,
+                                   hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_TIMING])
 def test_batch_matches_oracle(dev, setup, flags):
     import torch
     ctx, items = setup
@@ -79,6 +81,9 @@ def test_batch_matches_oracle(dev, setup, flags):
             d_out.fill_(0)
         torch.cuda.synchronize()
         hy.hyena_batch_run(b)
+        if flags & hy.HYENA_BATCH_TIMING:
+            ms = hy.hyena_batch_phase_ms(b)
+            assert all(m > 0 for m in ms)
         _check(items, bufs, (flags, rep))
     info = hy.hyena_batch_info(b)
     if flags & hy.HYENA_BATCH_PERSISTENT:
