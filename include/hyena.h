@@ -316,6 +316,30 @@ int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info);
 int hyena_batch_phase_ms(const hyena_batch *b, float *ms);
 void hyena_batch_destroy(hyena_batch *b);
 
+/* ------------------------------------------------------------------------
+ * Learned cost model: an FP32 MLP 8 -> 64 -> 64 -> 1 with ReLU that predicts
+ * the log time of a layer configuration (ring degree, RNS limbs, channel
+ * partition, Walsh group, layer shape) and replaces an exhaustive timed search
+ * over the parameters the paper selects by hand (the "Optimal Parameter
+ * Selection" and "Evaluation Setup" sections choose n and q per layer).
+ * Parameters: one device fp32 array theta of hyena_mlp_params() words laid out
+ * as W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3. Features: device fp32
+ * [B][8]; targets and predictions: device fp32 [B].
+ * ---------------------------------------------------------------------- */
+uint32_t hyena_mlp_params(void);
+/* floats of the workspace hyena_mlp_loss_grad needs for batch size B */
+size_t hyena_mlp_workspace_floats(uint32_t B);
+/* y = MLP(x) */
+int hyena_mlp_forward(const float *d_theta, const float *d_x, uint32_t B, float *d_y,
+                      hyena_stream_t stream);
+/* loss = mean (MLP(x) - t)^2 (d_loss may be NULL) and its gradient d_grad
+ * [params]; deterministic (fixed summation order). */
+int hyena_mlp_loss_grad(const float *d_theta, const float *d_x, const float *d_t, uint32_t B,
+                        float *d_grad, float *d_loss, float *d_work, hyena_stream_t stream);
+/* One Adam step (Kingma & Ba 2015) with bias correction for step >= 1. */
+int hyena_mlp_adam(float *d_theta, const float *d_grad, float *d_m, float *d_v, uint32_t step,
+                   float lr, float beta1, float beta2, float eps, hyena_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

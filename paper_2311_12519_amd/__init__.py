@@ -118,16 +118,21 @@ def _register_extra(L):
         "hyena_conv_schedules": [_P],
         "hyena_conv_schedule_info": [ctypes.c_int, _P],
         "hyena_conv_default_schedule": [_P],
-        "hyena_mlp_forward": [_P, _P, _P, _u32, _P],
-        "hyena_mlp_backward": [_P, _P, _P, _P, _u32, _P, _P],
+        "hyena_mlp_forward": [_P, _P, _u32, _P, _P],
+        "hyena_mlp_loss_grad": [_P, _P, _P, _u32, _P, _P, _P, _P],
         "hyena_mlp_adam": [_P, _P, _P, _P, _u32, ctypes.c_float, ctypes.c_float,
-                           ctypes.c_float, ctypes.c_float, _u32, _P],
+                           ctypes.c_float, ctypes.c_float, _P],
     }
     for name, args in extra.items():
         if hasattr(L, name):
             f = getattr(L, name)
             f.argtypes = args
             f.restype = None if name == "hyena_batch_destroy" else ctypes.c_int
+    if hasattr(L, "hyena_mlp_params"):
+        L.hyena_mlp_params.argtypes = []
+        L.hyena_mlp_params.restype = ctypes.c_uint32
+        L.hyena_mlp_workspace_floats.argtypes = [_u32]
+        L.hyena_mlp_workspace_floats.restype = ctypes.c_size_t
 
 
 def _check(code: int) -> None:
@@ -376,3 +381,36 @@ def hyena_batch_destroy(b: Batch) -> None:
     if b.handle:
         lib().hyena_batch_destroy(b.handle)
         b.handle = None
+
+
+# ---------------------------------------------------------------------------
+# cost-model MLP kernels
+# ---------------------------------------------------------------------------
+
+def hyena_mlp_params() -> int:
+    return int(lib().hyena_mlp_params())
+
+
+def hyena_mlp_workspace_floats(B: int) -> int:
+    return int(lib().hyena_mlp_workspace_floats(B))
+
+
+def hyena_mlp_forward(d_theta, d_x, d_y, stream=None) -> None:
+    B = d_x.shape[0]
+    _check(lib().hyena_mlp_forward(_dev_ptr(d_theta, "float32"), _dev_ptr(d_x, "float32"), B,
+                                   _dev_ptr(d_y, "float32"), _stream(stream)))
+
+
+def hyena_mlp_loss_grad(d_theta, d_x, d_t, d_grad, d_loss, d_work, stream=None) -> None:
+    B = d_x.shape[0]
+    _check(lib().hyena_mlp_loss_grad(_dev_ptr(d_theta, "float32"), _dev_ptr(d_x, "float32"),
+                                     _dev_ptr(d_t, "float32"), B, _dev_ptr(d_grad, "float32"),
+                                     _dev_ptr(d_loss, "float32") if d_loss is not None else None,
+                                     _dev_ptr(d_work, "float32"), _stream(stream)))
+
+
+def hyena_mlp_adam(d_theta, d_grad, d_m, d_v, step: int, lr: float, beta1: float = 0.9,
+                   beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(lib().hyena_mlp_adam(_dev_ptr(d_theta, "float32"), _dev_ptr(d_grad, "float32"),
+                                _dev_ptr(d_m, "float32"), _dev_ptr(d_v, "float32"), step, lr, beta1, beta2,
+                                eps, _stream(stream)))

@@ -1,0 +1,95 @@
+"""GPU tests of the cost model: the MLP forward / gradient / Adam kernels
+against the fp64 oracle, training convergence, and a reduced MobileNetV1
+experiment showing what the learned model gains over the default parameters."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2311_12519_amd as hy
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 65, 1000])
+def test_mlp_forward_and_gradient_match_oracle(dev, B):
+    import torch
+    rng = np.random.default_rng(B)
+    th = rng.normal(0, 0.3, omlp.NPARAM).astype(np.float32)
+    X = rng.normal(size=(B, 8)).astype(np.float32)
+    T = rng.normal(size=B).astype(np.float32)
+    d_th, d_x, d_t = _dev(th), _dev(X), _dev(T)
+    d_y = torch.empty(B, dtype=torch.float32, device="cuda")
+    hy.hyena_mlp_forward(d_th, d_x, d_y)
+    y_ref, _ = omlp.forward(th.astype(np.float64), X.astype(np.float64))
+    # fp32 evaluation of a 64-term dot product of O(1) values: |err| << 1e-4
+    assert np.allclose(_host(d_y), y_ref, rtol=1e-4, atol=1e-4)
+    grad = torch.empty(omlp.NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    work = torch.empty(hy.hyena_mlp_workspace_floats(B), dtype=torch.float32, device="cuda")
+    hy.hyena_mlp_loss_grad(d_th, d_x, d_t, grad, loss, work)
+    l_ref, g_ref = omlp.loss_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    g = _host(grad)
+    scale = np.abs(g_ref).max()
+    assert abs(_host(loss)[0] - l_ref) <= 1e-4 * max(1.0, l_ref)
+    assert np.all(np.abs(g - g_ref) <= 1e-4 * np.abs(g_ref) + 2e-5 * scale), np.abs(g - g_ref).max()
+    # deterministic: a second evaluation is bit-identical
+    g2 = torch.empty_like(grad)
+    hy.hyena_mlp_loss_grad(d_th, d_x, d_t, g2, None, work)
+    assert torch.equal(grad, g2)
+
+
+def test_mlp_adam_matches_oracle(dev):
+    import torch
+    rng = np.random.default_rng(7)
+    n = omlp.NPARAM
+    th, g = rng.normal(size=n), rng.normal(size=n)
+    m, v = rng.normal(size=n) * 0.1, np.abs(rng.normal(size=n)) * 0.1
+    d_th, d_g, d_m, d_v = _dev(th), _dev(g), _dev(m), _dev(v)
+    hy.hyena_mlp_adam(d_th, d_g, d_m, d_v, step=5, lr=1e-2)
+    th2, m2, v2 = omlp.adam(th, g, m, v, step=5, lr=1e-2)
+    assert np.allclose(_host(d_th), th2, rtol=1e-5, atol=1e-6)
+    assert np.allclose(_host(d_m), m2, rtol=1e-5, atol=1e-7)
+    assert np.allclose(_host(d_v), v2, rtol=1e-5, atol=1e-7)
+
+
+def test_mlp_training_fits_a_smooth_function(dev):
+    from paper_2311_12519_amd.costmodel import MLP
+    rng = np.random.default_rng(3)
+    X = rng.uniform(-1, 1, size=(1500, 8))
+    y = np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2] + 0.5 * X[:, 3]
+    model = MLP(seed=1)
+    hist = model.fit(X, y, steps=1500, lr=3e-3)
+    pred = model.predict(X)
+    assert hist[-1][1] < 0.1 * hist[0][1]
+    assert np.mean((pred - y) ** 2) < 0.02
+
+
+def test_cost_model_beats_default_parameters(dev):
+    """Reduced experiment: train on timings of random layer shapes, choose
+    parameters for six MobileNetV1 layers, judge with exhaustive timing."""
+    from paper_2311_12519_amd import costmodel as cm
+    timer = cm.Timer(pool_words=1 << 28)
+    mob = cm.mobilenet_shapes()
+    layers = [mob[i] for i in (0, 4, 9, 14, 24, 26)]
+    shapes = cm.random_shapes(11, 160, exclude=mob)
+    X, y = cm.collect(timer, shapes, 4, 11)
+    assert len(y) >= 500
+    model = cm.MLP(seed=2)
+    model.fit(X, y, steps=2500)
+    rep = cm.evaluate(timer, model, layers)
+    print("regret", rep["regret"], "gain over default", rep["gain_over_default"])
+    assert rep["gain_over_default"] > 1.0
+    assert rep["regret"] < 0.5

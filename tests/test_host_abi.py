@@ -21,7 +21,7 @@ def _declared_symbols():
     for fn in os.listdir(os.path.join(ROOT, "include")):
         if fn.endswith(".h"):
             src = open(os.path.join(ROOT, "include", fn)).read()
-            names |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*(hyena_\w+)\s*\(", src, re.M))
+            names |= set(re.findall(r"^\s*(?:int|void|const char \*|uint32_t|size_t)\s*(hyena_\w+)\s*\(", src, re.M))
     return names
 
 
