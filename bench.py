@@ -54,6 +54,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mac_persistent_vgg16_b8_n8192_counters.md")
+MAC_SOURCES = ["paper_2311_12519_amd/csrc/mac.h", "paper_2311_12519_amd/csrc/batch.hip"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent MAC from the committed rocprofv3
+    counter summary, or None when the MAC sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "source_sha256_16")))
+    h = hashlib.sha256()
+    for f in MAC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if vals.get("source_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,7 +370,8 @@ def main():
         out["roofline"] = {"bound": "alu",
                            "kernel": "mac_persistent_kernel" if head_mode == "tuned" else "mac_lds_kernel",
                            "achieved": ach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s (one v_mad_u64_u32 per coeff-MAC)",
-                           "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                           "frac": ach / VALU_PEAK_TOPS,
+                           "traffic": measured_traffic() if head_mode == "tuned" and args.primes == 31 else None,
                            "launches_per_step": 1 if head_mode == "tuned" else len(layers),
                            "hbm_algorithmic_GBs": mac_gbs, "hbm_frac": mac_gbs / HBM_PEAK_GBS}
         ntt_bytes = sum(o.in_words * 4 * 2 for o in layers) * n_img
