@@ -200,6 +200,8 @@ int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
  *   A[k] = sum_j a[j] psi_i^((2 brv(k) + 1) j) mod q_i
  * (evaluation at the odd powers of psi_i, bit-reversed order; the transform
  * that turns the negacyclic product into a pointwise one, q = 1 mod 2N).
+ * Inputs must be residues in [0, q_i). d_poly must be 16-byte aligned
+ * (EINVAL otherwise). Errors: EINVAL, EHIP.
  */
 int hyena_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
 

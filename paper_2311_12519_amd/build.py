@@ -24,9 +24,16 @@ FLAGS = ["-std=c++17", "--offload-arch=gfx950", "-O3", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
+# The NTT keeps each thread's residues in registers, which needs its fully
+# unrolled butterfly nests (up to 64 residues x 6 stages) to stay unrolled;
+# LLVM's default size cap for `#pragma unroll` would leave the largest one
+# rolled and the register array on the scratch stack.
+EXTRA = {"ntt.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

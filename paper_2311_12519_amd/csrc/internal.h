@@ -18,10 +18,9 @@ struct LimbConst {
     uint32_t qinv_neg; // -q^{-1} mod 2^32 (Montgomery)
     uint32_t r32s;     // Shoup companion of r32: floor(r32 * 2^32 / q)
     uint32_t ninv;     // N^{-1} mod q
-    uint32_t ninvs;    // Shoup companion of ninv
+    uint32_t ninv_m;   // N^{-1} 2^32 mod q (Montgomery form)
     uint32_t fold;     // products that fit between two folds of a lazy accumulator
-    uint32_t w1n;      // last inverse-NTT twiddle psi^-brv(1) times N^{-1}
-    uint32_t w1ns;     // its Shoup companion
+    uint32_t w1n_m;    // last inverse-NTT twiddle psi^-brv(1) times N^{-1}, Montgomery form
 };
 
 struct LimbTable {
@@ -37,8 +36,8 @@ struct hyena_ctx {
     bool lazy_ntt = false;   // every q_i < 2^30: NTT butterflies may run lazily
     // host twiddles (for the host-side NTT used by test-setup encryption)
     std::vector<uint32_t> h_fw, h_fws, h_iw, h_iws;  // [L][N]
-    // device twiddles: forward psi powers in bit-reversed order with Shoup
-    // companions, interleaved as pairs; inverse likewise.  [L][N][2]
+    // device twiddles in Montgomery form (w 2^32 mod q): forward psi powers
+    // in bit-reversed order, inverse psi^-1 powers likewise.  [L][N]
     uint32_t *d_fw = nullptr;
     uint32_t *d_iw = nullptr;
 };
@@ -56,6 +55,10 @@ int set_error(int code, const std::string &msg);
 // modular helpers (host)
 static inline uint32_t h_mulmod(uint32_t a, uint32_t b, uint32_t q) {
     return (uint32_t)((uint64_t)a * b % q);
+}
+// x 2^32 mod q: the Montgomery form the device NTT multiplies by
+static inline uint32_t to_montgomery(uint32_t x, uint32_t q) {
+    return (uint32_t)(((uint64_t)x << 32) % q);
 }
 uint32_t h_powmod(uint32_t b, uint64_t e, uint32_t q);
 static inline uint32_t shoup_companion(uint32_t w, uint32_t q) {

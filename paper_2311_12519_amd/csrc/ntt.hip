@@ -10,10 +10,12 @@
 // Design: one workgroup of T = 2^LOGT threads transforms one limb of one
 // polynomial (N = 2^LOGN residues, 16..64 KiB) resident in LDS. Each thread
 // keeps E = N/T residues in registers and runs e <= LOGE consecutive butterfly
-// stages on them (a radix-2^e pass) between LDS exchanges. The first pass
-// reads HBM directly with unit stride across lanes; the last pass writes
-// through LDS so that the HBM store is coalesced too. LDS words are padded
-// by one per 32 to break the bank conflicts of the strided passes.
+// stages on them (a radix-2^e pass) between LDS exchanges. The passes at the
+// two ends touch HBM directly: the one over the first stages with unit stride
+// across lanes, the one over the last stages with runs of 2^e consecutive
+// residues per thread (16-byte accesses), so a transform of P passes needs
+// P - 1 LDS exchanges. LDS words are padded by one per 32 to break the bank
+// conflicts of the strided passes. Polynomials must be 16-byte aligned.
 #include "internal.h"
 
 namespace {
@@ -23,29 +25,30 @@ __device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t q) {
     return min(x, x - q);
 }
 
-// Shoup multiplication: a * w mod q with ws = floor(w 2^32 / q), a < 2^32.
-__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
-    uint32_t qh = __umulhi(a, ws);
-    return csub(a * w - qh * q, q);
-}
-
-// Shoup product left in [0, 2q) (no final correction).
-__device__ __forceinline__ uint32_t shoup_lazy(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
-    return a * w - __umulhi(a, ws) * q;
+// Montgomery multiplication: a * wm * 2^-32 mod q, left in [0, 2q), for any
+// a < 2^32 and wm < q (wm = w 2^32 mod q gives a * w mod q). With
+// t = a wm < q 2^32 and m = t (-q^-1) mod 2^32, t + m q is divisible by
+// 2^32 and (t + m q) / 2^32 < 2q. Both words of each 64-bit product are used,
+// so it compiles to two v_mad_u64_u32 and one v_mul_lo_u32 (the fast forms on
+// gfx950), and the twiddle tables need no companion words.
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t wm, uint32_t q, uint32_t qn) {
+    const uint64_t t = (uint64_t)a * wm;
+    const uint32_t m = (uint32_t)t * qn;
+    return (uint32_t)(((uint64_t)m * q + t) >> 32);
 }
 
 // (lo, hi) -> (lo + w hi, lo - w hi). Exact variant (any q < 2^31): all values
 // stay canonical in [0, q). Lazy variant (Harvey's butterfly, q < 2^30):
 // values in [0, 4q) between stages.
 template <bool LAZY>
-__device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t ws, uint32_t q) {
+__device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t q, uint32_t qn) {
     if (LAZY) {
         const uint32_t x = min(lo, lo - 2 * q);           // [0, 2q)
-        const uint32_t t = shoup_lazy(hi, w, ws, q);      // [0, 2q)
+        const uint32_t t = mont_mul(hi, w, q, qn);        // [0, 2q)
         lo = x + t;                                       // [0, 4q)
         hi = x - t + 2 * q;                               // (0, 4q)
     } else {
-        const uint32_t t = shoup(hi, w, ws, q);
+        const uint32_t t = csub(mont_mul(hi, w, q, qn), q);
         const uint32_t d = lo - t;
         hi = min(d, d + q);       // lo - t wraps above 2q exactly when lo < t
         lo = csub(lo + t, q);
@@ -55,17 +58,17 @@ __device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, 
 // (lo, hi) -> (lo + hi, w (lo - hi)). Exact: canonical in and out. Lazy:
 // [0, 2q) in and out.
 template <bool LAZY>
-__device__ __forceinline__ void gs_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t ws, uint32_t q) {
+__device__ __forceinline__ void gs_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t q, uint32_t qn) {
     if (LAZY) {
         const uint32_t s = lo + hi;                       // [0, 4q)
         const uint32_t t = lo - hi + 2 * q;               // (0, 4q)
         lo = min(s, s - 2 * q);
-        hi = shoup_lazy(t, w, ws, q);
+        hi = mont_mul(t, w, q, qn);
     } else {
         const uint32_t s = lo + hi;
-        const uint32_t d = lo - hi;
+        const uint32_t d = lo - hi + q;                   // (0, 2q)
         lo = csub(s, q);
-        hi = shoup(min(d, d + q), w, ws, q);
+        hi = csub(mont_mul(d, w, q, qn), q);
     }
 }
 
@@ -76,8 +79,8 @@ __device__ __forceinline__ uint32_t lds_idx(uint32_t j) { return j + (j >> 5); }
 // with o = gi mod (N>>(s0+e)), b = gi div (N>>(s0+e)); thread tid owns groups
 // gi = tid + k*T, k < E>>e, stored at registers x[k*2^e + r].
 template <int LOGN, int LOGT, int E_LOG, int S0, int EP, bool LAZY>
-__device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint2 *__restrict__ tw,
-                                         uint32_t q, uint32_t tid) {
+__device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint32_t *__restrict__ tw,
+                                         uint32_t q, uint32_t qn, uint32_t tid) {
     constexpr int GE = 1 << EP;
     constexpr int NG = (1 << E_LOG) >> EP;          // groups per thread
     constexpr uint32_t OSPAN = 1u << (LOGN - S0 - EP);
@@ -93,8 +96,7 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint2 
             for (int r = 0; r < GE; r++) {
                 if (r & half) continue;
                 const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
-                const uint2 w = tw[widx];
-                ct_bfly<LAZY>(x[kg * GE + r], x[kg * GE + r + half], w.x, w.y, q);
+                ct_bfly<LAZY>(x[kg * GE + r], x[kg * GE + r + half], tw[widx], q, qn);
             }
         }
     }
@@ -128,12 +130,56 @@ __device__ __forceinline__ void from_lds(uint32_t (&x)[1 << E_LOG], const uint32
     }
 }
 
+// A pass that ends at the last stage (S0 + EP == LOGN) gives group gi the
+// 2^EP consecutive residues [gi 2^EP, (gi + 1) 2^EP): the thread moves them
+// between HBM and registers with 16-byte (or, for 2^EP = 2, 8-byte) accesses,
+// and the wave as a whole covers one contiguous span.
+template <int LOGT, int E_LOG, int EP>
+__device__ __forceinline__ void load_runs(uint32_t (&x)[1 << E_LOG], const uint32_t *__restrict__ a, uint32_t tid) {
+    constexpr int GE = 1 << EP, NG = (1 << E_LOG) >> EP;
+    static_assert(GE >= 2, "runs of at least two residues");
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++) {
+        const uint32_t *p = a + ((size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EP);
+        if constexpr (GE >= 4) {
+#pragma unroll
+            for (int r = 0; r < GE; r += 4) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(p + r);
+                x[kg * GE + r] = v.x, x[kg * GE + r + 1] = v.y, x[kg * GE + r + 2] = v.z, x[kg * GE + r + 3] = v.w;
+            }
+        } else {
+            const uint2 v = *reinterpret_cast<const uint2 *>(p);
+            x[kg * GE] = v.x, x[kg * GE + 1] = v.y;
+        }
+    }
+}
+
+template <int LOGT, int E_LOG, int EP>
+__device__ __forceinline__ void store_runs(const uint32_t (&x)[1 << E_LOG], uint32_t *__restrict__ a, uint32_t tid) {
+    constexpr int GE = 1 << EP, NG = (1 << E_LOG) >> EP;
+    static_assert(GE >= 2, "runs of at least two residues");
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++) {
+        uint32_t *p = a + ((size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EP);
+        if constexpr (GE >= 4) {
+#pragma unroll
+            for (int r = 0; r < GE; r += 4)
+                *reinterpret_cast<uint4 *>(p + r) =
+                    make_uint4(x[kg * GE + r], x[kg * GE + r + 1], x[kg * GE + r + 2], x[kg * GE + r + 3]);
+        } else {
+            *reinterpret_cast<uint2 *>(p) = make_uint2(x[kg * GE], x[kg * GE + 1]);
+        }
+    }
+}
+
 // Forward transform of one limb-polynomial a (N residues) by the block:
 // passes of E0, E1, E2 (, E3) stages; E0 = LOGN - LOGT is the register radix
-// (every thread holds 2^E0 residues).
+// (every thread holds 2^E0 residues). The first pass reads HBM with unit
+// stride across lanes, the last writes runs of consecutive residues; the
+// passes between exchange residues through LDS.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
-__device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint2 *__restrict__ tw,
-                                             uint32_t q, uint32_t *lds) {
+__device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
+                                             uint32_t q, uint32_t qn, uint32_t *lds) {
     constexpr int E_LOG = LOGN - LOGT;
     constexpr int T = 1 << LOGT, E = 1 << E_LOG;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
@@ -143,34 +189,28 @@ __device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uin
     // pass 0: stages [0, E0); group of thread tid: indices tid + r*T
 #pragma unroll
     for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
-    fwd_pass<LOGN, LOGT, E_LOG, 0, E0, LAZY>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, 0, E0, LAZY>(x, tw, q, qn, tid);
     to_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
-    fwd_pass<LOGN, LOGT, E_LOG, E0, E1, LAZY>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, E0, E1, LAZY>(x, tw, q, qn, tid);
     __syncthreads();
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-    fwd_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, LAZY>(x, tw, q, tid);
+    fwd_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, LAZY>(x, tw, q, qn, tid);
     if constexpr (E3 > 0) {
         __syncthreads();
         to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
         __syncthreads();
         from_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
-        fwd_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, LAZY>(x, tw, q, tid);
+        fwd_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, LAZY>(x, tw, q, qn, tid);
     }
     if (LAZY) {
 #pragma unroll
         for (int r = 0; r < E; r++) x[r] = csub(min(x[r], x[r] - 2 * q), q);  // [0, 4q) -> [0, q)
     }
-    constexpr int SL = E3 > 0 ? E0 + E1 + E2 : E0 + E1;
-    constexpr int EL = E3 > 0 ? E3 : E2;
-    __syncthreads();
-    to_lds<LOGN, LOGT, E_LOG, SL, EL>(x, lds, tid);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < E; r++) a[tid + r * T] = lds[lds_idx(tid + r * T)];
+    store_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
 }
 
 // Inverse: Gentleman-Sande stages run in the reverse order of the forward
@@ -178,12 +218,12 @@ __device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uin
 // to 0) pairs j and j + (N >> (s+1)) in block j >> (LOGN - s) with twiddle
 // psi^-brv(m + block). Passes are the forward passes taken in reverse.
 template <int LOGN, int LOGT, int E_LOG, int S0, int EP, bool LAST, bool LAZY>
-__device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint2 *__restrict__ tw,
+__device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint32_t *__restrict__ tw,
                                          const LimbConst &lc, uint32_t tid) {
     constexpr int GE = 1 << EP;
     constexpr int NG = (1 << E_LOG) >> EP;
     constexpr uint32_t OSPAN = 1u << (LOGN - S0 - EP);
-    const uint32_t q = lc.q;
+    const uint32_t q = lc.q, qn = lc.qinv_neg;
 #pragma unroll
     for (int kg = 0; kg < NG; kg++) {
         const uint32_t gi = tid + (uint32_t)kg * (1u << LOGT);
@@ -199,15 +239,14 @@ __device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint2 
                 if (LAST && S0 + u == 0) {
                     // last stage (one block, twiddle psi^-brv(1)): fold N^{-1}
                     // into both outputs and leave them canonical
+                    // (any input below 2^32 is valid: s, d < 4q)
                     const uint32_t s = lo + hi;
-                    const uint32_t d = LAZY ? lo - hi + 2 * q : lo - hi;
-                    const uint32_t dd = LAZY ? d : min(d, d + q);
-                    lo = shoup(LAZY ? s : csub(s, q), lc.ninv, lc.ninvs, q);
-                    hi = shoup(dd, lc.w1n, lc.w1ns, q);
+                    const uint32_t d = lo - hi + (LAZY ? 2 * q : q);
+                    lo = csub(mont_mul(s, lc.ninv_m, q, qn), q);
+                    hi = csub(mont_mul(d, lc.w1n_m, q, qn), q);
                 } else {
                     const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
-                    const uint2 w = tw[widx];
-                    gs_bfly<LAZY>(lo, hi, w.x, w.y, q);
+                    gs_bfly<LAZY>(lo, hi, tw[widx], q, qn);
                 }
             }
         }
@@ -215,26 +254,25 @@ __device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint2 
 }
 
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
-__device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uint2 *__restrict__ tw,
+__device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
                                              const LimbConst &lc, uint32_t *lds) {
     constexpr int E_LOG = LOGN - LOGT;
     constexpr int T = 1 << LOGT, E = 1 << E_LOG;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
     const uint32_t tid = threadIdx.x;
     uint32_t x[E];
-#pragma unroll
-    for (int r = 0; r < E; r++) lds[lds_idx(tid + r * T)] = a[tid + r * T];
-    __syncthreads();
+    // the first inverse pass (the forward's last) reads runs straight from HBM
     if constexpr (E3 > 0) {
-        from_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
+        load_runs<LOGT, E_LOG, E3>(x, a, tid);
         inv_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, false, LAZY>(x, tw, lc, tid);
-        __syncthreads();
         to_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
         __syncthreads();
+        from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
+    } else {
+        load_runs<LOGT, E_LOG, E2>(x, a, tid);
     }
-    from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
     inv_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, false, LAZY>(x, tw, lc, tid);
-    __syncthreads();
+    if constexpr (E3 > 0) __syncthreads();
     to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
@@ -256,9 +294,17 @@ struct NttSegs {
     uint32_t n;
 };
 
+// Waves per SIMD that the LDS footprint allows (160 KiB per CU): the register
+// budget the compiler may use without costing occupancy.
+constexpr int ntt_waves_per_simd(int logn, int logt) {
+    const int blocks = (160 * 1024) / (((1 << logn) + (1 << logn) / 32) * 4);
+    const int w = blocks * ((1 << logt) / 64) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY, bool INV>
-__global__ void __launch_bounds__(1 << LOGT)
-ntt_kernel(NttSegs sg, const uint2 *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
+ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
     constexpr int N = 1 << LOGN;
     __shared__ uint32_t lds[N + N / 32];
     // blocks of one segment hold limb-polynomials in [P][L][N] order; every
@@ -268,15 +314,15 @@ ntt_kernel(NttSegs sg, const uint2 *__restrict__ tw_all, LimbTable lt, uint32_t 
     const uint32_t local = blockIdx.x - sg.first[s];
     uint32_t *a = sg.ptr[s] + (size_t)local * N;
     const uint32_t limb = local % L;
-    const uint2 *tw = tw_all + (size_t)limb * N;
+    const uint32_t *tw = tw_all + (size_t)limb * N;
     if (INV) ntt_inv_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb], lds);
-    else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lds);
+    else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lt.c[limb].qinv_neg, lds);
 }
 
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
 hipError_t launch_sched(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
     const dim3 grid(sg.first[sg.n]), block(1u << LOGT);
-    const uint2 *tw = (const uint2 *)(inv ? c->d_iw : c->d_fw);
+    const uint32_t *tw = inv ? c->d_iw : c->d_fw;
     if (c->lazy_ntt) {  // Harvey's lazy butterflies need 4q < 2^32
         if (inv) hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, true, true>), grid, block, 0, s, sg, tw, c->lt, c->L);
         else hipLaunchKernelGGL((ntt_kernel<LOGN, LOGT, E0, E1, E2, E3, true, false>), grid, block, 0, s, sg, tw, c->lt, c->L);
@@ -333,6 +379,9 @@ int ntt_default_schedule(uint32_t logN) {
 int launch_ntt_segs(const hyena_ctx *c, uint32_t *const *ptrs, const size_t *P, uint32_t nseg, bool inv,
                     int sched, hipStream_t s) {
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
+    for (uint32_t i = 0; i < nseg; i++)
+        if (P[i] && ((uintptr_t)ptrs[i] & 15u))
+            return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
     if (sched < 0) sched = ntt_default_schedule(c->logN);
     if (sched < 0 || sched >= kNumNtt || kNtt[sched].logn != (int)c->logN)
         return set_error(HYENA_EINVAL, "hyena_ntt: schedule does not exist for this N");

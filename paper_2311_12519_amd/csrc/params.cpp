@@ -97,9 +97,8 @@ static void build_tables(hyena_ctx *c) {
         lc.qinv_neg = 0u - inv;
         lc.r32s = shoup_companion(lc.r32, q);
         lc.ninv = h_powmod(N, q - 2, q);
-        lc.ninvs = shoup_companion(lc.ninv, q);
-        lc.w1n = h_mulmod(c->h_iw[(size_t)i * N + 1], lc.ninv, q);
-        lc.w1ns = shoup_companion(lc.w1n, q);
+        lc.ninv_m = to_montgomery(lc.ninv, q);
+        lc.w1n_m = to_montgomery(h_mulmod(c->h_iw[(size_t)i * N + 1], lc.ninv, q), q);
         // After a fold the accumulator is < 2^32 (r32 + 1); each product is
         // <= (q-1)^2. Products that fit before the next fold:
         unsigned __int128 room = (((unsigned __int128)1) << 64) - 1 -
@@ -184,17 +183,16 @@ extern "C" int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint
         return HYENA_OK;
     }
     hipError_t e = hipGetDevice(&c->device);
-    const size_t bytes = sizeof(uint32_t) * 2 * (size_t)L * N;
+    const size_t bytes = sizeof(uint32_t) * (size_t)L * N;
     if (e == hipSuccess) e = hipMalloc((void **)&c->d_fw, bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&c->d_iw, bytes);
     if (e == hipSuccess) {
-        std::vector<uint32_t> fw(2 * (size_t)L * N), iw(2 * (size_t)L * N);
-        for (size_t k = 0; k < (size_t)L * N; k++) {
-            fw[2 * k] = c->h_fw[k];
-            fw[2 * k + 1] = c->h_fws[k];
-            iw[2 * k] = c->h_iw[k];
-            iw[2 * k + 1] = c->h_iws[k];
-        }
+        std::vector<uint32_t> fw((size_t)L * N), iw((size_t)L * N);
+        for (uint32_t i = 0; i < L; i++)
+            for (size_t k = 0; k < N; k++) {
+                fw[(size_t)i * N + k] = to_montgomery(c->h_fw[(size_t)i * N + k], c->q[i]);
+                iw[(size_t)i * N + k] = to_montgomery(c->h_iw[(size_t)i * N + k], c->q[i]);
+            }
         e = hipMemcpy(c->d_fw, fw.data(), bytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(c->d_iw, iw.data(), bytes, hipMemcpyHostToDevice);
     }
