@@ -290,8 +290,10 @@ typedef struct hyena_batch hyena_batch;
 #define HYENA_BATCH_PERSISTENT 0x1u /* layers sharing an LDS schedule run in one persistent launch */
 #define HYENA_BATCH_GRAPH 0x2u      /* the step is captured once into a hipGraph and replayed */
 #define HYENA_BATCH_TUNE 0x4u       /* MAC schedule per layer and NTT schedule per direction chosen
-                                       by timing; choices cached in the file named by the
-                                       environment variable HYENA_TUNE_CACHE when set */
+                                       by timing, and with HYENA_BATCH_PERSISTENT whether the
+                                       persistent launch or one launch per layer runs the
+                                       multiply-accumulate phase; choices cached in the file named
+                                       by the environment variable HYENA_TUNE_CACHE when set */
 #define HYENA_BATCH_TIMING 0x8u     /* record HIP events between the phases of every run for
                                        hyena_batch_phase_ms (with HYENA_BATCH_GRAPH: one graph
                                        per phase, events between their launches) */
@@ -309,7 +311,8 @@ int hyena_batch_create(const hyena_ctx *ctx, const hyena_layer_io *layers, uint3
  * capturing it on the first call). Calls on one batch must not overlap. */
 int hyena_batch_run(hyena_batch *b, hyena_stream_t stream);
 /* info[] = {ntt forward schedule, ntt inverse schedule, kernel launches per
- * step, n_layers, persistent launches, MAC schedule of layer 0, 1, ...};
+ * step, n_layers, persistent launches (0 when the autotuner chose one launch
+ * per layer), MAC schedule of layer 0, 1, ...};
  * entries beyond the end are -1. */
 int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info);
 /* Durations of the last run's phases in ms: ms[0] forward NTTs, ms[1]

@@ -16,6 +16,7 @@
 // convolutions run under MPC in the paper's protocol and are not part of this
 // server-side computation.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -39,11 +40,15 @@ hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, 
 namespace {
 
 // Thread 0 draws the next work item: its own XCD's queue first, then the
-// other queues in turn; `total` once every queue is exhausted.
-__device__ __forceinline__ uint32_t draw_item(uint32_t *counters, uint32_t total, uint32_t &qi) {
+// other queues in turn; `total` once every queue is exhausted. Queue x holds
+// the items [bounds[x], bounds[x + 1]): contiguous slices of equal estimated
+// cost, so the XCDs run out of work together and seldom steal (a stolen tile
+// is fetched into a second L2).
+__device__ __forceinline__ uint32_t draw_item(uint32_t *counters, const uint32_t *bounds, uint32_t total,
+                                              uint32_t &qi) {
     for (int tries = 0; tries < 8; tries++) {
-        const uint32_t lo = (uint32_t)(((uint64_t)total * qi) >> 3);
-        const uint32_t hi = (uint32_t)(((uint64_t)total * (qi + 1)) >> 3);
+        const uint32_t lo = bounds[qi];
+        const uint32_t hi = bounds[qi + 1];
         const uint32_t k = atomicAdd(&counters[qi], 1u);
         if (lo + k < hi) return lo + k;
         qi = (qi + 1) & 7u;
@@ -55,22 +60,27 @@ __device__ __forceinline__ uint32_t draw_item(uint32_t *counters, uint32_t total
 template <int MT, int OT, int WR, int WO, int NS>
 __global__ void __launch_bounds__(256, 3)
 mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
-                      uint32_t *__restrict__ counters, uint32_t total) {
+                      uint32_t *__restrict__ counters, const uint32_t *__restrict__ bounds, uint32_t total) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
     __shared__ uint32_t item_s[2];
     uint32_t qi = blockIdx.x & 7u;  // queue drawn from (thread 0 only)
-    if (threadIdx.x == 0) item_s[0] = draw_item(counters, total, qi);
+    if (threadIdx.x == 0) item_s[0] = draw_item(counters, bounds, total, qi);
     __syncthreads();
     for (uint32_t round = 0;; round ^= 1) {
         // uniform across the block: lets the layer's arguments load as scalars
         const uint32_t it = __builtin_amdgcn_readfirstlane(item_s[round]);
         if (it >= total) break;
-        // draw the following item now; its latency hides behind this one
-        if (threadIdx.x == 0) item_s[round ^ 1] = draw_item(counters, total, qi);
         uint32_t l = 0;
         while (l + 1 < n_layers && it >= first[l + 1]) l++;
         l = __builtin_amdgcn_readfirstlane(l);
-        mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds);
+        // the following item is claimed when this one's accumulation is done:
+        // items then start in queue order, as the hardware dispatcher would
+        // start blocks (tiles that share input rows stay in flight together
+        // and hit in L2), and the claim's latency hides behind the epilogue
+        auto claim = [&]() {
+            if (threadIdx.x == 0) item_s[round ^ 1] = draw_item(counters, bounds, total, qi);
+        };
+        mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds, claim);
         __syncthreads();  // LDS stages and item_s[round ^ 1] ready for the next round
     }
 }
@@ -79,7 +89,7 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, uint32_t);
+typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, const uint32_t *, uint32_t);
 
 PersistentFn persistent_fn(const int *info) {
 #define HY_P(M, O, R, W, S)                                                          \
@@ -151,6 +161,7 @@ struct hyena_batch {
         uint32_t grid = 0;
     };
     std::vector<Group> groups;
+    bool mac_solo = false;  // autotuner: per-layer launches beat the persistent ones
     int per_cu = 0;  // persistent blocks per CU
     std::vector<uint32_t> solo;   // layers launched on their own
     uint32_t *d_counters = nullptr;
@@ -167,6 +178,15 @@ struct hyena_batch {
 // 2: inverse NTTs) or all of them (phase < 0).
 static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
     const hyena_ctx *c = b->ctx;
+    if (b->mac_solo) {
+        for (uint32_t l = 0; l < b->desc.size(); l++) {
+            const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out,
+                                       b->mac_sched[l], true, s);
+            if (rc) return rc;
+            launches++;
+        }
+        return HYENA_OK;
+    }
     if (b->n_counters) {
         hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, b->d_counters, b->n_counters);
         launches++;
@@ -177,7 +197,8 @@ static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
         conv_sched_info(g.sched, info);
         PersistentFn fn = persistent_fn(info);
         hipLaunchKernelGGL(fn, dim3(g.grid), dim3(256), 0, s, (const MacArgs *)g.d_args,
-                           (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi, g.total);
+                           (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi,
+                           (const uint32_t *)(g.d_first + g.layers.size() + 1), g.total);
         launches++;
         // layers whose Walsh group is wider than the fused epilogue
         for (uint32_t l : g.layers) {
@@ -411,6 +432,34 @@ static int build_groups(hyena_batch *b) {
         }
         first.push_back(total);
         g.total = total;
+        // queue bounds: eight contiguous slices of equal estimated cost; an
+        // item costs its input groups (the loop trip) plus a few for the
+        // epilogue (reduction and stores)
+        {
+            std::vector<double> cost;
+            double sum = 0;
+            for (size_t j = 0; j < g.layers.size(); j++) {
+                cost.push_back((double)b->desc[g.layers[j]].n_groups + 2.0);
+                sum += cost.back() * (first[j + 1] - first[j]);
+            }
+            uint32_t x = 1;
+            double acc = 0;
+            std::vector<uint32_t> bounds = {0};
+            for (size_t j = 0; j < g.layers.size() && x < 8; j++) {
+                const uint32_t n = first[j + 1] - first[j];
+                while (x < 8 && acc + cost[j] * n >= sum * x / 8.0) {
+                    const double need = sum * x / 8.0 - acc;  // cost still missing in this layer
+                    uint32_t k = (uint32_t)std::ceil(need / cost[j]);
+                    k = std::min(k, n);
+                    bounds.push_back(std::max(bounds.back(), first[j] + k));
+                    x++;
+                }
+                acc += cost[j] * n;
+            }
+            while (bounds.size() < 9) bounds.push_back(total);
+            bounds[8] = total;
+            first.insert(first.end(), bounds.begin(), bounds.end());
+        }
         int info[6];
         conv_sched_info(g.sched, info);
         int per_cu = 0;
@@ -424,6 +473,42 @@ static int build_groups(hyena_batch *b) {
         HIP_TRY(hipMemcpy(g.d_first, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
         b->groups.push_back(g);
     }
+    return HYENA_OK;
+}
+
+// Autotuner, second stage: time the whole multiply-accumulate phase as the
+// persistent launches and as one launch per layer, and keep the faster.
+static int tune_mac_phase(hyena_batch *b) {
+    const hyena_ctx *c = b->ctx;
+    const std::string arch = arch_name(c->device);
+    std::ostringstream all;
+    for (size_t l = 0; l < b->desc.size(); l++) all << layer_key(c, arch, b->desc[l]) << "#" << b->mac_sched[l] << ";";
+    std::ostringstream k;
+    k << arch << "|macphase|" << std::hex << std::hash<std::string>()(all.str());
+    auto cache = load_cache();
+    auto it = cache.find(k.str());
+    if (it != cache.end()) {
+        b->mac_solo = it->second == 1;
+        return HYENA_OK;
+    }
+    hipStream_t s;
+    HIP_TRY(hipStreamCreate(&s));
+    int rc = HYENA_OK;
+    auto phase = [&](bool solo) {
+        b->mac_solo = solo;
+        int n = 0;
+        if (!rc) rc = issue_mac_phase(b, s, n);
+    };
+    const float tp = time_best(s, 3, [&] { phase(false); });
+    const float ts = time_best(s, 3, [&] { phase(true); });
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (rc) return rc;
+    // the persistent launch unless per-layer launches are clearly faster (the
+    // two are often within timing noise)
+    b->mac_solo = ts < 0.97f * tp;
+    cache[k.str()] = b->mac_solo ? 1 : 0;
+    save_cache(cache);
     return HYENA_OK;
 }
 
@@ -471,6 +556,7 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
             if (!rc && hipEventCreate(&e) != hipSuccess) rc = set_error(HYENA_EHIP, "hyena_batch_create: event");
     if (flags & HYENA_BATCH_TUNE) rc = tune(b);
     if (!rc) rc = build_groups(b);
+    if (!rc && (flags & HYENA_BATCH_TUNE) && !b->groups.empty()) rc = tune_mac_phase(b);
     if (rc) {
         hyena_batch_destroy(b);
         return rc;
@@ -546,7 +632,8 @@ extern "C" int hyena_batch_phase_ms(const hyena_batch *b, float *ms) {
 
 extern "C" int hyena_batch_info(const hyena_batch *b, int *info, size_t n_info) {
     if (!b || !info) return set_error(HYENA_EINVAL, "hyena_batch_info: NULL argument");
-    std::vector<int> v = {b->ntt_fwd, b->ntt_inv, b->launches, (int)b->desc.size(), (int)b->groups.size()};
+    std::vector<int> v = {b->ntt_fwd, b->ntt_inv, b->launches, (int)b->desc.size(),
+                          b->mac_solo ? 0 : (int)b->groups.size()};
     for (int s : b->mac_sched) v.push_back(s);
     for (size_t i = 0; i < n_info; i++) info[i] = i < v.size() ? v[i] : -1;
     return HYENA_OK;

@@ -87,9 +87,17 @@ struct MacLdsShape {
     static constexpr int LDS_WORDS = NS * PROWS * 64;
 };
 
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 // One logical block (64-slot chunk x row tile x output tile) of a layer.
-template <int MT, int OT, int WR, int WO, int NS>
-__device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical, uint32_t *lds_flat) {
+// `after_loop` runs once the last group's products are accumulated, before
+// the reduction and the stores (the persistent kernel claims its next work
+// item there).
+template <int MT, int OT, int WR, int WO, int NS, class Hook = NoHook>
+__device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical, uint32_t *lds_flat,
+                                              const Hook &after_loop = Hook()) {
     using S = MacLdsShape<MT, OT, WR, WO, NS>;
     constexpr int MB = S::MB, OB = S::OB, RND = S::RND, PROWS = S::PROWS;
     static_assert(WR * WO == 4, "four waves per block");
@@ -175,6 +183,7 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
         }
         st = (st + 1 == NS) ? 0 : st + 1;
     }
+    after_loop();
 
     const uint32_t q = lc.q;
     const uint32_t slot = slot0 + lane;
