@@ -4,19 +4,19 @@
 // launches over all layers), the multiply-accumulate of every layer, and the
 // inverse NTT of every layer's outputs. Layers whose multiply-accumulate uses
 // the same LDS schedule share one persistent launch: a grid sized to the
-// chip's occupancy pulls (layer, tile) work items from eight per-XCD queues
-// (each queue a contiguous slice of the item list, so neighbouring tiles of one
-// slot chunk stay in one L2) and steals from the other queues when its own is
-// empty; uneven layers balance dynamically. The step can be captured once into
-// a hipGraph and replayed. An autotuner times the candidate MAC schedules per
-// layer and the NTT schedules per direction, and keeps the choices in a text
-// cache (HYENA_TUNE_CACHE) so later runs reuse them.
+// chip's occupancy pulls (layer, tile) work items from eight per-XCD queues,
+// each holding one eighth of every layer (contiguous per layer, so the tiles
+// of one slot chunk stay in one L2); uneven layers are balanced by
+// construction, every XCD doing the same share of each. The step can be
+// captured once into a hipGraph and replayed. An autotuner times the
+// candidate MAC schedules per layer, the persistent launch against per-layer
+// launches and the NTT schedules per direction, and keeps the choices in a
+// text cache (HYENA_TUNE_CACHE) so later runs reuse them.
 //
 // Every layer's inputs are independent here: the nonlinear layers between
 // convolutions run under MPC in the paper's protocol and are not part of this
 // server-side computation.
 #include <algorithm>
-#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -39,49 +39,57 @@ hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, 
 
 namespace {
 
-// Thread 0 draws the next work item: its own XCD's queue first, then the
-// other queues in turn; `total` once every queue is exhausted. Queue x holds
-// the items [bounds[x], bounds[x + 1]): contiguous slices of equal estimated
-// cost, so the XCDs run out of work together and seldom steal (a stolen tile
-// is fetched into a second L2).
-__device__ __forceinline__ uint32_t draw_item(uint32_t *counters, const uint32_t *bounds, uint32_t total,
-                                              uint32_t &qi) {
-    for (int tries = 0; tries < 8; tries++) {
-        const uint32_t lo = bounds[qi];
-        const uint32_t hi = bounds[qi + 1];
-        const uint32_t k = atomicAdd(&counters[qi], 1u);
-        if (lo + k < hi) return lo + k;
-        qi = (qi + 1) & 7u;
-    }
-    return total;
+// Work queues of the persistent launch: queue x (drained by the blocks of
+// XCD x: blocks are dealt to the XCDs round robin) holds the x-th eighth of
+// every layer's items, a contiguous slice per layer, layers in order. Each XCD
+// thus does the same share of every layer, in order: tiles that share input
+// rows are in flight together in one L2, and no XCD runs dry early, so there
+// is no stealing (a stolen tile would fetch its rows into a second L2).
+// Table: lfirst[n_layers + 1] (first item of each layer) followed by
+// qfirst[8][n_layers + 1] (position of each layer's slice within queue x).
+__device__ __forceinline__ uint32_t slice_start(uint32_t n, uint32_t x) { return (uint32_t)(((uint64_t)n * x) >> 3); }
+
+// Thread 0 claims the next item of its XCD's queue; `total` once it is empty.
+// `l` is the layer of the previous claim (claims only move forward).
+__device__ __forceinline__ uint32_t draw_item(uint32_t *counters, const uint32_t *lfirst, uint32_t n_layers,
+                                              uint32_t total, uint32_t x, uint32_t &l) {
+    const uint32_t *qf = lfirst + (n_layers + 1) * (1 + x);
+    const uint32_t c = atomicAdd(&counters[x], 1u);
+    if (c >= qf[n_layers]) return total;
+    while (c >= qf[l + 1]) l++;
+    return lfirst[l] + slice_start(lfirst[l + 1] - lfirst[l], x) + (c - qf[l]);
 }
 
 // three resident blocks per CU (at most 168 VGPRs), as the per-layer kernel
 template <int MT, int OT, int WR, int WO, int NS>
 __global__ void __launch_bounds__(256, 3)
 mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
-                      uint32_t *__restrict__ counters, const uint32_t *__restrict__ bounds, uint32_t total) {
+                      uint32_t *__restrict__ counters, uint32_t total) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
-    __shared__ uint32_t item_s[2];
-    uint32_t qi = blockIdx.x & 7u;  // queue drawn from (thread 0 only)
-    if (threadIdx.x == 0) item_s[0] = draw_item(counters, bounds, total, qi);
+    __shared__ uint32_t item_s[2], layer_s[2];  // claimed item and its layer, double buffered
+    const uint32_t x = blockIdx.x & 7u;  // this block's XCD and queue
+    uint32_t lq = 0;                     // layer of thread 0's last claim
+    if (threadIdx.x == 0) {
+        item_s[0] = draw_item(counters, first, n_layers, total, x, lq);
+        layer_s[0] = lq;
+    }
     __syncthreads();
     for (uint32_t round = 0;; round ^= 1) {
         // uniform across the block: lets the layer's arguments load as scalars
         const uint32_t it = __builtin_amdgcn_readfirstlane(item_s[round]);
         if (it >= total) break;
-        uint32_t l = 0;
-        while (l + 1 < n_layers && it >= first[l + 1]) l++;
-        l = __builtin_amdgcn_readfirstlane(l);
+        const uint32_t l = __builtin_amdgcn_readfirstlane(layer_s[round]);
         // the following item is claimed when this one's accumulation is done:
         // items then start in queue order, as the hardware dispatcher would
-        // start blocks (tiles that share input rows stay in flight together
-        // and hit in L2), and the claim's latency hides behind the epilogue
+        // start blocks, and the claim's latency hides behind the epilogue
         auto claim = [&]() {
-            if (threadIdx.x == 0) item_s[round ^ 1] = draw_item(counters, bounds, total, qi);
+            if (threadIdx.x == 0) {
+                item_s[round ^ 1] = draw_item(counters, first, n_layers, total, x, lq);
+                layer_s[round ^ 1] = lq;
+            }
         };
         mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds, claim);
-        __syncthreads();  // LDS stages and item_s[round ^ 1] ready for the next round
+        __syncthreads();  // LDS stages and the next claim ready for the next round
     }
 }
 
@@ -89,7 +97,7 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, const uint32_t *, uint32_t);
+typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, uint32_t);
 
 PersistentFn persistent_fn(const int *info) {
 #define HY_P(M, O, R, W, S)                                                          \
@@ -164,7 +172,7 @@ struct hyena_batch {
     bool mac_solo = false;  // autotuner: per-layer launches beat the persistent ones
     int per_cu = 0;  // persistent blocks per CU
     std::vector<uint32_t> solo;   // layers launched on their own
-    uint32_t *d_counters = nullptr;
+    uint32_t *d_counters = nullptr;  // per persistent launch: 8 queue counters
     uint32_t n_counters = 0;
     // one graph for the whole step, or one per phase when timing (events
     // between graph launches; event nodes inside a graph cannot be timed)
@@ -197,8 +205,7 @@ static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
         conv_sched_info(g.sched, info);
         PersistentFn fn = persistent_fn(info);
         hipLaunchKernelGGL(fn, dim3(g.grid), dim3(256), 0, s, (const MacArgs *)g.d_args,
-                           (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi,
-                           (const uint32_t *)(g.d_first + g.layers.size() + 1), g.total);
+                           (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi, g.total);
         launches++;
         // layers whose Walsh group is wider than the fused epilogue
         for (uint32_t l : g.layers) {
@@ -432,41 +439,28 @@ static int build_groups(hyena_batch *b) {
         }
         first.push_back(total);
         g.total = total;
-        // queue bounds: eight contiguous slices of equal estimated cost; an
-        // item costs its input groups (the loop trip) plus a few for the
-        // epilogue (reduction and stores)
+        // per-queue slice table (see draw_item): qfirst[x][j] = items of the
+        // layers before j in queue x
         {
-            std::vector<double> cost;
-            double sum = 0;
-            for (size_t j = 0; j < g.layers.size(); j++) {
-                cost.push_back((double)b->desc[g.layers[j]].n_groups + 2.0);
-                sum += cost.back() * (first[j + 1] - first[j]);
-            }
-            uint32_t x = 1;
-            double acc = 0;
-            std::vector<uint32_t> bounds = {0};
-            for (size_t j = 0; j < g.layers.size() && x < 8; j++) {
-                const uint32_t n = first[j + 1] - first[j];
-                while (x < 8 && acc + cost[j] * n >= sum * x / 8.0) {
-                    const double need = sum * x / 8.0 - acc;  // cost still missing in this layer
-                    uint32_t k = (uint32_t)std::ceil(need / cost[j]);
-                    k = std::min(k, n);
-                    bounds.push_back(std::max(bounds.back(), first[j] + k));
-                    x++;
+            const size_t nl = g.layers.size();
+            std::vector<uint32_t> qf(8 * (nl + 1), 0);
+            for (uint32_t x = 0; x < 8; x++)
+                for (size_t j = 0; j < nl; j++) {
+                    const uint64_t n = first[j + 1] - first[j];
+                    const uint32_t sz = (uint32_t)((n * (x + 1)) >> 3) - (uint32_t)((n * x) >> 3);
+                    qf[x * (nl + 1) + j + 1] = qf[x * (nl + 1) + j] + sz;
                 }
-                acc += cost[j] * n;
-            }
-            while (bounds.size() < 9) bounds.push_back(total);
-            bounds[8] = total;
-            first.insert(first.end(), bounds.begin(), bounds.end());
+            first.insert(first.end(), qf.begin(), qf.end());
         }
         int info[6];
         conv_sched_info(g.sched, info);
         int per_cu = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)persistent_fn(info), 256, 0));
         b->per_cu = per_cu;
+        // every XCD queue needs its own blocks: a multiple of 8, at least 8
         g.grid = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
         if (g.grid > total) g.grid = std::max<uint32_t>(total, 1);
+        g.grid = std::max<uint32_t>(8, (g.grid + 7) & ~7u);
         HIP_TRY(hipMalloc((void **)&g.d_args, sizeof(MacArgs) * args.size()));
         HIP_TRY(hipMalloc((void **)&g.d_first, sizeof(uint32_t) * first.size()));
         HIP_TRY(hipMemcpy(g.d_args, args.data(), sizeof(MacArgs) * args.size(), hipMemcpyHostToDevice));
