@@ -55,25 +55,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mac_persistent_vgg16_b8_n8192_counters.md")
-MAC_SOURCES = ["paper_2311_12519_amd/csrc/mac.h", "paper_2311_12519_amd/csrc/batch.hip"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mac_vgg16_b8_n8192_counters.md")
+MAC_SOURCES = ["paper_2311_12519_amd/csrc/mac.h", "paper_2311_12519_amd/csrc/batch.hip",
+               "paper_2311_12519_amd/csrc/conv.hip"]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent MAC from the committed rocprofv3
-    counter summary, or None when the MAC sources changed since it was taken."""
+def measured_traffic(kernel):
+    """HBM bytes per step of the MAC kernel from the committed rocprofv3
+    counter summary, or None when it was taken for another kernel or the MAC
+    sources changed since."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    vals = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch", "source_sha256_16")))
+    vals = dict(l.split(": ", 1) for l in text.splitlines()
+                if l.startswith(("traffic_bytes_per_step", "source_sha256_16", "kernel")))
+    if vals.get("kernel", "").strip() != kernel:
+        return None
     h = hashlib.sha256()
     for f in MAC_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if vals.get("source_sha256_16", "").strip() != h.hexdigest()[:16]:
         return None
-    return int(vals["traffic_bytes_per_launch"])
+    return int(vals["traffic_bytes_per_step"])
 
 
 def parse():
@@ -373,10 +378,16 @@ def main():
         # v_mad_u64_u32 per coeff-MAC
         t_hbm = (w_bytes + io_bytes) / (HBM_PEAK_GBS * 1e9)
         t_alu = total_macs / (VALU_PEAK_TOPS * 1e12)
-        common = {"kernel": "mac_persistent_kernel" if head_mode == "tuned" else "mac_lds_kernel",
-                  "traffic": measured_traffic() if head_mode == "tuned" and args.primes == 31 else None,
-                  "algorithmic_bytes_per_launch": (w_bytes + io_bytes) if head_mode == "tuned" else None,
-                  "launches_per_step": 1 if head_mode == "tuned" else len(layers),
+        # the tuned step runs the multiply-accumulate as one persistent launch
+        # unless its autotuner found per-layer launches clearly faster
+        persistent = head_mode == "tuned" and head["schedules"]["persistent_launches"] > 0
+        kernel = "mac_persistent_kernel" if persistent else "mac_lds_kernel"
+        launches = 1 if persistent else len(layers)
+        common = {"kernel": kernel,
+                  "traffic": measured_traffic(kernel) if head_mode == "tuned" and args.primes == 31 else None,
+                  "traffic_unit": "HBM bytes per step (all launches of the kernel)",
+                  "algorithmic_bytes_per_step": w_bytes + io_bytes,
+                  "launches_per_step": launches,
                   "roof_ms": {"hbm": t_hbm * 1e3, "alu": t_alu * 1e3},
                   "alu_achieved_TOPs": ach, "alu_peak_TOPs": VALU_PEAK_TOPS, "alu_frac": ach / VALU_PEAK_TOPS,
                   "hbm_achieved_GBs": mac_gbs, "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": mac_gbs / HBM_PEAK_GBS}
