@@ -377,7 +377,12 @@ static int tune(hyena_batch *b) {
     std::ostringstream nk;
     nk << arch << "|ntt|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt << "|polys" << (polys >= 4096 ? 4096 : polys);
     const std::string kf = nk.str() + "|fwd", ki = nk.str() + "|inv";
-    if (cache.count(kf) && cache.count(ki)) {
+    int nfirst = 0, ncount = 0;
+    hyena_ntt_schedules(c->N, &nfirst, &ncount);
+    auto valid_ntt = [&](const std::string &k) {
+        return cache.count(k) && cache[k] >= nfirst && cache[k] < nfirst + ncount;
+    };
+    if (valid_ntt(kf) && valid_ntt(ki)) {
         b->ntt_fwd = cache[kf];
         b->ntt_inv = cache[ki];
     } else {

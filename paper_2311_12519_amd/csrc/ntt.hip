@@ -16,6 +16,8 @@
 // residues per thread (16-byte accesses), so a transform of P passes needs
 // P - 1 LDS exchanges. LDS words are padded by one per 32 to break the bank
 // conflicts of the strided passes. Polynomials must be 16-byte aligned.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace {
@@ -253,23 +255,21 @@ __device__ __forceinline__ void inv_pass(uint32_t (&x)[1 << E_LOG], const uint32
     }
 }
 
+// Inverse transform in two parts. inv_front: from the first pass's registers
+// (loaded by load_runs: the first inverse pass is the forward's last, over
+// runs of consecutive residues) through every pass but the last, ending with
+// the last pass's residues in registers. inv_back: the last pass (uniform
+// twiddles, scalar loads; the N^{-1} factor) and the coalesced store.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
-__device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
-                                             const LimbConst &lc, uint32_t *lds) {
+__device__ __forceinline__ void inv_front(uint32_t (&x)[1 << (LOGN - LOGT)], const uint32_t *__restrict__ tw,
+                                          const LimbConst &lc, uint32_t *lds, uint32_t tid) {
     constexpr int E_LOG = LOGN - LOGT;
-    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
-    const uint32_t tid = threadIdx.x;
-    uint32_t x[E];
-    // the first inverse pass (the forward's last) reads runs straight from HBM
     if constexpr (E3 > 0) {
-        load_runs<LOGT, E_LOG, E3>(x, a, tid);
         inv_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, false, LAZY>(x, tw, lc, tid);
         to_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
         __syncthreads();
         from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-    } else {
-        load_runs<LOGT, E_LOG, E2>(x, a, tid);
     }
     inv_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, false, LAZY>(x, tw, lc, tid);
     if constexpr (E3 > 0) __syncthreads();
@@ -281,9 +281,27 @@ __device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uin
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     __syncthreads();
     from_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
+}
+
+template <int LOGN, int LOGT, int E0, bool LAZY>
+__device__ __forceinline__ void inv_back(uint32_t (&x)[1 << (LOGN - LOGT)], uint32_t *__restrict__ a,
+                                         const uint32_t *__restrict__ tw, const LimbConst &lc, uint32_t tid) {
+    constexpr int E_LOG = LOGN - LOGT;
+    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
     inv_pass<LOGN, LOGT, E_LOG, 0, E0, true, LAZY>(x, tw, lc, tid);
 #pragma unroll
     for (int r = 0; r < E; r++) a[tid + r * T] = x[r];
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__device__ __forceinline__ void ntt_inv_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
+                                             const LimbConst &lc, uint32_t *lds) {
+    constexpr int E_LOG = LOGN - LOGT;
+    const uint32_t tid = threadIdx.x;
+    uint32_t x[1 << E_LOG];
+    load_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
+    inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, lc, lds, tid);
+    inv_back<LOGN, LOGT, E0, LAZY>(x, a, tw, lc, tid);
 }
 
 // Polynomial p of a launch: a contiguous [P][L][N] array (segments == 1) or
@@ -319,6 +337,48 @@ ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32
     else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lt.c[limb].qinv_neg, lds);
 }
 
+// Persistent inverse transform: a grid of a few blocks per CU (a multiple of
+// L, so a block keeps one limb); block b transforms limb-polynomials b,
+// b + grid, ... and loads the next one's first-pass residues into registers
+// while it runs the current one's last pass and store. The last pass reads
+// only uniform (scalar) twiddles, so no vector-memory wait in it has to cover
+// the prefetch; the wait comes when the next polynomial starts.
+__device__ __forceinline__ uint32_t *seg_poly(const NttSegs &sg, uint32_t &s, uint32_t p, uint32_t N) {
+    while (s + 1 < sg.n && p >= sg.first[s + 1]) s++;
+    return sg.ptr[s] + (size_t)(p - sg.first[s]) * N;
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
+ntt_inv_persist_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
+    constexpr int EF = E3 > 0 ? E3 : E2;
+    __shared__ uint32_t lds[N + N / 32];
+    const uint32_t tid = threadIdx.x, total = sg.first[sg.n];
+    uint32_t p = blockIdx.x, s = 0;
+    if (p >= total) return;
+    uint32_t x[E], nx[E];
+    load_runs<LOGT, E_LOG, EF>(nx, seg_poly(sg, s, p, N), tid);
+    for (;;) {
+        // every segment starts at limb 0, so the limb is p mod L; looked up
+        // per polynomial so that the twiddle loads stay in the loop rather
+        // than holding registers across it
+        const uint32_t limb = __builtin_amdgcn_readfirstlane(p % L);
+        const uint32_t *tw = tw_all + (size_t)limb * N;
+        const LimbConst lc = lt.c[limb];
+        uint32_t *a = sg.ptr[s] + (size_t)(p - sg.first[s]) * N;
+#pragma unroll
+        for (int r = 0; r < E; r++) x[r] = nx[r];
+        const uint32_t pn = p + gridDim.x;
+        inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, lc, lds, tid);
+        if (pn < total) load_runs<LOGT, E_LOG, EF>(nx, seg_poly(sg, s, pn, N), tid);
+        inv_back<LOGN, LOGT, E0, LAZY>(x, a, tw, lc, tid);
+        if (pn >= total) break;
+        p = pn;
+        __syncthreads();  // the last pass's LDS reads precede the next exchange
+    }
+}
+
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
 hipError_t launch_sched(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
     const dim3 grid(sg.first[sg.n]), block(1u << LOGT);
@@ -333,16 +393,37 @@ hipError_t launch_sched(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStre
     return hipGetLastError();
 }
 
-// NTT schedules per ring degree: threads per polynomial and stages per pass.
+// Persistent schedule: forward transforms as launch_sched; inverse ones with
+// ntt_inv_persist_kernel on a grid of as many blocks as fit on the chip.
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_persist(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
+    if (!inv) return launch_sched<LOGN, LOGT, E0, E1, E2, E3>(sg, c, false, s);
+    const auto kern = c->lazy_ntt ? ntt_inv_persist_kernel<LOGN, LOGT, E0, E1, E2, E3, true>
+                                  : ntt_inv_persist_kernel<LOGN, LOGT, E0, E1, E2, E3, false>;
+    int n_cu = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 1 << LOGT, 0);
+    if (e != hipSuccess) return e;
+    const uint32_t total = sg.first[sg.n];
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(total, (uint32_t)std::max(1, per_cu) * n_cu));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1u << LOGT), 0, s, sg, inv ? c->d_iw : c->d_fw, c->lt, c->L);
+    return hipGetLastError();
+}
+
+// NTT schedules per ring degree: threads per polynomial, stages per pass and
+// whether the inverse runs persistently (next polynomial prefetched).
 struct NttSched {
-    int logn, logt, e0, e1, e2, e3;
+    int logn, logt, e0, e1, e2, e3, persist;
 };
 const NttSched kNtt[] = {
-    {10, 6, 4, 3, 3, 0},
-    {11, 7, 4, 4, 3, 0},
-    {12, 8, 4, 4, 4, 0}, {12, 7, 5, 5, 2, 0}, {12, 6, 6, 3, 3, 0},
-    {13, 8, 5, 4, 4, 0}, {13, 9, 4, 4, 4, 1}, {13, 7, 6, 6, 1, 0},
-    {14, 9, 5, 5, 4, 0}, {14, 10, 4, 4, 4, 2}, {14, 8, 6, 6, 2, 0},
+    {10, 6, 4, 3, 3, 0, 0},
+    {11, 7, 4, 4, 3, 0, 0},
+    {12, 8, 4, 4, 4, 0, 0}, {12, 7, 5, 5, 2, 0, 0}, {12, 6, 6, 3, 3, 0, 0},
+    {12, 8, 4, 4, 4, 0, 1}, {12, 7, 5, 5, 2, 0, 1},
+    {13, 8, 5, 4, 4, 0, 0}, {13, 9, 4, 4, 4, 1, 0}, {13, 7, 6, 6, 1, 0, 0},
+    {13, 8, 5, 4, 4, 0, 1}, {13, 9, 4, 4, 4, 1, 1},
+    {14, 9, 5, 5, 4, 0, 0}, {14, 10, 4, 4, 4, 2, 0}, {14, 8, 6, 6, 2, 0, 0},
+    {14, 9, 5, 5, 4, 0, 1}, {14, 10, 4, 4, 4, 2, 1},
 };
 const int kNumNtt = sizeof(kNtt) / sizeof(kNtt[0]);
 
@@ -353,12 +434,18 @@ hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hip
         case 2: return launch_sched<12, 8, 4, 4, 4, 0>(d, c, inv, s);
         case 3: return launch_sched<12, 7, 5, 5, 2, 0>(d, c, inv, s);
         case 4: return launch_sched<12, 6, 6, 3, 3, 0>(d, c, inv, s);
-        case 5: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 6: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 7: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
-        case 8: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 9: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
-        case 10: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
+        case 5: return launch_persist<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 6: return launch_persist<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 7: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 8: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 9: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
+        case 10: return launch_persist<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 11: return launch_persist<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 12: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 13: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 14: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
+        case 15: return launch_persist<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 16: return launch_persist<14, 10, 4, 4, 4, 2>(d, c, inv, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -370,8 +457,8 @@ int ntt_default_schedule(uint32_t logN) {
         case 10: return 0;
         case 11: return 1;
         case 12: return 2;
-        case 13: return 5;
-        case 14: return 9;
+        case 13: return 7;
+        case 14: return 13;
         default: return -1;
     }
 }

@@ -116,3 +116,32 @@ def test_batch_tuned_uses_cache(dev, setup, tmp_path, monkeypatch):
         d_out.fill_(0)
     hy.hyena_batch_run(b2)
     _check(items, bufs, "cached")
+
+
+def test_batch_every_ntt_schedule_from_cache(dev, setup, tmp_path, monkeypatch):
+    """Segmented NTT launches over all layers with every schedule, forced
+    through the tuning cache (persistent inverse schedules cross segment
+    boundaries inside one block's loop)."""
+    import torch
+    ctx, items = setup
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HYENA_TUNE_CACHE", str(cache))
+    bufs = _buffers(items)
+    pristine = [d_ct.clone() for d_ct, _ in bufs]
+    flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH
+    layers = [(it["d"], d_ct, it["d_wn"], d_out) for it, (d_ct, d_out) in zip(items, bufs)]
+    hy.hyena_batch_destroy(hy.hyena_batch_create(ctx, layers, flags))   # writes the cache
+    lines = cache.read_text().splitlines()
+    assert any("|ntt|" in ln for ln in lines)
+    for sid in hy.hyena_ntt_schedules(N):
+        text = "\n".join(ln.split("\t")[0] + "\t" + str(sid) if "|ntt|" in ln else ln for ln in lines) + "\n"
+        cache.write_text(text)
+        b = hy.hyena_batch_create(ctx, layers, flags)
+        info = hy.hyena_batch_info(b)
+        assert info["ntt_fwd"] == sid and info["ntt_inv"] == sid
+        for (d_ct, d_out), p in zip(bufs, pristine):
+            d_ct.copy_(p)
+            d_out.fill_(0)
+        hy.hyena_batch_run(b)
+        _check(items, bufs, ("ntt schedule", sid))
+        hy.hyena_batch_destroy(b)

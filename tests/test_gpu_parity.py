@@ -306,3 +306,30 @@ def test_every_ntt_schedule_matches_oracle(dev, N, L, bits):
             assert np.array_equal(got[1, i], want[i]), (sid, i)
         hy.hyena_ntt_sched(ctx, d, True, sid)
         assert np.array_equal(from_dev(d), a), sid
+
+
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 31), (4096, 2, 30), (16384, 2, 31)])
+def test_ntt_schedules_many_polys(dev, N, L, bits):
+    """Every schedule on more limb-polynomials than a persistent grid holds
+    (so persistent blocks loop and prefetch), against the default schedule
+    and, on sampled polynomials, against the oracle."""
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N * 7 + bits)
+    P = 2600 // L + 1                      # > 4 blocks x 256 CUs limb-polynomials
+    a = rand_res(rng, (P, L, N), ctx.primes)
+    d = to_dev(a)
+    hy.hyena_intt(ctx, d)
+    want_inv = from_dev(d)
+    d = to_dev(a)
+    hy.hyena_ntt(ctx, d)
+    want_fwd = from_dev(d)
+    for pi in (0, P // 2, P - 1):          # the default schedule against the oracle
+        for i, q in enumerate(ctx.primes):
+            assert np.array_equal(want_inv[pi, i], orc.intt(a[pi, i], q, ctx.psi[i])), (pi, i)
+    for sid in hy.hyena_ntt_schedules(N):
+        d = to_dev(a)
+        hy.hyena_ntt_sched(ctx, d, True, sid)
+        assert np.array_equal(from_dev(d), want_inv), ("inverse", sid)
+        d = to_dev(a)
+        hy.hyena_ntt_sched(ctx, d, False, sid)
+        assert np.array_equal(from_dev(d), want_fwd), ("forward", sid)
