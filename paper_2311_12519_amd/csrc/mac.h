@@ -31,10 +31,9 @@ __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
 __device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
     const uint32_t q = lc.q;
     const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
-    // hi mod q: floor(hi * mu32 / 2^32) is floor(hi / q) or one less
-    const uint32_t hr = csub(hi - __umulhi(hi, lc.mu32) * q, q);
-    // y = hi * 2^32 + lo = hr * r32 + lo (mod q), y < q * 2^32
-    const uint64_t y = mad64(hr, lc.r32, lo);
+    // y = hi * 2^32 + lo = hi * r32 + lo (mod q); with r32 = 2^32 mod q <= q - 1,
+    // y <= (r32 + 1)(2^32 - 1) < q * 2^32, the range Montgomery reduction takes
+    const uint64_t y = mad64(hi, lc.r32, lo);
     // Montgomery REDC: z = y * 2^-32 mod q in [0, 2q)
     const uint32_t m = (uint32_t)y * lc.qinv_neg;
     const uint64_t t = mad64(m, q, y);

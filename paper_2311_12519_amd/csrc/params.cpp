@@ -91,7 +91,6 @@ static void build_tables(hyena_ctx *c) {
         LimbConst &lc = c->lt.c[i];
         lc.q = q;
         lc.r32 = (uint32_t)((1ull << 32) % q);
-        lc.mu32 = (uint32_t)((1ull << 32) / q);
         uint32_t inv = 1;  // Newton iteration for q^{-1} mod 2^32
         for (int it = 0; it < 5; it++) inv *= 2u - q * inv;
         lc.qinv_neg = 0u - inv;
