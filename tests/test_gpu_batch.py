@@ -145,3 +145,41 @@ def test_batch_every_ntt_schedule_from_cache(dev, setup, tmp_path, monkeypatch):
         hy.hyena_batch_run(b)
         _check(items, bufs, ("ntt schedule", sid))
         hy.hyena_batch_destroy(b)
+
+
+@pytest.mark.parametrize("solo", [0, 1])
+def test_batch_mac_launch_form_from_cache(dev, setup, tmp_path, monkeypatch, solo):
+    """Both launch forms of the tuned multiply-accumulate phase (one persistent
+    launch, or one launch per layer), forced through the tuning cache."""
+    import torch
+    ctx, items = setup
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("HYENA_TUNE_CACHE", str(cache))
+    bufs = _buffers(items)
+    pristine = [d_ct.clone() for d_ct, _ in bufs]
+    flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH
+    layers = [(it["d"], d_ct, it["d_wn"], d_out) for it, (d_ct, d_out) in zip(items, bufs)]
+    hy.hyena_batch_destroy(hy.hyena_batch_create(ctx, layers, flags))   # writes the cache
+
+    def rewrite(tag, value):
+        lines = cache.read_text().splitlines()
+        assert any(tag in ln for ln in lines), tag
+        cache.write_text("\n".join(ln.split("\t")[0] + "\t" + str(value) if tag in ln else ln
+                                   for ln in lines) + "\n")
+
+    # an LDS schedule for every layer that admits one (the library re-tunes the
+    # others), so that a persistent group exists and its launch form is tuned
+    lds = [sid for sid, info in enumerate(hy.hyena_conv_schedules()) if info[0]][0]
+    rewrite("|mac|", lds)
+    hy.hyena_batch_destroy(hy.hyena_batch_create(ctx, layers, flags))   # tunes and caches the form
+    rewrite("|macphase|", solo)
+    b = hy.hyena_batch_create(ctx, layers, flags)
+    info = hy.hyena_batch_info(b)
+    assert (info["persistent_launches"] == 0) == bool(solo)
+    for rep in range(2):
+        for (d_ct, d_out), p in zip(bufs, pristine):
+            d_ct.copy_(p)
+            d_out.fill_(0)
+        hy.hyena_batch_run(b)
+        _check(items, bufs, ("launch form", solo, rep))
+    hy.hyena_batch_destroy(b)
