@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-alt-primes", action="store_true",
+                    help="skip the supplementary tuned run with primes below 2^30")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -424,7 +426,41 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(ctx, layers, orc, args.cpu_seconds)
+    if args.primes == 31 and args.mode in ("all", "tuned") and not args.no_alt_primes:
+        out["primes_below_2^30"] = alt_primes(args, hy, wl, torch, orc, layers, n_img, total_macs)
     print(json.dumps(out))
+
+
+def alt_primes(args, hy, wl, torch, orc, layers31, n_img, total_macs):
+    """Supplementary figure: the same workload and tuned path with three primes
+    below 2^30 (Harvey's lazy NTT butterflies, 15 products per fold); the
+    headline stays on the largest primes below 2^31."""
+    import argparse
+    for o in layers31:   # release the first run's buffers
+        o.ct = o.ct0 = o.out = o.d_wn = o.d_w = None
+    torch.cuda.empty_cache()
+    a = argparse.Namespace(**vars(args))
+    a.primes = 30
+    log("supplementary run: primes below 2^30 ...")
+    ctx, layers = setup(a, hy, wl, torch)
+    flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING
+    batch = hy.hyena_batch_create(ctx, [(o.desc_b, o.ct, o.d_wn, o.out) for o in layers], flags)
+    checked = 0 if args.no_check else check(ctx, layers, orc, torch, n_img, lambda: hy.hyena_batch_run(batch))
+    for _ in range(args.warmup):
+        hy.hyena_batch_run(batch)
+    torch.cuda.synchronize()
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hy.hyena_batch_run(batch)
+        phases.append(hy.hyena_batch_phase_ms(batch))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ph = np.array(phases).mean(axis=0)
+    log(f"primes < 2^30: {dt * 1e3:.2f} ms/step")
+    return {"ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt, "primes": ctx.primes,
+            "kernels_ms": {"ntt": float(ph[0]), "mac": float(ph[1]), "intt": float(ph[2])},
+            "parity_checked_outputs": checked, "schedules": hy.hyena_batch_info(batch)}
 
 
 if __name__ == "__main__":
