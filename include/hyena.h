@@ -188,8 +188,8 @@ int hyena_unpack_output(const hyena_conv_desc *desc, uint32_t N, const int32_t *
  *   Kw_{G,j,g} = c_n^{-1} (mod q_i) * (kernel polynomial of gw, as K above)
  *   d_wntt[G][j][g][i] = NTT_i(Kw_{G,j,g})      (same transform as hyena_ntt)
  * d_w: device int8 [Co][Ci][k][k] ([Co][1][k][k] if depthwise).
- * d_wntt: device uint32 [Co/c_n][c_n][w_groups][L][N]. For c_n = 1 this is the
- * NTT of K_{o,g}. Errors: EINVAL, EHIP.
+ * d_wntt: device uint32 [Co/c_n][c_n][w_groups][L][N], 16-byte aligned. For
+ * c_n = 1 this is the NTT of K_{o,g}. Errors: EINVAL, EHIP.
  */
 int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                          const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
@@ -221,7 +221,9 @@ int hyena_ntt_sched(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, int invers
                     hyena_stream_t stream);
 
 /*
- * The homomorphic convolution in the NTT domain (Sections 3.2, 4.1, 4.2.2):
+ * The homomorphic convolution in the NTT domain (the "Prior Art on Homomorphic
+ * Convolution" and "Enabling Output Channel Packing" sections, with the
+ * "Lazy Reduction" of the "Latency Optimization" section):
  *   A[b][tau][G][j][p][i][k] = sum_g ct[b][tau][g][p][i][k] * W[G][j][g][i][k]  mod q_i
  * accumulated lazily in 64 bits with one reduction per output coefficient.
  * With HYENA_FUSE_WHT (or c_n = 1) the output is already per output channel:
@@ -230,6 +232,7 @@ int hyena_ntt_sched(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, int invers
  * d_ct_ntt: device uint32 [batch][tiles][n_groups][2][L][N], NTT domain.
  * d_wntt:   device uint32 [Co/c_n][c_n][w_groups][L][N] (hyena_encode_weights).
  * d_out_ntt: device uint32 [batch][tiles][Co][2][L][N]; must not alias inputs.
+ * The three device arrays must be 16-byte aligned (copied in 16-byte pieces).
  * Errors: EINVAL, EHIP.
  */
 int hyena_conv(const hyena_ctx *ctx, const hyena_conv_desc *desc,
@@ -283,7 +286,7 @@ typedef struct {
     uint32_t *d_ct;               /* device [batch][tiles][n_groups][2][L][N], coefficient domain */
     const uint32_t *d_wntt;       /* device, from hyena_encode_weights */
     uint32_t *d_out;              /* device [batch][tiles][Co][2][L][N]; must not alias d_ct */
-} hyena_layer_io;
+} hyena_layer_io;                 /* all three 16-byte aligned */
 
 typedef struct hyena_batch hyena_batch;
 

@@ -543,6 +543,11 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
             return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
                                                " has a NULL buffer or an unplanned descriptor");
         }
+        if (((uintptr_t)io.d_ct | (uintptr_t)io.d_wntt | (uintptr_t)io.d_out) & 15u) {
+            delete b;
+            return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
+                                               " has a buffer that is not 16-byte aligned");
+        }
         b->desc.push_back(*io.desc);
         if (b->desc.back().batch == 0) b->desc.back().batch = 1;
         b->io.push_back(io);

@@ -377,6 +377,8 @@ hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, 
 int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
                 uint32_t *out, int sched, bool per_channel, hipStream_t s) {
     if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
+    if (((uintptr_t)ct | (uintptr_t)w | (uintptr_t)out) & 15u)
+        return set_error(HYENA_EINVAL, "hyena_conv: device arrays must be 16-byte aligned");
     if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
     if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
@@ -447,6 +449,7 @@ extern "C" int hyena_wht_pack(const hyena_ctx *c, uint32_t cn, const uint32_t *i
 extern "C" int hyena_encode_weights(const hyena_ctx *c, const hyena_conv_desc *d, const int8_t *d_w,
                                     uint32_t *d_wntt, hyena_stream_t s) {
     if (!c || !d || !d_w || !d_wntt) return set_error(HYENA_EINVAL, "hyena_encode_weights: NULL argument");
+    if ((uintptr_t)d_wntt & 15u) return set_error(HYENA_EINVAL, "hyena_encode_weights: d_wntt must be 16-byte aligned");
     if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_encode_weights: descriptor not planned");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_encode_weights: context was created host-only");
     const hipStream_t st = (hipStream_t)s;

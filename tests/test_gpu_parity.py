@@ -333,3 +333,24 @@ def test_ntt_schedules_many_polys(dev, N, L, bits):
         d = to_dev(a)
         hy.hyena_ntt_sched(ctx, d, False, sid)
         assert np.array_equal(from_dev(d), want_fwd), ("forward", sid)
+
+
+def test_misaligned_device_arrays_rejected(dev):
+    """16-byte alignment is checked on the host before any launch (EINVAL)."""
+    import torch
+    N, L = 8192, 3
+    ctx = ctx_for(N, L, 31)
+    d = hy.hyena_conv_plan(ctx, 16, 16, 16, 16, 3, c_n=1, flags=hy.HYENA_FUSE_WHT)
+    ct = torch.zeros(d.n_in * 2 * L * N + 4, dtype=torch.int32, device="cuda")
+    w = torch.zeros(hy.wntt_words(ctx, d) + 4, dtype=torch.int32, device="cuda")
+    out = torch.zeros(d.n_out * 2 * L * N + 4, dtype=torch.int32, device="cuda")
+    n_ct, n_w, n_out = ct.numel() - 4, w.numel() - 4, out.numel() - 4
+    with pytest.raises(hy.HyenaError, match="aligned"):
+        hy.hyena_conv(ctx, d, ct[1:1 + n_ct], w[:n_w], out[:n_out])
+    with pytest.raises(hy.HyenaError, match="aligned"):
+        hy.hyena_conv(ctx, d, ct[:n_ct], w[:n_w], out[1:1 + n_out])
+    with pytest.raises(hy.HyenaError, match="aligned"):
+        hy.hyena_ntt(ctx, ct[1:1 + 2 * L * N])
+    with pytest.raises(hy.HyenaError, match="aligned"):
+        hy.hyena_encode_weights(ctx, d, torch.zeros(16 * 16 * 9, dtype=torch.int8, device="cuda"), w[1:1 + n_w])
+    torch.cuda.synchronize()
