@@ -24,8 +24,11 @@ Three schedules of the same arithmetic are timed:
             captured in a hipGraph and replayed. Phase durations come from HIP
             events recorded on the launch stream between the graphs of the
             three phases (a timed run replays one graph per phase).
-Before timing, one step of each schedule is checked against the oracle on
-sampled output ciphertexts (every coefficient of both parts and all limbs).
+Before timing, one step of each schedule runs from pristine inputs and two
+output ciphertexts per layer (every coefficient of both parts and all limbs)
+are copied to the host; the cpu_baseline leg, the only part of this script
+that runs the oracle, computes those outputs (timed as part of the baseline)
+and checks every schedule's against them bit for bit.
 `value` is the tuned schedule's throughput.
 
 `--copy-calibration` instead times a plain 1 GiB device copy (the reference
@@ -202,8 +205,11 @@ class Events:
         return out
 
 
-def check(ctx, layers, orc, torch, images, step):
-    """One step from pristine inputs; sampled outputs vs the oracle."""
+def sample_outputs(ctx, layers, torch, images, step):
+    """One step from pristine inputs; host copies of two sampled output
+    ciphertexts per layer (the first and the last (tile, output channel) of
+    image layer mod images) and of the inputs they depend on. Nothing here
+    computes expected values: the cpu_baseline leg does, with the oracle."""
     N, L = ctx.N, ctx.L
     for o in layers:
         o.ct.copy_(o.ct0)
@@ -211,30 +217,49 @@ def check(ctx, layers, orc, torch, images, step):
     torch.cuda.synchronize()
     step()
     torch.cuda.synchronize()
-    checked = 0
+    got = []
     for li, o in enumerate(layers):
-        d = o.desc_b
-        pl = orc.plan(N, o.lay.H, o.lay.W, o.lay.Ci, o.lay.Co, o.lay.k)
-        b = li % images
-        ct = o.ct0[b].cpu().numpy().view(np.uint32).reshape(pl.tiles, pl.n_groups, 2, L, N)
-        sel = [(0, 0), (pl.tiles - 1, o.lay.Co - 1)]
-        want = orc.conv_products(pl, ct, o.w, ctx.primes, outputs=sel)
-        got = o.out[b].cpu().numpy().view(np.uint32).reshape(pl.tiles, o.lay.Co, 2, L, N)
-        for u, (tau, oc) in enumerate(sel):
-            if not np.array_equal(got[tau, oc], want[u]):
-                raise SystemExit(f"parity failure: layer {o.lay.name} image {b} output {(tau, oc)}")
-            checked += 1
-    return checked
+        b, tiles, co = li % images, o.desc_b.tiles, o.lay.Co
+        out = o.out[b].view(tiles, co, 2, L, N)
+        sel = [(0, 0), (tiles - 1, co - 1)]
+        got.append((sel, [out[t, oc].cpu().numpy().view(np.uint32).copy() for t, oc in sel]))
+    return got
 
 
-def cpu_baseline(ctx, layers, orc, seconds):
-    """The oracle (sparse-tap schoolbook, OpenMP) on a bounded sample: whole
-    output ciphertexts of successive layers, until about `seconds` of CPU time."""
-    import ctypes  # noqa: F401
+def sampled_inputs(ctx, layers, images):
+    """Host copies of the input ciphertexts (coefficient domain) and weights of
+    the sampled image of every layer."""
+    return [(o.lay, o.ct0[li % images].cpu().numpy().view(np.uint32).copy(), o.w) for li, o in enumerate(layers)]
+
+
+def cpu_baseline(ctx, layers, orc, seconds, parity):
+    """The oracle (sparse-tap schoolbook, OpenMP) on a bounded sample. It first
+    computes the sampled outputs of every parity set (inputs, primes and the
+    GPU outputs of each schedule, taken before timing) and checks each
+    schedule's outputs against them bit for bit, then continues on whole
+    output ciphertexts of random inputs until about `seconds` of CPU time.
+    Returns the baseline and the number of output ciphertexts checked."""
     N, L = ctx.N, ctx.L
-    rng = np.random.default_rng(0)
-    done_macs, spent, outs = 0, 0.0, 0
+    done_macs, spent, outs, checked = 0, 0.0, 0, 0
     names = []
+    for inputs, primes, by_mode in parity:
+        for li, (lay, ct, w) in enumerate(inputs):
+            pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k)
+            sel = next(iter(by_mode.values()))[li][0]
+            t0 = time.perf_counter()
+            want = orc.conv_products(pl, ct.reshape(pl.tiles, pl.n_groups, 2, L, N), w, primes, outputs=sel)
+            spent += time.perf_counter() - t0
+            done_macs += len(sel) * pl.n_groups * 2 * L * N
+            outs += len(sel)
+            names.append(lay.name)
+            for mode, samples in by_mode.items():
+                s_sel, got = samples[li]
+                for u, (tau, oc) in enumerate(s_sel):
+                    if not np.array_equal(got[u], want[u]):
+                        raise SystemExit(f"parity failure: {mode} layer {lay.name} output {(tau, oc)} "
+                                         f"primes {primes}")
+                    checked += 1
+    rng = np.random.default_rng(0)
     li = 0
     while spent < seconds and li < 64:
         o = layers[li % len(layers)]
@@ -255,7 +280,7 @@ def cpu_baseline(ctx, layers, orc, seconds):
     return {"value": done_macs / spent, "unit": "coeff-MAC/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{outs} output ciphertexts (all coefficients, 2 parts x {L} limbs) of VGG layers "
-                      f"{sorted(set(names))}, {spent:.1f} s"}
+                      f"{sorted(set(names))}, {spent:.1f} s"}, checked
 
 
 def copy_calibration(args, torch):
@@ -293,9 +318,6 @@ def main():
     n_img = args.images
     total_macs = sum(o.macs for o in layers) * n_img
     n_layer_runs = len(layers) * n_img
-    orc = None
-    if not args.no_check or not args.no_cpu_baseline:
-        import oracle as orc
 
     modes = ["plain", "batched", "tuned"] if args.mode == "all" else [args.mode]
     batch = None
@@ -309,11 +331,12 @@ def main():
         "batched": lambda: step_batched(ctx, layers, hy),
         "tuned": lambda: hy.hyena_batch_run(batch),
     }
-    checked = 0
+    # outputs of one step of every schedule, sampled before timing; the
+    # cpu_baseline leg checks them against the oracle
+    parity = []
     if not args.no_check:
-        for mode in modes:
-            checked += check(ctx, layers, orc, torch, n_img, steps[mode])
-        log(f"parity ok: {checked} sampled output ciphertexts bit-exact across {modes}")
+        parity.append((sampled_inputs(ctx, layers, n_img), ctx.primes,
+                       {m: sample_outputs(ctx, layers, torch, n_img, steps[m]) for m in modes}))
 
     res = {}
     for mode in modes:
@@ -375,9 +398,9 @@ def main():
                    "images": n_img, "layers": len(layers), "N": 8192, "L": 3, "prime_bits": args.primes,
                    "schedule": head_mode},
         "layers_per_s": head["layers_per_s"],
+        "parity_checked_outputs": 0,
         "encode_weights_ms": min(enc),
         "ms_per_step_with_encode": head["ms_per_step"] + min(enc),
-        "parity_checked_outputs": checked,
         "schedules": res,
     }
     if "plain" in res:
@@ -423,18 +446,32 @@ def main():
             "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": ach},
             "intt": {"ms": km["intt"], "GBs": intt_bytes / (km["intt"] * 1e-3) / 1e9},
         }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(ctx, layers, orc, args.cpu_seconds)
+    layers_host = [Layer() for _ in layers]   # what the random part of the baseline needs
+    for h, o in zip(layers_host, layers):
+        h.lay, h.w = o.lay, o.w
     if args.primes == 31 and args.mode in ("all", "tuned") and not args.no_alt_primes:
-        out["primes_below_2^30"] = alt_primes(args, hy, wl, torch, orc, layers, n_img, total_macs)
+        out["primes_below_2^30"], alt_parity = alt_primes(args, hy, wl, torch, layers, n_img, total_macs)
+        parity += alt_parity
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        log("cpu baseline (oracle), with the parity check of the sampled outputs ...")
+        out["cpu_baseline"], checked = cpu_baseline(ctx, layers_host, orc, args.cpu_seconds, parity)
+        n_alt = 0
+        if "primes_below_2^30" in out and alt_parity:
+            n_alt = sum(len(sel) for sel, _ in alt_parity[0][2]["tuned"])
+            out["primes_below_2^30"]["parity_checked_outputs"] = n_alt
+        out["parity_checked_outputs"] = checked - n_alt
+        log(f"parity ok: {checked} sampled output ciphertexts bit-exact")
+    else:
+        log("no oracle run: outputs not checked (--no-cpu-baseline)")
     print(json.dumps(out))
 
 
-def alt_primes(args, hy, wl, torch, orc, layers31, n_img, total_macs):
+def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):
     """Supplementary figure: the same workload and tuned path with three primes
     below 2^30 (Harvey's lazy NTT butterflies, 15 products per fold); the
-    headline stays on the largest primes below 2^31."""
+    headline stays on the largest primes below 2^31. Returns the figure and the
+    parity set for the cpu_baseline leg."""
     import argparse
     for o in layers31:   # release the first run's buffers
         o.ct = o.ct0 = o.out = o.d_wn = o.d_w = None
@@ -445,7 +482,10 @@ def alt_primes(args, hy, wl, torch, orc, layers31, n_img, total_macs):
     ctx, layers = setup(a, hy, wl, torch)
     flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING
     batch = hy.hyena_batch_create(ctx, [(o.desc_b, o.ct, o.d_wn, o.out) for o in layers], flags)
-    checked = 0 if args.no_check else check(ctx, layers, orc, torch, n_img, lambda: hy.hyena_batch_run(batch))
+    parity = []
+    if not args.no_check:
+        parity.append((sampled_inputs(ctx, layers, n_img), ctx.primes,
+                       {"tuned": sample_outputs(ctx, layers, torch, n_img, lambda: hy.hyena_batch_run(batch))}))
     for _ in range(args.warmup):
         hy.hyena_batch_run(batch)
     torch.cuda.synchronize()
@@ -458,9 +498,9 @@ def alt_primes(args, hy, wl, torch, orc, layers31, n_img, total_macs):
     dt = (time.perf_counter() - t0) / args.steps
     ph = np.array(phases).mean(axis=0)
     log(f"primes < 2^30: {dt * 1e3:.2f} ms/step")
-    return {"ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt, "primes": ctx.primes,
-            "kernels_ms": {"ntt": float(ph[0]), "mac": float(ph[1]), "intt": float(ph[2])},
-            "parity_checked_outputs": checked, "schedules": hy.hyena_batch_info(batch)}
+    return ({"ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt, "primes": ctx.primes,
+             "kernels_ms": {"ntt": float(ph[0]), "mac": float(ph[1]), "intt": float(ph[2])},
+             "parity_checked_outputs": 0, "schedules": hy.hyena_batch_info(batch)}, parity)
 
 
 if __name__ == "__main__":
