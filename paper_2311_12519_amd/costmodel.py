@@ -9,7 +9,7 @@ ceiling and whose worst-case noise still decrypts (the library's planner
 refuses the rest). Timing every candidate is the exhaustive search; a small
 FP32 MLP (8 -> 64 -> 64 -> 1, trained and evaluated by the library's own HIP
 kernels) predicts the log time of a candidate from its features and picks the
-argmin instead. The exhaustive table stays as the judge of the model's regret.
+argmin instead. The exhaustive table stays as the reference for the model's regret.
 
 Training data are timings of random layer shapes (never the evaluated
 network's own shapes), drawn by the same timer. Everything that touches the GPU
@@ -292,7 +292,7 @@ def collect(timer: Timer, shapes, per_shape: int, seed: int, log=None):
 
 
 def evaluate(timer: Timer, model: MLP, shapes, log=None):
-    """Exhaustive timing of every candidate of every layer (the judge), the
+    """Exhaustive timing of every candidate of every layer (the reference), the
     model's picks, and the default parameters."""
     rows = []
     t_search = 0.0
