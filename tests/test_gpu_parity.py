@@ -215,6 +215,8 @@ VARIANTS = [
     ("ci_lowered", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 8, 3), 1, 1, True, 5),
     ("cn32_unfusable", (8192, 3, 31), wl.Layer("t", 14, 14, 32, 32, 3), 32, 1, True, 0),
     ("primes30_batch8", (8192, 3, 30), wl.Layer("t", 28, 28, 64, 32, 3), 1, 8, True, 0),
+    # the largest ring and the most limbs the 128-bit ceiling allows (14 x 31 bits)
+    ("n16384_max_limbs", (16384, 14, 31), wl.Layer("t", 14, 14, 16, 8, 3), 2, 1, True, 0),
 ]
 
 
