@@ -446,6 +446,8 @@ def main():
             "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": ach},
             "intt": {"ms": km["intt"], "GBs": intt_bytes / (km["intt"] * 1e-3) / 1e9},
         }
+    if head_mode == "tuned":
+        out["kernels"]["wht"] = wht_bandwidth(ctx, layers, hy, torch)
     layers_host = [Layer() for _ in layers]   # what the random part of the baseline needs
     for h, o in zip(layers_host, layers):
         h.lay, h.w = o.lay, o.w
@@ -465,6 +467,30 @@ def main():
     else:
         log("no oracle run: outputs not checked (--no-cpu-baseline)")
     print(json.dumps(out))
+
+
+def wht_bandwidth(ctx, layers, hy, torch):
+    """The unfused Walsh-Hadamard pass (hyena_wht_pack) over the largest output
+    array of the step, in place, for c_n = 2 and 4 (every VGG-16 layer runs with
+    c_n = 1, so the step itself does not run it): algorithmic bytes = read and
+    write of every word once."""
+    o = max(layers, key=lambda x: x.out.numel())
+    res = {"array": o.lay.name, "bytes": o.out.numel() * 4}
+    for cn in (2, 4):
+        G = o.out.numel() // (cn * 2 * ctx.L * ctx.N)
+        hy.hyena_wht_pack(ctx, cn, o.out, o.out, G)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            hy.hyena_wht_pack(ctx, cn, o.out, o.out, G)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        gbs = 2 * o.out.numel() * 4 / (best * 1e-3) / 1e9
+        res[f"c_n={cn}"] = {"ms": best, "GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    return res
 
 
 def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):

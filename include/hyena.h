@@ -264,7 +264,8 @@ int hyena_conv_tiled(const hyena_ctx *ctx, const hyena_conv_desc *desc,
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by
  * the position: blocks are [2][L][N] ciphertexts (poly_words = 2*L*N).
- * d_in, d_out: device uint32 [G][c_n][2][L][N]; d_out may alias d_in.
+ * d_in, d_out: device uint32 [G][c_n][2][L][N], 16-byte aligned; d_out may
+ * alias d_in. Errors: EINVAL, EHIP.
  */
 int hyena_wht_pack(const hyena_ctx *ctx, uint32_t c_n, const uint32_t *d_in,
                    uint32_t *d_out, size_t G, hyena_stream_t stream);

@@ -137,30 +137,58 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
 
 // Standalone Walsh-Hadamard recombination: out[G][b] = sum_j H[b][j] in[G][j].
 // One thread per (G, word of a [2][L][N] block); c_n <= 64 residues in registers.
+// Walsh-Hadamard butterflies across groups of CN polynomials: block x covers
+// 256 x VW words of one ciphertext (all groups share the word layout), block
+// y strides over the groups, so no index needs a 64-bit division. Each thread
+// moves VW consecutive words of each of the CN polynomials (16-byte accesses
+// for CN <= 16; narrower for wider groups to bound registers).
 template <int CN>
-__global__ void __launch_bounds__(256) wht_kernel(const uint32_t *in, uint32_t *out,
-                                                  size_t G, uint32_t N, uint32_t L, LimbTable lt) {
-    const size_t words = (size_t)2 * L * N;
-    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= G * words) return;
-    const size_t gg = idx / words, wi = idx % words;
-    const uint32_t q = lt.c[(wi / N) % L].q;
-    const uint32_t *src = in + gg * CN * words + wi;
-    uint32_t y[CN];
-#pragma unroll
-    for (int j = 0; j < CN; j++) y[j] = src[(size_t)j * words];
-#pragma unroll
-    for (int h = 1; h < CN; h <<= 1)
+__global__ void __launch_bounds__(256) wht_kernel(const uint32_t *in, uint32_t *out, size_t G, uint32_t words,
+                                                  uint32_t logN, uint32_t L, LimbTable lt) {
+    constexpr int VW = CN <= 16 ? 4 : (CN <= 32 ? 2 : 1);
+    const uint32_t w0 = (blockIdx.x * 256 + threadIdx.x) * VW;
+    if (w0 >= words) return;
+    const uint32_t p = w0 >> logN;                 // polynomial within the ciphertext: part * L + limb
+    const uint32_t q = lt.c[p >= L ? p - L : p].q;
+    for (size_t gg = blockIdx.y; gg < G; gg += gridDim.y) {
+        const uint32_t *src = in + gg * CN * (size_t)words + w0;
+        uint32_t y[CN][VW];
 #pragma unroll
         for (int j = 0; j < CN; j++) {
-            if (j & h) continue;
-            const uint32_t u = y[j], v = y[j + h];
-            y[j] = csub(u + v, q);
-            y[j + h] = csub(u - v + q, q);
+            if constexpr (VW == 4) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(src + (size_t)j * words);
+                y[j][0] = v.x, y[j][1] = v.y, y[j][2] = v.z, y[j][3] = v.w;
+            } else if constexpr (VW == 2) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(src + (size_t)j * words);
+                y[j][0] = v.x, y[j][1] = v.y;
+            } else {
+                y[j][0] = src[(size_t)j * words];
+            }
         }
-    uint32_t *dst = out + gg * CN * words + wi;
 #pragma unroll
-    for (int j = 0; j < CN; j++) dst[(size_t)j * words] = y[j];
+        for (int h = 1; h < CN; h <<= 1)
+#pragma unroll
+            for (int j = 0; j < CN; j++) {
+                if (j & h) continue;
+#pragma unroll
+                for (int v = 0; v < VW; v++) {
+                    const uint32_t a = y[j][v], b = y[j + h][v];
+                    y[j][v] = csub(a + b, q);
+                    y[j + h][v] = csub(a - b + q, q);
+                }
+            }
+        uint32_t *dst = out + gg * CN * (size_t)words + w0;
+#pragma unroll
+        for (int j = 0; j < CN; j++) {
+            if constexpr (VW == 4) {
+                *reinterpret_cast<uint4 *>(dst + (size_t)j * words) = make_uint4(y[j][0], y[j][1], y[j][2], y[j][3]);
+            } else if constexpr (VW == 2) {
+                *reinterpret_cast<uint2 *>(dst + (size_t)j * words) = make_uint2(y[j][0], y[j][1]);
+            } else {
+                dst[(size_t)j * words] = y[j][0];
+            }
+        }
+    }
 }
 
 __global__ void fill_zero_kernel(uint32_t *p, size_t n) {
@@ -246,15 +274,16 @@ hipError_t launch_mac_lds(const MacArgs &base, hipStream_t s) {
 
 hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
                       hipStream_t s) {
-    const size_t n = G * 2 * (size_t)c->L * c->N;
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    const uint32_t words = 2 * c->L * c->N;        // one ciphertext; N is a multiple of 256
+    const uint32_t vw = cn <= 16 ? 4 : (cn <= 32 ? 2 : 1);
+    const dim3 grid((words / vw + 255) / 256, (unsigned)std::min<size_t>(G, 65535)), block(256);
     switch (cn) {
-        case 2: hipLaunchKernelGGL(wht_kernel<2>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
-        case 4: hipLaunchKernelGGL(wht_kernel<4>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
-        case 8: hipLaunchKernelGGL(wht_kernel<8>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
-        case 16: hipLaunchKernelGGL(wht_kernel<16>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
-        case 32: hipLaunchKernelGGL(wht_kernel<32>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
-        case 64: hipLaunchKernelGGL(wht_kernel<64>, grid, block, 0, s, in, out, G, c->N, c->L, c->lt); break;
+        case 2: hipLaunchKernelGGL(wht_kernel<2>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
+        case 4: hipLaunchKernelGGL(wht_kernel<4>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
+        case 8: hipLaunchKernelGGL(wht_kernel<8>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
+        case 16: hipLaunchKernelGGL(wht_kernel<16>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
+        case 32: hipLaunchKernelGGL(wht_kernel<32>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
+        case 64: hipLaunchKernelGGL(wht_kernel<64>, grid, block, 0, s, in, out, G, words, c->logN, c->L, c->lt); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -434,6 +463,8 @@ extern "C" int hyena_conv_tiled(const hyena_ctx *c, const hyena_conv_desc *d, co
 extern "C" int hyena_wht_pack(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
                               hyena_stream_t s) {
     if (!c || (G && (!in || !out))) return set_error(HYENA_EINVAL, "hyena_wht_pack: NULL argument");
+    if (((uintptr_t)in | (uintptr_t)out) & 15u)
+        return set_error(HYENA_EINVAL, "hyena_wht_pack: device arrays must be 16-byte aligned");
     if (cn == 0 || (cn & (cn - 1)) || cn > 64) return set_error(HYENA_EINVAL, "hyena_wht_pack: c_n must be 1..64, a power of two");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_wht_pack: context was created host-only");
     if (G == 0) return HYENA_OK;
