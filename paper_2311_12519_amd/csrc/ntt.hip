@@ -180,17 +180,12 @@ __device__ __forceinline__ void store_runs(const uint32_t (&x)[1 << E_LOG], uint
 // stride across lanes, the last writes runs of consecutive residues; the
 // passes between exchange residues through LDS.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
-__device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
-                                             uint32_t q, uint32_t qn, uint32_t *lds) {
+__device__ __forceinline__ void fwd_front(uint32_t (&x)[1 << (LOGN - LOGT)], const uint32_t *__restrict__ tw,
+                                          uint32_t q, uint32_t qn, uint32_t *lds, uint32_t tid) {
     constexpr int E_LOG = LOGN - LOGT;
-    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
+    constexpr int E = 1 << E_LOG;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
     static_assert(E0 == E_LOG && E1 <= E_LOG && E2 <= E_LOG && E3 <= E_LOG, "pass wider than the registers");
-    const uint32_t tid = threadIdx.x;
-    uint32_t x[E];
-    // pass 0: stages [0, E0); group of thread tid: indices tid + r*T
-#pragma unroll
-    for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
     fwd_pass<LOGN, LOGT, E_LOG, 0, E0, LAZY>(x, tw, q, qn, tid);
     to_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
     __syncthreads();
@@ -212,6 +207,23 @@ __device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uin
 #pragma unroll
         for (int r = 0; r < E; r++) x[r] = csub(min(x[r], x[r] - 2 * q), q);  // [0, 4q) -> [0, q)
     }
+}
+
+// Forward transform of one limb-polynomial a (N residues) by the block:
+// passes of E0, E1, E2 (, E3) stages; E0 = LOGN - LOGT is the register radix
+// (every thread holds 2^E0 residues). The first pass reads HBM with unit
+// stride across lanes, the last writes runs of consecutive residues; the
+// passes between exchange residues through LDS.
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
+                                             uint32_t q, uint32_t qn, uint32_t *lds) {
+    constexpr int E_LOG = LOGN - LOGT;
+    constexpr int T = 1 << LOGT, E = 1 << E_LOG;
+    const uint32_t tid = threadIdx.x;
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
+    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
     store_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
 }
 
@@ -379,6 +391,60 @@ ntt_inv_persist_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTabl
     }
 }
 
+// Streaming transform (either direction): a persistent grid whose size is a
+// multiple of L, so every block keeps one limb. The block copies that limb's
+// twiddles into LDS once; the passes then read twiddles from LDS (counted on
+// lgkmcnt), so the only vector-memory traffic is the polynomials themselves
+// and the next polynomial's residues can be loaded into registers as soon as
+// the current one's have arrived: its loads overlap the whole transform of the
+// current one, not only its last pass.
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY, bool INV>
+__global__ void __launch_bounds__(1 << LOGT)
+ntt_stream_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN, E_LOG = LOGN - LOGT, T = 1 << LOGT, E = 1 << E_LOG;
+    constexpr int EF = E3 > 0 ? E3 : E2;   // the pass over the last (forward) stages
+    __shared__ uint32_t lds[N + N / 32];
+    __shared__ uint32_t tws[N];
+    const uint32_t tid = threadIdx.x, total = sg.first[sg.n];
+    uint32_t p = blockIdx.x, s = 0;
+    if (p >= total) return;
+    // every segment starts at limb 0 and the grid is a multiple of L (or covers
+    // every polynomial in one round), so p mod L is the same for all of this
+    // block's polynomials
+    const uint32_t limb = __builtin_amdgcn_readfirstlane(p % L);
+    const uint32_t *tw = tw_all + (size_t)limb * N;
+    for (int i = tid; i < N; i += T) tws[i] = tw[i];
+    const LimbConst lc = lt.c[limb];
+    uint32_t x[E], nx[E];
+    auto load = [&](uint32_t (&v)[E], const uint32_t *a) {
+        if (INV) {
+            load_runs<LOGT, E_LOG, EF>(v, a, tid);
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; r++) v[r] = a[tid + r * T];
+        }
+    };
+    load(nx, seg_poly(sg, s, p, N));
+    __syncthreads();   // twiddles in LDS
+    for (;;) {
+        uint32_t *a = sg.ptr[s] + (size_t)(p - sg.first[s]) * N;
+#pragma unroll
+        for (int r = 0; r < E; r++) x[r] = nx[r];
+        const uint32_t pn = p + gridDim.x;
+        if (pn < total) load(nx, seg_poly(sg, s, pn, N));   // s now refers to pn
+        if (INV) {
+            inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tws, lc, lds, tid);
+            inv_back<LOGN, LOGT, E0, LAZY>(x, a, tws, lc, tid);
+        } else {
+            fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tws, lc.q, lc.qinv_neg, lds, tid);
+            store_runs<LOGT, E_LOG, EF>(x, a, tid);
+        }
+        if (pn >= total) break;
+        p = pn;
+        __syncthreads();  // this polynomial's LDS reads precede the next one's exchange
+    }
+}
+
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
 hipError_t launch_sched(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
     const dim3 grid(sg.first[sg.n]), block(1u << LOGT);
@@ -410,8 +476,31 @@ hipError_t launch_persist(const NttSegs &sg, const hyena_ctx *c, bool inv, hipSt
     return hipGetLastError();
 }
 
+// Streaming schedule: both directions with ntt_stream_kernel on as many
+// blocks as fit on the chip, rounded down to a multiple of L (one limb per
+// block), or one block per polynomial when there are fewer.
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_stream(const NttSegs &sg, const hyena_ctx *c, bool inv, hipStream_t s) {
+    void (*kern)(NttSegs, const uint32_t *, LimbTable, uint32_t);
+    if (c->lazy_ntt) kern = inv ? ntt_stream_kernel<LOGN, LOGT, E0, E1, E2, E3, true, true>
+                                : ntt_stream_kernel<LOGN, LOGT, E0, E1, E2, E3, true, false>;
+    else kern = inv ? ntt_stream_kernel<LOGN, LOGT, E0, E1, E2, E3, false, true>
+                    : ntt_stream_kernel<LOGN, LOGT, E0, E1, E2, E3, false, false>;
+    int n_cu = 0, per_cu = 0;
+    hipError_t e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, 1 << LOGT, 0);
+    if (e != hipSuccess) return e;
+    const uint32_t total = sg.first[sg.n], fit = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
+    const uint32_t grid = total <= fit ? total : std::max<uint32_t>(c->L, fit / c->L * c->L);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(1u << LOGT), 0, s, sg, inv ? c->d_iw : c->d_fw, c->lt, c->L);
+    return hipGetLastError();
+}
+
 // NTT schedules per ring degree: threads per polynomial, stages per pass and
-// whether the inverse runs persistently (next polynomial prefetched).
+// how the launch runs: 0 one block per limb-polynomial, 1 persistent inverse
+// (next polynomial prefetched during the last pass), 2 streaming, both
+// directions (twiddles in LDS, next polynomial prefetched for the whole
+// transform).
 struct NttSched {
     int logn, logt, e0, e1, e2, e3, persist;
 };
@@ -419,11 +508,11 @@ const NttSched kNtt[] = {
     {10, 6, 4, 3, 3, 0, 0},
     {11, 7, 4, 4, 3, 0, 0},
     {12, 8, 4, 4, 4, 0, 0}, {12, 7, 5, 5, 2, 0, 0}, {12, 6, 6, 3, 3, 0, 0},
-    {12, 8, 4, 4, 4, 0, 1}, {12, 7, 5, 5, 2, 0, 1},
+    {12, 8, 4, 4, 4, 0, 1}, {12, 7, 5, 5, 2, 0, 1}, {12, 8, 4, 4, 4, 0, 2}, {12, 7, 5, 5, 2, 0, 2},
     {13, 8, 5, 4, 4, 0, 0}, {13, 9, 4, 4, 4, 1, 0}, {13, 7, 6, 6, 1, 0, 0},
-    {13, 8, 5, 4, 4, 0, 1}, {13, 9, 4, 4, 4, 1, 1},
+    {13, 8, 5, 4, 4, 0, 1}, {13, 9, 4, 4, 4, 1, 1}, {13, 8, 5, 4, 4, 0, 2}, {13, 9, 4, 4, 4, 1, 2},
     {14, 9, 5, 5, 4, 0, 0}, {14, 10, 4, 4, 4, 2, 0}, {14, 8, 6, 6, 2, 0, 0},
-    {14, 9, 5, 5, 4, 0, 1}, {14, 10, 4, 4, 4, 2, 1},
+    {14, 9, 5, 5, 4, 0, 1}, {14, 10, 4, 4, 4, 2, 1}, {14, 9, 5, 5, 4, 0, 2}, {14, 10, 4, 4, 4, 2, 2},
 };
 const int kNumNtt = sizeof(kNtt) / sizeof(kNtt[0]);
 
@@ -436,16 +525,22 @@ hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hip
         case 4: return launch_sched<12, 6, 6, 3, 3, 0>(d, c, inv, s);
         case 5: return launch_persist<12, 8, 4, 4, 4, 0>(d, c, inv, s);
         case 6: return launch_persist<12, 7, 5, 5, 2, 0>(d, c, inv, s);
-        case 7: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 8: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 9: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
-        case 10: return launch_persist<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 11: return launch_persist<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 12: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 13: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
-        case 14: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
-        case 15: return launch_persist<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 16: return launch_persist<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 7: return launch_stream<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 8: return launch_stream<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 9: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 10: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 11: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
+        case 12: return launch_persist<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 13: return launch_persist<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 14: return launch_stream<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 15: return launch_stream<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 16: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 17: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 18: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
+        case 19: return launch_persist<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 20: return launch_persist<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 21: return launch_stream<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 22: return launch_stream<14, 10, 4, 4, 4, 2>(d, c, inv, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -457,8 +552,8 @@ int ntt_default_schedule(uint32_t logN) {
         case 10: return 0;
         case 11: return 1;
         case 12: return 2;
-        case 13: return 7;
-        case 14: return 13;
+        case 13: return 9;
+        case 14: return 17;
         default: return -1;
     }
 }
