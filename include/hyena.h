@@ -186,10 +186,13 @@ int hyena_unpack_output(const hyena_conv_desc *desc, uint32_t N, const int32_t *
  * For each Walsh group G, Walsh index j and input group g:
  *   gw[G*c_n+j] = sum_b H[j][b] f[G*c_n+b]     (Sylvester H_{c_n})
  *   Kw_{G,j,g} = c_n^{-1} (mod q_i) * (kernel polynomial of gw, as K above)
- *   d_wntt[G][j][g][i] = NTT_i(Kw_{G,j,g})      (same transform as hyena_ntt)
+ *   d_wntt[G][j][g][i] = 2^32 NTT_i(Kw_{G,j,g}) mod q_i
+ * (same transform as hyena_ntt; the factor 2^32 is the Montgomery form that
+ * lets hyena_conv finish each output with a single Montgomery reduction, so
+ * weights given to hyena_conv from elsewhere must carry it too).
  * d_w: device int8 [Co][Ci][k][k] ([Co][1][k][k] if depthwise).
  * d_wntt: device uint32 [Co/c_n][c_n][w_groups][L][N], 16-byte aligned. For
- * c_n = 1 this is the NTT of K_{o,g}. Errors: EINVAL, EHIP.
+ * c_n = 1 this is 2^32 times the NTT of K_{o,g}. Errors: EINVAL, EHIP.
  */
 int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                          const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
@@ -230,7 +233,8 @@ int hyena_ntt_sched(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, int invers
  *   Y[.][G*c_n+b] = sum_j H[b][j] A[.][G][j]  mod q_i,
  * otherwise it holds the Walsh components A and hyena_wht_pack finishes.
  * d_ct_ntt: device uint32 [batch][tiles][n_groups][2][L][N], NTT domain.
- * d_wntt:   device uint32 [Co/c_n][c_n][w_groups][L][N] (hyena_encode_weights).
+ * d_wntt:   device uint32 [Co/c_n][c_n][w_groups][L][N] (hyena_encode_weights:
+ *           W times 2^32 mod q_i).
  * d_out_ntt: device uint32 [batch][tiles][Co][2][L][N]; must not alias inputs.
  * The three device arrays must be 16-byte aligned (copied in 16-byte pieces).
  * Errors: EINVAL, EHIP.

@@ -198,13 +198,16 @@ __global__ void fill_zero_kernel(uint32_t *p, size_t n) {
 
 // Scatter the taps of every Walsh kernel polynomial into a zeroed
 // [Co][w_groups][L][N] array (coefficient domain). Thread per (o, tap):
-//   value = c_n^{-1} * sum_b H[j][b] f[G*c_n+b][ch][di][dj]  mod q_i,
+//   value = c_n^{-1} 2^32 * sum_b H[j][b] f[G*c_n+b][ch][di][dj]  mod q_i,
 //   exponent O - c'*Bt - di*Wp - dj,  o = G*c_n + j,  ch = g*ci + c'.
+// The factor 2^32 puts the kernel polynomials in Montgomery form (the NTT is
+// linear, so their transforms carry it too): the multiply-accumulate's one
+// Montgomery reduction per output then removes it and returns the plain sum.
 struct EncArgs {
     const int8_t *w;
     uint32_t *out;
     uint32_t N, L, Co, Ci, k, ci, Bt, Wp, O, n_groups, w_groups, c_n, depthwise;
-    uint32_t cninv[HYENA_MAX_LIMBS];
+    uint32_t wscale[HYENA_MAX_LIMBS];   // c_n^{-1} 2^32 mod q_i
     LimbTable lt;
 };
 
@@ -243,7 +246,7 @@ __global__ void encode_scatter_kernel(EncArgs a) {
         const uint32_t q = a.lt.c[i].q;
         const int64_t v = (int64_t)gsum % (int64_t)q;
         const uint32_t vr = (uint32_t)(v < 0 ? v + q : v);
-        const uint32_t val = (uint32_t)((uint64_t)vr * a.cninv[i] % q);
+        const uint32_t val = (uint32_t)((uint64_t)vr * a.wscale[i] % q);
         a.out[(((size_t)o * a.w_groups + gslot) * a.L + i) * a.N + e] = val;
     }
 }
@@ -505,7 +508,7 @@ extern "C" int hyena_encode_weights(const hyena_ctx *c, const hyena_conv_desc *d
     a.c_n = d->c_n ? d->c_n : 1;
     a.depthwise = d->depthwise;
     a.lt = c->lt;
-    for (uint32_t i = 0; i < c->L; i++) a.cninv[i] = h_powmod(a.c_n, c->q[i] - 2, c->q[i]);
+    for (uint32_t i = 0; i < c->L; i++) a.wscale[i] = to_montgomery(h_powmod(a.c_n, c->q[i] - 2, c->q[i]), c->q[i]);
     const size_t taps = (size_t)d->Co * (d->depthwise ? a.c_n : d->Ci) * d->k * d->k;
     hipLaunchKernelGGL(encode_scatter_kernel, dim3((unsigned)((taps + 255) / 256)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();

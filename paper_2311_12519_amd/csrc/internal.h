@@ -15,7 +15,6 @@ struct LimbConst {
     uint32_t q;        // prime modulus, 2^29 < q < 2^31
     uint32_t r32;      // 2^32 mod q
     uint32_t qinv_neg; // -q^{-1} mod 2^32 (Montgomery)
-    uint32_t r32s;     // Shoup companion of r32: floor(r32 * 2^32 / q)
     uint32_t ninv;     // N^{-1} mod q
     uint32_t ninv_m;   // N^{-1} 2^32 mod q (Montgomery form)
     uint32_t fold;     // products that fit between two folds of a lazy accumulator

@@ -19,27 +19,23 @@ namespace {
 
 __device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t q) { return min(x, x - q); }
 
-__device__ __forceinline__ uint32_t shoup(uint32_t a, uint32_t w, uint32_t ws, uint32_t q) {
-    return csub(a * w - __umulhi(a, ws) * q, q);
-}
-
 __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
     return (uint64_t)a * b + c;  // one v_mad_u64_u32
 }
 
-// Exact reduction of a 64-bit accumulator to [0, q).
+// Exact reduction of a 64-bit accumulator to [0, q), times 2^-32. The encoded
+// weights carry a factor 2^32 (Montgomery form, applied once when they are
+// encoded), so for acc = sum ct * (w 2^32) this returns sum ct * w mod q.
 __device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
     const uint32_t q = lc.q;
     const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
     // y = hi * 2^32 + lo = hi * r32 + lo (mod q); with r32 = 2^32 mod q <= q - 1,
     // y <= (r32 + 1)(2^32 - 1) < q * 2^32, the range Montgomery reduction takes
     const uint64_t y = mad64(hi, lc.r32, lo);
-    // Montgomery REDC: z = y * 2^-32 mod q in [0, 2q)
+    // Montgomery REDC: y * 2^-32 mod q in [0, 2q)
     const uint32_t m = (uint32_t)y * lc.qinv_neg;
     const uint64_t t = mad64(m, q, y);
-    const uint32_t z = csub((uint32_t)(t >> 32), q);
-    // times 2^32 mod q
-    return shoup(z, lc.r32, lc.r32s, q);
+    return csub((uint32_t)(t >> 32), q);
 }
 
 __device__ __forceinline__ uint64_t fold(uint64_t acc, uint32_t r32) {

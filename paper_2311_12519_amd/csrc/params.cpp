@@ -94,7 +94,6 @@ static void build_tables(hyena_ctx *c) {
         uint32_t inv = 1;  // Newton iteration for q^{-1} mod 2^32
         for (int it = 0; it < 5; it++) inv *= 2u - q * inv;
         lc.qinv_neg = 0u - inv;
-        lc.r32s = shoup_companion(lc.r32, q);
         lc.ninv = h_powmod(N, q - 2, q);
         lc.ninv_m = to_montgomery(lc.ninv, q);
         lc.w1n_m = to_montgomery(h_mulmod(c->h_iw[(size_t)i * N + 1], lc.ninv, q), q);

@@ -124,8 +124,9 @@ def test_encode_weights_matches_oracle(dev, c_n, dw):
         for slot, g in enumerate(gs):
             Kw = orc.walsh_kernel_residues(pl, w, c_n, ctx.primes, G, j, g)
             for i, q in enumerate(ctx.primes):
-                want = orc.ntt(Kw[i], q, ctx.psi[i])
-                assert np.array_equal(got[o, 0 if dw else slot, i], want), (o, g, i)
+                # the encoding is documented as 2^32 times the NTT (Montgomery form)
+                want = (orc.ntt(Kw[i], q, ctx.psi[i]).astype(np.uint64) << np.uint64(32)) % np.uint64(q)
+                assert np.array_equal(got[o, 0 if dw else slot, i], want.astype(np.uint32)), (o, g, i)
 
 
 # ---------------------------------------------------------------- Walsh-Hadamard
