@@ -232,6 +232,17 @@ def sampled_inputs(ctx, layers, images):
     return [(o.lay, o.ct0[li % images].cpu().numpy().view(np.uint32).copy(), o.w) for li, o in enumerate(layers)]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(ctx, layers, orc, seconds, parity):
     """The oracle (sparse-tap schoolbook, OpenMP) on a bounded sample. It first
     computes the sampled outputs of every parity set (inputs, primes and the
@@ -278,7 +289,7 @@ def cpu_baseline(ctx, layers, orc, seconds, parity):
         names.append(o.lay.name)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": done_macs / spent, "unit": "coeff-MAC/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "sample": f"{outs} output ciphertexts (all coefficients, 2 parts x {L} limbs) of VGG layers "
                       f"{sorted(set(names))}, {spent:.1f} s"}, checked
 
