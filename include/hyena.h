@@ -298,10 +298,13 @@ typedef struct hyena_batch hyena_batch;
 #define HYENA_BATCH_PERSISTENT 0x1u /* layers sharing an LDS schedule run in one persistent launch */
 #define HYENA_BATCH_GRAPH 0x2u      /* the step is captured once into a hipGraph and replayed */
 #define HYENA_BATCH_TUNE 0x4u       /* MAC schedule per layer and NTT schedule per direction chosen
-                                       by timing, and with HYENA_BATCH_PERSISTENT whether the
-                                       persistent launch or one launch per layer runs the
-                                       multiply-accumulate phase; choices cached in the file named
-                                       by the environment variable HYENA_TUNE_CACHE when set */
+                                       by timing (the forward on the inputs, the inverse on the
+                                       outputs; inverse schedules within 5% of each other are
+                                       timed again right after a multiply-accumulate phase, as
+                                       they run in a step), and with HYENA_BATCH_PERSISTENT
+                                       whether the persistent launch or one launch per layer runs
+                                       the multiply-accumulate phase; choices cached in the file
+                                       named by the environment variable HYENA_TUNE_CACHE when set */
 #define HYENA_BATCH_TIMING 0x8u     /* record HIP events between the phases of every run for
                                        hyena_batch_phase_ms (with HYENA_BATCH_GRAPH: one graph
                                        per phase, events between their launches) */
@@ -310,7 +313,8 @@ typedef struct hyena_batch hyena_batch;
  * Build a batched step over n_layers layers. Copies the descriptors and keeps
  * the buffer pointers (the caller keeps the buffers alive until
  * hyena_batch_destroy). With HYENA_BATCH_TUNE the schedules are timed on the
- * given buffers (their contents are left unchanged). Allocates small device
+ * given buffers: the input ciphertexts and the weights are left unchanged, the
+ * output arrays are overwritten (as by every step). Allocates small device
  * tables. Errors: EINVAL, EHIP, ENOMEM.
  */
 int hyena_batch_create(const hyena_ctx *ctx, const hyena_layer_io *layers, uint32_t n_layers,

@@ -170,6 +170,10 @@ struct hyena_batch {
     };
     std::vector<Group> groups;
     bool mac_solo = false;  // autotuner: per-layer launches beat the persistent ones
+    // autotuner: inverse-NTT schedules within 5% of the fastest when timed on
+    // their own, and the cache key of the choice (settled in step context)
+    std::vector<int> inv_cands;
+    std::string inv_key;
     int per_cu = 0;  // persistent blocks per CU
     std::vector<uint32_t> solo;   // layers launched on their own
     uint32_t *d_counters = nullptr;  // per persistent launch: 8 queue counters
@@ -364,19 +368,25 @@ static int tune(hyena_batch *b) {
     }
     for (size_t l = 0; l < b->desc.size(); l++)
         cache[layer_key(c, arch, b->desc[l]) + (persistent ? "|persistent" : "")] = b->mac_sched[l];
-    // NTT schedules per direction over every layer's inputs (a forward and an
-    // inverse transform in a row leave the data unchanged)
-    std::vector<uint32_t *> ptrs;
-    std::vector<size_t> P;
-    size_t polys = 0;
+    // NTT schedules per direction, each timed alone on the arrays it
+    // transforms in a step: the forward on every layer's inputs (an untimed
+    // default inverse after each timed forward restores them), the inverse on
+    // every layer's outputs (overwritten by every step anyway)
+    std::vector<uint32_t *> pin, pout;
+    std::vector<size_t> Pin, Pout;
+    size_t polys_in = 0, polys_out = 0;
     for (size_t l = 0; l < b->desc.size(); l++) {
-        ptrs.push_back(b->io[l].d_ct);
-        P.push_back((size_t)b->desc[l].batch * b->desc[l].n_in * 2);
-        polys += P.back();
+        pin.push_back(b->io[l].d_ct);
+        Pin.push_back((size_t)b->desc[l].batch * b->desc[l].n_in * 2);
+        polys_in += Pin.back();
+        pout.push_back(b->io[l].d_out);
+        Pout.push_back((size_t)b->desc[l].batch * b->desc[l].n_out * 2);
+        polys_out += Pout.back();
     }
     std::ostringstream nk;
-    nk << arch << "|ntt|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt << "|polys" << (polys >= 4096 ? 4096 : polys);
-    const std::string kf = nk.str() + "|fwd", ki = nk.str() + "|inv";
+    nk << arch << "|ntt|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt;
+    const std::string kf = nk.str() + "|polys" + std::to_string(std::min<size_t>(polys_in, 4096)) + "|fwd";
+    const std::string ki = nk.str() + "|polys" + std::to_string(std::min<size_t>(polys_out, 4096)) + "|inv";
     int nfirst = 0, ncount = 0;
     hyena_ntt_schedules(c->N, &nfirst, &ncount);
     auto valid_ntt = [&](const std::string &k) {
@@ -386,21 +396,44 @@ static int tune(hyena_batch *b) {
         b->ntt_fwd = cache[kf];
         b->ntt_inv = cache[ki];
     } else {
-        int first = 0, count = 0;
-        hyena_ntt_schedules(c->N, &first, &count);
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        // best of 3 timed runs of `timed` after one warm-up; `after` (untimed)
+        // follows every run
+        auto best_of = [&](auto timed, auto after) {
+            float best = 1e30f;
+            for (int r = 0; r < 4; r++) {
+                (void)hipEventRecord(e0, s);
+                timed();
+                (void)hipEventRecord(e1, s);
+                after();
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (r > 0) best = std::min(best, ms);
+            }
+            return best;
+        };
         float bf = 1e30f, bi = 1e30f;
-        for (int sid = first; sid < first + count; sid++) {
-            const float tf = time_best(s, 2, [&] {
-                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), false, sid, s);
-                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), true, -1, s);
-            });
-            const float ti = time_best(s, 2, [&] {
-                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), false, -1, s);
-                launch_ntt_segs(c, ptrs.data(), P.data(), (uint32_t)ptrs.size(), true, sid, s);
-            });
+        std::vector<std::pair<float, int>> inv_times;
+        for (int sid = nfirst; sid < nfirst + ncount; sid++) {
+            const float tf = best_of(
+                [&] { launch_ntt_segs(c, pin.data(), Pin.data(), (uint32_t)pin.size(), false, sid, s); },
+                [&] { launch_ntt_segs(c, pin.data(), Pin.data(), (uint32_t)pin.size(), true, -1, s); });
+            const float ti = best_of(
+                [&] { launch_ntt_segs(c, pout.data(), Pout.data(), (uint32_t)pout.size(), true, sid, s); },
+                [] {});
             if (tf < bf) { bf = tf; b->ntt_fwd = sid; }
             if (ti < bi) { bi = ti; b->ntt_inv = sid; }
+            inv_times.emplace_back(ti, sid);
         }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::sort(inv_times.begin(), inv_times.end());
+        for (const auto &t : inv_times)
+            if (t.first <= 1.05f * bi) b->inv_cands.push_back(t.second);
+        b->inv_key = ki;
         cache[kf] = b->ntt_fwd;
         cache[ki] = b->ntt_inv;
         dirty = true;
@@ -511,6 +544,56 @@ static int tune_mac_phase(hyena_batch *b) {
     return HYENA_OK;
 }
 
+// Autotuner, third stage: in a step the inverse transforms run right after
+// the multiply-accumulate, whose output writes they then read; schedules that
+// time alike on their own can differ there by several percent. Time each
+// close candidate after an untimed multiply-accumulate phase and keep the
+// fastest.
+static int tune_inv_in_step(hyena_batch *b) {
+    const hyena_ctx *c = b->ctx;
+    std::vector<uint32_t *> pout;
+    std::vector<size_t> Pout;
+    for (size_t l = 0; l < b->desc.size(); l++) {
+        pout.push_back(b->io[l].d_out);
+        Pout.push_back((size_t)b->desc[l].batch * b->desc[l].n_out * 2);
+    }
+    hipStream_t s;
+    HIP_TRY(hipStreamCreate(&s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = HYENA_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = set_error(HYENA_EHIP, "hyena_batch_create: event");
+    float best = 1e30f;
+    int best_sid = b->ntt_inv;
+    for (int sid : b->inv_cands) {
+        float t = 1e30f;
+        for (int r = 0; r < 4 && !rc; r++) {
+            int n = 0;
+            rc = issue_mac_phase(b, s, n);
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            rc = launch_ntt_segs(c, pout.data(), Pout.data(), (uint32_t)pout.size(), true, sid, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t = std::min(t, ms);
+        }
+        if (rc) break;
+        if (t < best) { best = t; best_sid = sid; }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (rc) return rc;
+    b->ntt_inv = best_sid;
+    auto cache = load_cache();
+    cache[b->inv_key] = best_sid;
+    save_cache(cache);
+    return HYENA_OK;
+}
+
 extern "C" void hyena_batch_destroy(hyena_batch *b) {
     if (!b) return;
     for (int i = 0; i < 3; i++) {
@@ -561,6 +644,7 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
     if (flags & HYENA_BATCH_TUNE) rc = tune(b);
     if (!rc) rc = build_groups(b);
     if (!rc && (flags & HYENA_BATCH_TUNE) && !b->groups.empty()) rc = tune_mac_phase(b);
+    if (!rc && (flags & HYENA_BATCH_TUNE) && b->inv_cands.size() > 1) rc = tune_inv_in_step(b);
     if (rc) {
         hyena_batch_destroy(b);
         return rc;
