@@ -396,9 +396,12 @@ static int tune(hyena_batch *b) {
         b->ntt_fwd = cache[kf];
         b->ntt_inv = cache[ki];
     } else {
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            (void)hipStreamDestroy(s);
+            return set_error(HYENA_EHIP, "hyena_batch_create: event");
+        }
         // best of 3 timed runs of `timed` after one warm-up; `after` (untimed)
         // follows every run
         auto best_of = [&](auto timed, auto after) {
@@ -499,11 +502,14 @@ static int build_groups(hyena_batch *b) {
         g.grid = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
         if (g.grid > total) g.grid = std::max<uint32_t>(total, 1);
         g.grid = std::max<uint32_t>(8, (g.grid + 7) & ~7u);
-        HIP_TRY(hipMalloc((void **)&g.d_args, sizeof(MacArgs) * args.size()));
-        HIP_TRY(hipMalloc((void **)&g.d_first, sizeof(uint32_t) * first.size()));
-        HIP_TRY(hipMemcpy(g.d_args, args.data(), sizeof(MacArgs) * args.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(g.d_first, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
+        // owned by the batch before allocating, so hyena_batch_destroy frees
+        // whatever was allocated if a later call fails
         b->groups.push_back(g);
+        hyena_batch::Group &G = b->groups.back();
+        HIP_TRY(hipMalloc((void **)&G.d_args, sizeof(MacArgs) * args.size()));
+        HIP_TRY(hipMalloc((void **)&G.d_first, sizeof(uint32_t) * first.size()));
+        HIP_TRY(hipMemcpy(G.d_args, args.data(), sizeof(MacArgs) * args.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(G.d_first, first.data(), sizeof(uint32_t) * first.size(), hipMemcpyHostToDevice));
     }
     return HYENA_OK;
 }
@@ -667,9 +673,11 @@ static int capture(hyena_batch *b, int phase, int slot) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
     }
-    if (e != hipSuccess || e2 != hipSuccess)
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
         return set_error(HYENA_EHIP, std::string("hyena_batch_run: capture failed: ") +
                                          hipGetErrorString(e != hipSuccess ? e : e2));
+    }
     b->graph[slot] = g;
     HIP_TRY(hipGraphInstantiate(&b->exec[slot], g, nullptr, nullptr, 0));
     return HYENA_OK;
