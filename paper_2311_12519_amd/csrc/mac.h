@@ -108,7 +108,10 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
     const uint32_t r32 = lc.r32;
     const size_t LN = (size_t)a.L * a.N;
     const uint32_t row0 = mt * MB, o0 = ot * OB;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index is the same on every lane: read it into a scalar so that
+    // everything derived from it (LDS bases, output rows and channels, bounds
+    // checks, store addresses) is scalar arithmetic and uniform branches
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t wr = wave / WO, wo = wave % WO;
 
     // loader: in round rd thread tid copies 16 B of LDS row rd*16 + tid/16
@@ -181,7 +184,6 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
     after_loop();
 
     const uint32_t q = lc.q;
-    const uint32_t slot = slot0 + lane;
     const uint32_t orow0 = row0 + wr * MT, oo0 = o0 + wo * OT;
 #pragma unroll
     for (int r = 0; r < MT; r++) {
@@ -203,10 +205,13 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
         }
         const uint32_t row = orow0 + r;
         if (row >= a.rows) break;
-        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
+        // uniform base of output (row, oo0) at this block's first slot; the
+        // lanes store 64 consecutive words from it
+        typedef __attribute__((address_space(1))) uint32_t gword;
+        gword *dst = (gword *)a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN + slot0;
 #pragma unroll
         for (int j = 0; j < OT; j++)
-            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + slot] = y[j];
+            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + lane] = y[j];
     }
 }
 
