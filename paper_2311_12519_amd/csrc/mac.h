@@ -131,13 +131,15 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
             stride[rd] = LN;
         }
     }
-    auto issue = [&](int st, uint32_t g) {
+    // the copies are issued for groups 0, 1, 2, ... in order, so each round
+    // keeps a running source pointer, advanced by its stride per issue
+    auto issue = [&](int st) {
 #pragma unroll
         for (int rd = 0; rd < RND; rd++) {
-            const uint32_t *p = src[rd] + (size_t)g * stride[rd];
-            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)p,
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src[rd],
                                              (__attribute__((address_space(3))) void *)&lds[st][rd * 16 + wave * 4][0],
                                              16, 0, 0);
+            src[rd] += stride[rd];
         }
     };
 
@@ -150,7 +152,7 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
     const uint32_t g1 = a.n_groups;
 #pragma unroll
     for (int i = 0; i < NS - 1; i++)
-        if ((uint32_t)i < g1) issue(i, i);
+        if ((uint32_t)i < g1) issue(i);
     const uint32_t F = lc.fold;
     uint32_t since = 0;
     int st = 0;
@@ -162,7 +164,7 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
         // workgroup barrier without a fence: the copies this stage needs are
         // complete per the wait above; later stages stay in flight
         asm volatile("s_barrier" ::: "memory");
-        if (g + NS - 1 < g1) issue(st == 0 ? NS - 1 : st - 1, g + NS - 1);
+        if (g + NS - 1 < g1) issue(st == 0 ? NS - 1 : st - 1);   // group g + NS - 1
         uint32_t x[MT], w[OT];
 #pragma unroll
         for (int r = 0; r < MT; r++) x[r] = lds[st][wr * MT + r][lane];
