@@ -18,6 +18,7 @@ struct LimbConst {
     uint32_t ninv;     // N^{-1} mod q
     uint32_t ninv_m;   // N^{-1} 2^32 mod q (Montgomery form)
     uint32_t fold;     // products that fit between two folds of a lazy accumulator
+    uint32_t nofold;   // products after the last fold the final reduction takes unfolded
     uint32_t w1n_m;    // last inverse-NTT twiddle psi^-brv(1) times N^{-1}, Montgomery form
 };
 

@@ -2,6 +2,8 @@
 // the persistent batched kernel (device code; included by conv.hip and
 // batch.hip only).
 #pragma once
+#include <type_traits>
+
 #include "internal.h"
 
 // Arguments of one layer's multiply-accumulate (also stored in device memory
@@ -26,12 +28,15 @@ __device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
 // Exact reduction of a 64-bit accumulator to [0, q), times 2^-32. The encoded
 // weights carry a factor 2^32 (Montgomery form, applied once when they are
 // encoded), so for acc = sum ct * (w 2^32) this returns sum ct * w mod q.
+// FOLD = false when acc is already below q 2^32 (at most lc.nofold products
+// since the last fold).
+template <bool FOLD = true>
 __device__ __forceinline__ uint32_t reduce64(uint64_t acc, const LimbConst &lc) {
     const uint32_t q = lc.q;
     const uint32_t hi = (uint32_t)(acc >> 32), lo = (uint32_t)acc;
     // y = hi * 2^32 + lo = hi * r32 + lo (mod q); with r32 = 2^32 mod q <= q - 1,
     // y <= (r32 + 1)(2^32 - 1) < q * 2^32, the range Montgomery reduction takes
-    const uint64_t y = mad64(hi, lc.r32, lo);
+    const uint64_t y = FOLD ? mad64(hi, lc.r32, lo) : acc;
     // Montgomery REDC: y * 2^-32 mod q in [0, 2q)
     const uint32_t m = (uint32_t)y * lc.qinv_neg;
     const uint64_t t = mad64(m, q, y);
@@ -187,11 +192,14 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
 
     const uint32_t q = lc.q;
     const uint32_t orow0 = row0 + wr * MT, oo0 = o0 + wo * OT;
+    // the products since the last fold decide whether the reduction folds
+    // first (a uniform branch around the whole epilogue)
+    auto epilogue = [&](auto fold_first) {
 #pragma unroll
     for (int r = 0; r < MT; r++) {
         uint32_t y[OT];
 #pragma unroll
-        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
+        for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
         if (a.fuse) {
 #pragma unroll
             for (int h = 1; h < OT; h <<= 1) {
@@ -215,6 +223,9 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
         for (int j = 0; j < OT; j++)
             if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + lane] = y[j];
     }
+    };
+    if (since > lc.nofold) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
 }
 
 template <int MT, int OT, int WR, int WO, int NS>

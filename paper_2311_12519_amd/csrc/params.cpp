@@ -103,6 +103,13 @@ static void build_tables(hyena_ctx *c) {
                                  (((unsigned __int128)(lc.r32 + 1ull)) << 32);
         unsigned __int128 f = room / ((unsigned __int128)(q - 1) * (q - 1));
         lc.fold = (uint32_t)(f > 15 ? 15 : (f < 1 ? 1 : f));
+        // Unfolded products after the last fold that the final Montgomery
+        // reduction still takes without a fold of its own: its input must stay
+        // below q 2^32 (at most fold - 1 are ever left over)
+        unsigned __int128 redc_room = (((unsigned __int128)q) << 32) - 1 -
+                                      (((unsigned __int128)(lc.r32 + 1ull)) << 32);
+        unsigned __int128 nf = redc_room / ((unsigned __int128)(q - 1) * (q - 1));
+        lc.nofold = (uint32_t)(nf > lc.fold - 1 ? lc.fold - 1 : nf);
     }
     c->lazy_ntt = true;
     for (uint32_t i = 0; i < c->L; i++)
