@@ -105,6 +105,7 @@ PersistentFn persistent_fn(const int *info) {
         return mac_persistent_kernel<M, O, R, W, S>;
     HY_P(8, 8, 2, 2, 4) HY_P(8, 8, 2, 2, 3) HY_P(4, 8, 2, 2, 4) HY_P(8, 8, 1, 4, 4)
     HY_P(2, 16, 1, 4, 4) HY_P(4, 16, 1, 4, 3) HY_P(8, 4, 4, 1, 4) HY_P(4, 8, 1, 4, 4)
+    HY_P(8, 8, 2, 2, 5) HY_P(8, 8, 2, 2, 6)
 #undef HY_P
     return nullptr;
 }

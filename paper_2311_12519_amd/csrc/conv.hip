@@ -309,6 +309,7 @@ static const MacSched kScheds[] = {
     {0, 4, 1, 0, 0, 0},  {0, 8, 2, 0, 0, 0},  {0, 8, 1, 0, 0, 0},
     {1, 8, 8, 2, 2, 4},  {1, 8, 8, 2, 2, 3},  {1, 4, 8, 2, 2, 4},  {1, 8, 8, 1, 4, 4},
     {1, 2, 16, 1, 4, 4}, {1, 4, 16, 1, 4, 3}, {1, 8, 4, 4, 1, 4},  {1, 4, 8, 1, 4, 4},
+    {1, 8, 8, 2, 2, 5},  {1, 8, 8, 2, 2, 6},
 };
 static const int kNumScheds = sizeof(kScheds) / sizeof(kScheds[0]);
 
@@ -344,6 +345,7 @@ static hipError_t dispatch_mac(const MacArgs &a, const MacSched &t, hipStream_t 
     if (t.mt == M && t.ot == O && t.wr == R && t.wo == W && t.ns == S) return launch_mac_lds<M, O, R, W, S>(a, s);
         HY_L(8, 8, 2, 2, 4) HY_L(8, 8, 2, 2, 3) HY_L(4, 8, 2, 2, 4) HY_L(8, 8, 1, 4, 4)
         HY_L(2, 16, 1, 4, 4) HY_L(4, 16, 1, 4, 3) HY_L(8, 4, 4, 1, 4) HY_L(4, 8, 1, 4, 4)
+        HY_L(8, 8, 2, 2, 5) HY_L(8, 8, 2, 2, 6)
 #undef HY_L
         return hipErrorInvalidValue;
     }
