@@ -183,3 +183,60 @@ def test_batch_mac_launch_form_from_cache(dev, setup, tmp_path, monkeypatch, sol
         hy.hyena_batch_run(b)
         _check(items, bufs, ("launch form", solo, rep))
     hy.hyena_batch_destroy(b)
+
+
+def test_vgg_full_size_tuned_batch_sampled(dev, tmp_path, monkeypatch):
+    """Three VGG-16 layers at their full size (conv1_2: 7 row tiles, 64 input
+    groups; conv4_2: 57 groups; conv5_1: 16 groups) for 8 images at N = 8192,
+    L = 3, in the launch configuration the benchmark times: one tuned batch
+    with the persistent multiply-accumulate and hipGraph replay. Sampled output
+    ciphertexts equal the oracle's on every coefficient, after the first run
+    and after a replay of the captured graph."""
+    import torch
+    monkeypatch.setenv("HYENA_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    n, l_, images = 8192, 3, 8
+    ctx = hy.hyena_create(n, l_)
+    by_name = {lay.name: lay for lay in wl.vgg16_layers()}
+    gen = torch.Generator(device="cuda")
+    items = []
+    for i, name in enumerate(["conv1_2", "conv4_2", "conv5_1"]):
+        lay = by_name[name]
+        d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=1, flags=hy.HYENA_FUSE_WHT,
+                               batch=images)
+        pl = orc.plan(n, lay.H, lay.W, lay.Ci, lay.Co, lay.k)
+        ct0 = torch.empty((images, pl.tiles, pl.n_groups, 2, l_, n), dtype=torch.int32, device="cuda")
+        gen.manual_seed(700 + i)
+        for li, q in enumerate(ctx.primes):
+            ct0[..., li, :] = torch.randint(0, q, ct0[..., li, :].shape, generator=gen, device="cuda",
+                                            dtype=torch.int64).to(torch.int32)
+        w = wl.weights(7000 + i, lay)
+        d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+        hy.hyena_encode_weights(ctx, d, torch.from_numpy(w).cuda(), d_wn)
+        d_out = torch.empty(images * pl.tiles * lay.Co * 2 * l_ * n, dtype=torch.int32, device="cuda")
+        # (image, tile, output channel): first, last and one in between
+        sel = [(0, 0, 0), (3, pl.tiles // 2, lay.Co // 2 + 1), (images - 1, pl.tiles - 1, lay.Co - 1)]
+        items.append(dict(d=d, pl=pl, ct0=ct0, d_ct=ct0.clone(), w=w, d_wn=d_wn, d_out=d_out, sel=sel))
+    flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH
+    b = hy.hyena_batch_create(ctx, [(it["d"], it["d_ct"], it["d_wn"], it["d_out"]) for it in items], flags)
+    assert hy.hyena_batch_info(b)["layers"] == 3
+    want = []
+    for it in items:
+        pl = it["pl"]
+        w_it = []
+        for img, tau, o in it["sel"]:
+            ct_img = it["ct0"][img].cpu().numpy().view(np.uint32)
+            w_it.append(orc.conv_products(pl, ct_img, it["w"], ctx.primes, outputs=[(tau, o)])[0])
+        want.append(w_it)
+    for rep in range(2):
+        for it in items:
+            it["d_ct"].copy_(it["ct0"])
+        torch.cuda.synchronize()
+        hy.hyena_batch_run(b)
+        torch.cuda.synchronize()
+        for it, w_it in zip(items, want):
+            pl = it["pl"]
+            got = it["d_out"].view(images, pl.tiles, it["d"].Co, 2, l_, n)
+            for (img, tau, o), wv in zip(it["sel"], w_it):
+                g = got[img, tau, o].cpu().numpy().view(np.uint32)
+                assert np.array_equal(g, wv), (rep, it["d"].Co, img, tau, o)
+    hy.hyena_batch_destroy(b)
