@@ -34,7 +34,7 @@ struct hyena_ctx {
     uint32_t fold_min = 1;   // minimum of lt.c[i].fold
     bool lazy_ntt = false;   // every q_i < 2^30: NTT butterflies may run lazily
     // host twiddles (for the host-side NTT used by test-setup encryption)
-    std::vector<uint32_t> h_fw, h_fws, h_iw, h_iws;  // [L][N]
+    std::vector<uint32_t> h_fw, h_iw;  // [L][N]
     // device twiddles in Montgomery form (w 2^32 mod q): forward psi powers
     // in bit-reversed order, inverse psi^-1 powers likewise.  [L][N]
     uint32_t *d_fw = nullptr;
@@ -60,9 +60,6 @@ static inline uint32_t to_montgomery(uint32_t x, uint32_t q) {
     return (uint32_t)(((uint64_t)x << 32) % q);
 }
 uint32_t h_powmod(uint32_t b, uint64_t e, uint32_t q);
-static inline uint32_t shoup_companion(uint32_t w, uint32_t q) {
-    return (uint32_t)(((uint64_t)w << 32) / q);
-}
 uint32_t bit_reverse(uint32_t x, uint32_t logn);
 
 // host NTT (same transform as the device one), used by test-setup crypto

@@ -68,9 +68,7 @@ static uint32_t security_ceiling(uint32_t N) {
 static void build_tables(hyena_ctx *c) {
     const uint32_t N = c->N;
     c->h_fw.assign((size_t)c->L * N, 0);
-    c->h_fws.assign((size_t)c->L * N, 0);
     c->h_iw.assign((size_t)c->L * N, 0);
-    c->h_iws.assign((size_t)c->L * N, 0);
     for (uint32_t i = 0; i < c->L; i++) {
         const uint32_t q = c->q[i], psi = c->psi[i];
         const uint32_t psi_inv = h_powmod(psi, q - 2, q);
@@ -84,9 +82,7 @@ static void build_tables(hyena_ctx *c) {
         for (uint32_t k = 0; k < N; k++) {
             uint32_t r = bit_reverse(k, c->logN);
             c->h_fw[(size_t)i * N + k] = pw[r];
-            c->h_fws[(size_t)i * N + k] = shoup_companion(pw[r], q);
             c->h_iw[(size_t)i * N + k] = ipw[r];
-            c->h_iws[(size_t)i * N + k] = shoup_companion(ipw[r], q);
         }
         LimbConst &lc = c->lt.c[i];
         lc.q = q;
