@@ -106,11 +106,14 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
     }
 
     const uint32_t q = lc.q;
+    // the reduction folds first unless at most lc.nofold products were added
+    // since the last fold (a depthwise output has one product: never)
+    auto epilogue = [&](auto fold_first) {
 #pragma unroll
     for (int r = 0; r < MT; r++) {
         uint32_t y[OT];
 #pragma unroll
-        for (int j = 0; j < OT; j++) y[j] = reduce64(acc[r][j], lc);
+        for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
         if (a.fuse) {
             // Walsh-Hadamard butterflies over each aligned group of c_n outputs
 #pragma unroll
@@ -133,6 +136,9 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
             if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN + slot] = y[j];
         }
     }
+    };
+    if (since > lc.nofold) epilogue(std::true_type{});
+    else epilogue(std::false_type{});
 }
 
 // Standalone Walsh-Hadamard recombination: out[G][b] = sum_j H[b][j] in[G][j].
