@@ -110,32 +110,33 @@ __global__ void __launch_bounds__(256) mac_kernel(MacArgs a) {
     // since the last fold (a depthwise output has one product: never)
     auto epilogue = [&](auto fold_first) {
 #pragma unroll
-    for (int r = 0; r < MT; r++) {
-        uint32_t y[OT];
+        for (int r = 0; r < MT; r++) {
+            uint32_t y[OT];
 #pragma unroll
-        for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
-        if (a.fuse) {
-            // Walsh-Hadamard butterflies over each aligned group of c_n outputs
+            for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
+            if (a.fuse) {
+                // Walsh-Hadamard butterflies over each aligned group of c_n outputs
 #pragma unroll
-            for (int h = 1; h < OT; h <<= 1) {
-                if ((uint32_t)h >= a.c_n) break;
+                for (int h = 1; h < OT; h <<= 1) {
+                    if ((uint32_t)h >= a.c_n) break;
 #pragma unroll
-                for (int j = 0; j < OT; j++) {
-                    if (j & h) continue;
-                    const uint32_t u = y[j], v = y[j + h];
-                    y[j] = csub(u + v, q);
-                    y[j + h] = csub(u - v + q, q);
+                    for (int j = 0; j < OT; j++) {
+                        if (j & h) continue;
+                        const uint32_t u = y[j], v = y[j + h];
+                        y[j] = csub(u + v, q);
+                        y[j + h] = csub(u - v + q, q);
+                    }
                 }
             }
-        }
-        const uint32_t row = row0 + r;
-        if (row >= a.rows) break;
-        uint32_t *dst = a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
+            const uint32_t row = row0 + r;
+            if (row >= a.rows) break;
+            typedef __attribute__((address_space(1))) uint32_t gword;
+            gword *dst = (gword *)a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN;
 #pragma unroll
-        for (int j = 0; j < OT; j++) {
-            if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN + slot] = y[j];
+            for (int j = 0; j < OT; j++) {
+                if (o0 + j < a.Co) dst[(size_t)(o0 + j) * 2 * LN + slot] = y[j];
+            }
         }
-    }
     };
     if (since > lc.nofold) epilogue(std::true_type{});
     else epilogue(std::false_type{});

@@ -196,33 +196,33 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
     // first (a uniform branch around the whole epilogue)
     auto epilogue = [&](auto fold_first) {
 #pragma unroll
-    for (int r = 0; r < MT; r++) {
-        uint32_t y[OT];
+        for (int r = 0; r < MT; r++) {
+            uint32_t y[OT];
 #pragma unroll
-        for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
-        if (a.fuse) {
+            for (int j = 0; j < OT; j++) y[j] = reduce64<decltype(fold_first)::value>(acc[r][j], lc);
+            if (a.fuse) {
 #pragma unroll
-            for (int h = 1; h < OT; h <<= 1) {
-                if ((uint32_t)h >= a.c_n) break;
+                for (int h = 1; h < OT; h <<= 1) {
+                    if ((uint32_t)h >= a.c_n) break;
 #pragma unroll
-                for (int j = 0; j < OT; j++) {
-                    if (j & h) continue;
-                    const uint32_t u = y[j], v = y[j + h];
-                    y[j] = csub(u + v, q);
-                    y[j + h] = csub(u - v + q, q);
+                    for (int j = 0; j < OT; j++) {
+                        if (j & h) continue;
+                        const uint32_t u = y[j], v = y[j + h];
+                        y[j] = csub(u + v, q);
+                        y[j + h] = csub(u - v + q, q);
+                    }
                 }
             }
-        }
-        const uint32_t row = orow0 + r;
-        if (row >= a.rows) break;
-        // uniform base of output (row, oo0) at this block's first slot; the
-        // lanes store 64 consecutive words from it
-        typedef __attribute__((address_space(1))) uint32_t gword;
-        gword *dst = (gword *)a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN + slot0;
+            const uint32_t row = orow0 + r;
+            if (row >= a.rows) break;
+            // uniform base of output (row, oo0) at this block's first slot; the
+            // lanes store 64 consecutive words from it
+            typedef __attribute__((address_space(1))) uint32_t gword;
+            gword *dst = (gword *)a.out + ((size_t)(row >> 1) * a.Co * 2 + (row & 1)) * LN + slot0;
 #pragma unroll
-        for (int j = 0; j < OT; j++)
-            if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + lane] = y[j];
-    }
+            for (int j = 0; j < OT; j++)
+                if (oo0 + j < a.Co) dst[(size_t)(oo0 + j) * 2 * LN + lane] = y[j];
+        }
     };
     if (since > lc.nofold) epilogue(std::true_type{});
     else epilogue(std::false_type{});
