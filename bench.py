@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alt-primes", action="store_true",
                     help="skip the supplementary tuned run with primes below 2^30")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the supplementary direct-versus-NTT run on MobileNetV1's depthwise layers")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -465,6 +467,8 @@ def main():
     if args.primes == 31 and args.mode in ("all", "tuned") and not args.no_alt_primes:
         out["primes_below_2^30"], alt_parity = alt_primes(args, hy, wl, torch, layers, n_img, total_macs)
         parity += alt_parity
+    if args.mode in ("all", "tuned") and not args.no_direct:
+        out["direct_depthwise"] = direct_depthwise(args, hy, wl, torch)
     if not args.no_cpu_baseline:
         import oracle as orc
         log("cpu baseline (oracle), with the parity check of the sampled outputs ...")
@@ -502,6 +506,68 @@ def wht_bandwidth(ctx, layers, hy, torch):
         gbs = 2 * o.out.numel() * 4 / (best * 1e-3) / 1e9
         res[f"c_n={cn}"] = {"ms": best, "GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
     return res
+
+
+def direct_depthwise(args, hy, wl, torch):
+    """Supplementary figure: MobileNetV1's 13 depthwise 3x3 layers at 224x224
+    for the same number of images, N = 8192, three primes below 2^31, computed
+    two ways on the same inputs: the NTT path (forward NTT of the input
+    ciphertexts, pointwise product with the encoded weights, inverse NTT; the
+    weights encoded beforehand) and the coefficient-domain direct convolution
+    from the integer taps (hyena_conv_direct). The two outputs must agree on
+    every coefficient (the benchmark stops otherwise); times are per layer the
+    best of 3 runs, summed."""
+    N, L, n_img = 8192, 3, args.images
+    log("supplementary run: direct versus NTT path, MobileNetV1 depthwise layers ...")
+    ctx = hy.hyena_create(N, L)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    t_ntt = t_dir = 0.0
+    n_layers = 0
+    for li, lay in enumerate(wl.mobilenet_v1_layers()):
+        if not lay.depthwise:
+            continue
+        n_layers += 1
+        d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, depthwise=True, c_n=1,
+                               flags=hy.HYENA_FUSE_WHT, batch=n_img)
+        ct0 = torch.empty(n_img * d.n_in * 2 * L * N, dtype=torch.int32, device=dev)
+        v = ct0.view(-1, L, N)
+        gen.manual_seed(wl.layer_seed(5, li))
+        for i, q in enumerate(ctx.primes):
+            v[:, i, :] = torch.randint(0, q, v[:, i, :].shape, generator=gen, device=dev,
+                                       dtype=torch.int64).to(torch.int32)
+        w = torch.from_numpy(wl.weights(wl.layer_seed(5, li), lay)).to(dev)
+        wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device=dev)
+        hy.hyena_encode_weights(ctx, d, w, wn)
+        ct = torch.empty_like(ct0)
+        out_ntt = torch.empty(n_img * d.n_out * 2 * L * N, dtype=torch.int32, device=dev)
+        out_dir = torch.empty_like(out_ntt)
+        best_n = best_d = 1e30
+        for rep in range(4):
+            ct.copy_(ct0)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            hy.hyena_ntt(ctx, ct)
+            hy.hyena_conv(ctx, d, ct, wn, out_ntt)
+            hy.hyena_intt(ctx, out_ntt)
+            e1.record()
+            hy.hyena_conv_direct(ctx, d, ct0, w, out_dir)
+            e2.record()
+            torch.cuda.synchronize()
+            if rep:
+                best_n = min(best_n, e0.elapsed_time(e1))
+                best_d = min(best_d, e1.elapsed_time(e2))
+        if not torch.equal(out_ntt, out_dir):
+            raise SystemExit(f"direct and NTT paths differ on MobileNetV1 layer {lay.name}")
+        t_ntt += best_n
+        t_dir += best_d
+        del ct0, ct, out_ntt, out_dir, wn
+    hy.hyena_destroy(ctx)
+    log(f"depthwise layers: NTT path {t_ntt:.3f} ms, direct {t_dir:.3f} ms")
+    return {"workload": f"MobileNetV1 13 depthwise 3x3 layers at 224x224, {n_img} images, N=8192, "
+                        "3 primes < 2^31",
+            "layers": n_layers, "images": n_img, "ntt_path_ms": t_ntt, "direct_ms": t_dir,
+            "speedup_direct_vs_ntt": t_ntt / t_dir, "outputs_equal": True}
 
 
 def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):

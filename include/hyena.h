@@ -244,6 +244,29 @@ int hyena_conv(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                uint32_t *d_out_ntt, hyena_stream_t stream);
 
 /*
+ * The same convolution computed in the coefficient domain, straight from the
+ * integer taps (the products of ciphertext coefficients by small plaintext
+ * integers without reduction and one reduction per output coefficient of the
+ * "Lazy Reduction" passage, "Latency Optimization" section):
+ *   Y[b][tau][o][p][i] = sum_g ct[b][tau][g][p][i] * K_{o,g}  mod (X^N + 1, q_i)
+ * with K_{o,g} the kernel polynomial of hyena_encode_weights' c_n = 1 form,
+ * each of its taps f X^e applied as a negacyclic shift. No NTT is involved:
+ * the result equals hyena_intt(hyena_conv(hyena_ntt(ct))) with
+ * HYENA_FUSE_WHT (or c_n = 1), whatever desc->c_n is. It does less work than
+ * that path when an output has few taps (depthwise layers; c_i = 1 layers with
+ * few input ciphertexts).
+ * d_ct:  device uint32 [batch][tiles][n_groups][2][L][N], coefficient domain.
+ * d_w:   device int8 [Co][Ci][k][k] ([Co][1][k][k] if depthwise).
+ * d_out: device uint32 [batch][tiles][Co][2][L][N], coefficient domain; must
+ *        not overlap d_ct (EINVAL).
+ * N must be a multiple of 1024 (EUNSUPPORTED); at most 2^20 taps per output,
+ * L * Co and batch * tiles at most 65535 (EINVAL). Errors: EINVAL,
+ * EUNSUPPORTED, EHIP.
+ */
+int hyena_conv_direct(const hyena_ctx *ctx, const hyena_conv_desc *desc, const uint32_t *d_ct,
+                      const int8_t *d_w, uint32_t *d_out, hyena_stream_t stream);
+
+/*
  * Schedules of the multiply-accumulate. Every schedule computes the same
  * result as hyena_conv (bit for bit); they differ in speed only, and are what
  * the autotuner searches. hyena_conv_schedules reports how many exist;

@@ -77,6 +77,7 @@ _SIGS = {
     "hyena_ntt": [_P, _P, _sz, _P],
     "hyena_intt": [_P, _P, _sz, _P],
     "hyena_conv": [_P, _P, _P, _P, _P, _P],
+    "hyena_conv_direct": [_P, _P, _P, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -286,6 +287,13 @@ def hyena_ntt_sched(ctx: Ctx, d_poly, inverse: bool, sched: int, stream=None) ->
 def hyena_conv(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_wntt, d_out_ntt, stream=None) -> None:
     _check(lib().hyena_conv(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct_ntt, "int32"),
                             _dev_ptr(d_wntt, "int32"), _dev_ptr(d_out_ntt, "int32"), _stream(stream)))
+
+
+def hyena_conv_direct(ctx: Ctx, desc: ConvDesc, d_ct, d_w, d_out, stream=None) -> None:
+    """Coefficient-domain convolution from the int8 taps (no NTT); the result
+    equals hyena_intt(hyena_conv(hyena_ntt(d_ct))) with per-channel outputs."""
+    _check(lib().hyena_conv_direct(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct, "int32"),
+                                   _dev_ptr(d_w, "int8"), _dev_ptr(d_out, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

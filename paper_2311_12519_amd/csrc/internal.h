@@ -19,6 +19,7 @@ struct LimbConst {
     uint32_t ninv_m;   // N^{-1} 2^32 mod q (Montgomery form)
     uint32_t fold;     // products that fit between two folds of a lazy accumulator
     uint32_t nofold;   // products after the last fold the final reduction takes unfolded
+    uint32_t r64;      // 2^64 mod q: a Montgomery product by it multiplies by 2^32
     uint32_t w1n_m;    // last inverse-NTT twiddle psi^-brv(1) times N^{-1}, Montgomery form
 };
 

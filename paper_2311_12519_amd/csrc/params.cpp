@@ -106,6 +106,7 @@ static void build_tables(hyena_ctx *c) {
                                       (((unsigned __int128)(lc.r32 + 1ull)) << 32);
         unsigned __int128 nf = redc_room / ((unsigned __int128)(q - 1) * (q - 1));
         lc.nofold = (uint32_t)(nf > lc.fold - 1 ? lc.fold - 1 : nf);
+        lc.r64 = (uint32_t)((((unsigned __int128)1) << 64) % q);
     }
     c->lazy_ntt = true;
     for (uint32_t i = 0; i < c->L; i++)

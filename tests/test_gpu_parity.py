@@ -357,3 +357,79 @@ def test_misaligned_device_arrays_rejected(dev):
     with pytest.raises(hy.HyenaError, match="aligned"):
         hy.hyena_encode_weights(ctx, d, torch.zeros(16 * 16 * 9, dtype=torch.int8, device="cuda"), w[1:1 + n_w])
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- direct (coefficient domain)
+
+DIRECT_CASES = [
+    # (name, (N, L, bits), layer, batch)
+    ("depthwise", (8192, 3, 31), wl.Layer("t", 28, 28, 32, 32, 3, depthwise=True), 2),
+    ("depthwise_30bit", (4096, 2, 30), wl.Layer("t", 14, 14, 64, 64, 3, depthwise=True), 1),
+    ("small_std", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 16, 3), 1),
+    ("tiles_halo", (4096, 2, 30), wl.Layer("t", 70, 70, 3, 8, 3), 1),
+    ("short_group", (4096, 2, 30), wl.Layer("t", 12, 12, 37, 8, 3), 3),
+    ("pointwise", (8192, 3, 31), wl.Layer("t", 14, 14, 64, 40, 1), 1),
+]
+
+
+@pytest.mark.parametrize("name,params,lay,batch", DIRECT_CASES, ids=[c[0] for c in DIRECT_CASES])
+def test_conv_direct_matches_oracle(dev, name, params, lay, batch):
+    """The coefficient-domain direct convolution equals the oracle's sparse-tap
+    schoolbook products on every coefficient of every output, part and limb."""
+    import torch
+    say(f"direct {name}")
+    ctx = ctx_for(*params)
+    N, L = params[0], params[1]
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, depthwise=lay.depthwise, batch=batch)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, lay.depthwise)
+    rng = np.random.default_rng(31 + len(name))
+    ct = rand_res(rng, (batch, pl.tiles, pl.n_groups, 2, L, N), ctx.primes)
+    w = wl.weights(3100 + len(name), lay)
+    d_out = torch.empty(batch * pl.tiles * lay.Co * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_conv_direct(ctx, d, to_dev(ct), torch.from_numpy(w).cuda(), d_out)
+    got = from_dev(d_out).reshape(batch, pl.tiles, lay.Co, 2, L, N)
+    for b in range(batch):
+        want = orc.conv_products(pl, ct[b], w, ctx.primes).reshape(pl.tiles, lay.Co, 2, L, N)
+        assert np.array_equal(got[b], want), (name, b)
+
+
+def test_conv_direct_equals_ntt_path(dev):
+    """Direct result == inverse NTT of the NTT-domain product with the Walsh
+    packing (c_n = 2, fused), on a layer with row tiles and a short group."""
+    import torch
+    ctx = ctx_for(8192, 3, 31)
+    N, L = 8192, 3
+    lay = wl.Layer("t", 28, 28, 40, 24, 3)
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=2, flags=hy.HYENA_FUSE_WHT, batch=2)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k)
+    rng = np.random.default_rng(77)
+    ct = rand_res(rng, (2, pl.tiles, pl.n_groups, 2, L, N), ctx.primes)
+    w = wl.weights(7700, lay)
+    d_w = torch.from_numpy(w).cuda()
+    n_out = 2 * pl.tiles * lay.Co * 2 * L * N
+    direct = torch.empty(n_out, dtype=torch.int32, device="cuda")
+    hy.hyena_conv_direct(ctx, d, to_dev(ct), d_w, direct)
+    d_ct = to_dev(ct)
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, d_w, d_wn)
+    via_ntt = torch.empty(n_out, dtype=torch.int32, device="cuda")
+    hy.hyena_ntt(ctx, d_ct)
+    hy.hyena_conv(ctx, d, d_ct, d_wn, via_ntt)
+    hy.hyena_intt(ctx, via_ntt)
+    assert torch.equal(direct, via_ntt)
+
+
+def test_conv_direct_rejects_overlap_and_unplanned(dev):
+    import torch
+    ctx = ctx_for(4096, 2, 30)
+    lay = wl.Layer("t", 16, 16, 16, 16, 3)
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k)
+    n_in = d.n_in * 2 * 2 * 4096
+    n_out = d.n_out * 2 * 2 * 4096
+    buf = torch.zeros(n_in + n_out, dtype=torch.int32, device="cuda")
+    w = torch.zeros(16 * 16 * 9, dtype=torch.int8, device="cuda")
+    with pytest.raises(hy.HyenaError):       # output overlapping the input
+        hy.hyena_conv_direct(ctx, d, buf[:n_in], w, buf[n_in // 2:n_in // 2 + n_out])
+    bad = hy.ConvDesc()
+    with pytest.raises(hy.HyenaError):       # descriptor never planned
+        hy.hyena_conv_direct(ctx, bad, buf[:n_in], w, buf[n_in:])
