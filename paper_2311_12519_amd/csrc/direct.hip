@@ -30,6 +30,8 @@ struct DirectArgs {
     const int8_t *w;      // [Co][wch][k][k]
     uint32_t *out;        // [rows][Co][2][L][N], coefficient domain
     uint32_t N, L, Co, Ci, k, ci, Bt, Wp, O, n_groups, depthwise, wch;
+    uint32_t wwords;      // 32-bit words of LDS holding the taps
+    uint32_t win_len;     // DCHUNK + (k - 1)(Wp + 1): window length per part
     LimbTable lt;
 };
 
@@ -41,77 +43,62 @@ __device__ __forceinline__ uint32_t dmont(uint64_t t, uint32_t q, uint32_t qn) {
     return (uint32_t)(((uint64_t)m * q + t) >> 32);
 }
 
-// Add tap (w, e) of one input polynomial pair (parts 0 and 1 at src, src + LN)
-// to the thread's DSLICE coefficients k = k0 + s 256 + tid of both parts. The
-// coefficient read is k - e, or k - e + N with the weight negated where k < e;
-// both lie in [0, N).
-__device__ __forceinline__ void direct_tap(int64_t (&acc)[2][DSLICE], const uint32_t *src, size_t LN,
-                                           int32_t w, uint32_t e, uint32_t k0, uint32_t N, uint32_t tid) {
-#pragma unroll
-    for (int s = 0; s < DSLICE; s++) {
-        const uint32_t kb = k0 + (uint32_t)s * 256u;   // block-uniform, kb + 256 <= N
-        uint32_t idx;
-        int32_t ws;
-        if (kb >= e) {                  // no lane wraps
-            idx = kb - e + tid;
-            ws = w;
-        } else if (kb + 256u <= e) {    // every lane wraps
-            idx = kb + N - e + tid;
-            ws = -w;
-        } else {                        // the range straddles e: per lane
-            const uint32_t kk = kb + tid;
-            const bool wrap = kk < e;
-            idx = wrap ? kk + N - e : kk - e;
-            ws = wrap ? -w : w;
-        }
-        acc[0][s] += (int64_t)ws * (int64_t)(int32_t)src[idx];
-        acc[1][s] += (int64_t)ws * (int64_t)(int32_t)src[LN + idx];
-    }
-}
-
+// One block: DCHUNK consecutive output coefficients k0 ... k0 + DCHUNK - 1 of
+// both parts of one (row, output channel, limb). For every input channel the
+// block stages in LDS the window of input coefficients its taps read: with the
+// channel's largest exponent e_hi and tap span `span` (taps have exponents
+// e_hi - d, 0 <= d <= span), raw indices j = k - e run over
+// [k0 - e_hi, k0 + DCHUNK - 1 - e_hi + span]; the window holds a[j] for j >= 0
+// and -a[j + N] for j < 0 (the negacyclic wrap), so tap e = e_hi - d reads
+// window position k - k0 + d with no per-lane branch.
 __global__ void __launch_bounds__(256) direct_kernel(DirectArgs a) {
-    extern __shared__ int8_t lw[];   // this output channel's taps, [wch][k][k]
+    extern __shared__ int32_t smem[];
+    int8_t *lw = reinterpret_cast<int8_t *>(smem);   // this output channel's taps, [wch][k][k]
+    int32_t *win = smem + a.wwords;                   // [2][win_len] signed window
     const uint32_t tid = threadIdx.x;
     const uint32_t k0 = blockIdx.x * DCHUNK;
     const uint32_t limb = blockIdx.y % a.L, o = blockIdx.y / a.L;
     const uint32_t row = blockIdx.z;     // image x tile
     const uint32_t kk2 = a.k * a.k, nw = a.wch * kk2;
     for (uint32_t i = tid; i < nw; i += 256) lw[i] = a.w[(size_t)o * nw + i];
-    __syncthreads();
 
     const size_t LN = (size_t)a.L * a.N;
+    const uint32_t wl = a.win_len;       // DCHUNK + span
     int64_t acc[2][DSLICE];
 #pragma unroll
     for (int p = 0; p < 2; p++)
 #pragma unroll
         for (int s = 0; s < DSLICE; s++) acc[p][s] = 0;
 
-    if (a.depthwise) {
-        // channel o sits at position o mod ci of input group o / ci
-        const uint32_t g = o / a.ci, cp = o % a.ci;
+    // input channels of this output: all of them, or channel o alone if depthwise
+    const uint32_t ch_first = a.depthwise ? o : 0, ch_end = a.depthwise ? o + 1 : a.Ci;
+    for (uint32_t ch = ch_first; ch < ch_end; ch++) {
+        const uint32_t g = ch / a.ci, cp = ch % a.ci;
+        const int8_t *wt = lw + (a.depthwise ? 0 : ch * kk2);
+        const uint32_t e_hi = a.O - cp * a.Bt;          // >= span: O = (ci-1) Bt + span
+        const int32_t j0 = (int32_t)k0 - (int32_t)e_hi;  // >= -(N - 1)
         const uint32_t *src = a.ct + ((size_t)row * a.n_groups + g) * 2 * LN + (size_t)limb * a.N;
+        __syncthreads();   // the taps (first pass) or the previous window are no longer read
+        for (uint32_t i = tid; i < wl; i += 256) {
+            const int32_t j = j0 + (int32_t)i;             // in [-(N-1), N-1]
+            const uint32_t jj = j >= 0 ? (uint32_t)j : (uint32_t)(j + (int32_t)a.N);
+            const int32_t v0 = (int32_t)src[jj], v1 = (int32_t)src[LN + jj];
+            win[i] = j >= 0 ? v0 : -v0;
+            win[wl + i] = j >= 0 ? v1 : -v1;
+        }
+        __syncthreads();
         for (uint32_t di = 0; di < a.k; di++)
             for (uint32_t dj = 0; dj < a.k; dj++) {
-                const int32_t w = lw[di * a.k + dj];
+                const int32_t w = wt[di * a.k + dj];
                 if (w == 0) continue;
-                const uint32_t e = a.O - cp * a.Bt - di * a.Wp - dj;
-                direct_tap(acc, src, LN, w, e, k0, a.N, tid);
+                const uint32_t d = di * a.Wp + dj;           // e = e_hi - d, d <= span
+#pragma unroll
+                for (int s = 0; s < DSLICE; s++) {
+                    const uint32_t pos = (uint32_t)s * 256u + tid + d;   // < DCHUNK + span
+                    acc[0][s] += (int64_t)w * (int64_t)win[pos];
+                    acc[1][s] += (int64_t)w * (int64_t)win[wl + pos];
+                }
             }
-    } else {
-        for (uint32_t g = 0; g < a.n_groups; g++) {
-            const uint32_t *src = a.ct + ((size_t)row * a.n_groups + g) * 2 * LN + (size_t)limb * a.N;
-            for (uint32_t cp = 0; cp < a.ci; cp++) {
-                const uint32_t ch = g * a.ci + cp;
-                if (ch >= a.Ci) break;   // short last group
-                for (uint32_t di = 0; di < a.k; di++)
-                    for (uint32_t dj = 0; dj < a.k; dj++) {
-                        const int32_t w = lw[(ch * a.k + di) * a.k + dj];
-                        if (w == 0) continue;
-                        const uint32_t e = a.O - cp * a.Bt - di * a.Wp - dj;
-                        direct_tap(acc, src, LN, w, e, k0, a.N, tid);
-                    }
-            }
-        }
     }
 
     const LimbConst lc = a.lt.c[limb];
@@ -165,7 +152,12 @@ extern "C" int hyena_conv_direct(const hyena_ctx *c, const hyena_conv_desc *d, c
     a.depthwise = d->depthwise;
     a.wch = d->depthwise ? 1 : d->Ci;
     a.lt = c->lt;
-    const size_t lds = ((size_t)a.wch * a.k * a.k + 3) & ~(size_t)3;
+    const uint32_t span = (d->k - 1) * (d->Wp + 1);
+    if (d->O != (d->ci - 1) * d->Bt + span) return set_error(HYENA_EINVAL, "hyena_conv_direct: inconsistent descriptor");
+    a.wwords = (a.wch * a.k * a.k + 3) / 4;
+    a.win_len = DCHUNK + span;
+    const size_t lds = 4 * ((size_t)a.wwords + 2 * (size_t)a.win_len);
+    if (lds > 64 * 1024) return set_error(HYENA_EINVAL, "hyena_conv_direct: layer needs more than 64 KiB of LDS");
     const dim3 grid(c->N / DCHUNK, c->L * d->Co, (unsigned)rows);
     hipLaunchKernelGGL(direct_kernel, grid, dim3(256), lds, (hipStream_t)s, a);
     hipError_t e = hipGetLastError();
