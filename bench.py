@@ -62,7 +62,7 @@ def log(*a):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mac_vgg16_b8_n8192_counters.md")
 MAC_SOURCES = ["paper_2311_12519_amd/csrc/mac.h", "paper_2311_12519_amd/csrc/batch.hip",
-               "paper_2311_12519_amd/csrc/conv.hip"]
+               "paper_2311_12519_amd/csrc/conv.hip", "paper_2311_12519_amd/csrc/internal.h"]
 
 
 def measured_traffic(kernel):
