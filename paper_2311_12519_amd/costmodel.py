@@ -4,9 +4,11 @@ The paper chooses the encryption parameters by hand per layer (the ring degree
 by input size, the moduli for noise and speed; "Optimal Parameter Selection",
 "Evaluation Setup"). Here the choice is searched: for every layer the
 candidates are (ring degree N, RNS limb count L, channels per ciphertext c_i,
-Walsh group c_n), restricted to parameter sets that meet the 128-bit security
-ceiling and whose worst-case noise still decrypts (the library's planner
-refuses the rest). Timing every candidate is the exhaustive search; a small
+Walsh group c_n) computed through the NTT path, plus, for layers with at most
+DIRECT_MAX_TAPS taps per output, (N, L, c_i) computed by the coefficient-domain
+direct convolution; all restricted to parameter sets that meet the 128-bit
+security ceiling and whose worst-case noise still decrypts (the library's
+planner refuses the rest). Timing every candidate is the exhaustive search; a small
 FP32 MLP (8 -> 64 -> 64 -> 1, trained and evaluated by the library's own HIP
 kernels) predicts the log time of a candidate from its features and picks the
 argmin instead. The exhaustive table stays as the reference for the model's regret.
@@ -28,14 +30,19 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (HYENA_FUSE_WHT, HYENA_HOST_ONLY, HyenaError, hyena_conv, hyena_conv_plan, hyena_create,
-               hyena_intt, hyena_mlp_adam, hyena_mlp_forward, hyena_mlp_loss_grad, hyena_mlp_params,
-               hyena_mlp_workspace_floats, hyena_ntt)
+from . import (HYENA_FUSE_WHT, HYENA_HOST_ONLY, HyenaError, hyena_conv, hyena_conv_direct, hyena_conv_plan,
+               hyena_create, hyena_intt, hyena_mlp_adam, hyena_mlp_forward, hyena_mlp_loss_grad,
+               hyena_mlp_params, hyena_mlp_workspace_floats, hyena_ntt)
 
 RING_DEGREES = (4096, 8192, 16384)
 SECURITY_LOGQ_128 = {4096: 109, 8192: 218, 16384: 438}   # ternary secret, 128-bit
 MAX_MACS = 1 << 32          # candidates above this many coeff-MACs are not searched
 MAX_BYTES = 1 << 30         # nor those whose weight and ciphertext buffers exceed 1 GiB
+# the direct path is a candidate up to this many taps per output: 3x3 and 5x5
+# depthwise layers and a first layer over 3 input channels; with 32 taps and
+# more (pointwise layers over 32+ channels) the NTT path was faster wherever
+# timed, and offering the direct path there only made the model err
+DIRECT_MAX_TAPS = 27
 
 
 @dataclass(frozen=True)
@@ -44,6 +51,7 @@ class Cand:
     L: int
     ci: int
     c_n: int
+    direct: bool = False     # coefficient-domain direct convolution instead of the NTT path
 
 
 @dataclass(frozen=True)
@@ -82,6 +90,11 @@ def _sizes(d, N, L):
     return macs, w_bytes, io_bytes
 
 
+def _taps(s: Shape) -> int:
+    """Taps per output coefficient of the direct path."""
+    return s.k * s.k * (1 if s.depthwise else s.Ci)
+
+
 def candidates(s: Shape, max_extra_limbs: int = 2):
     """Valid (N, L, c_i, c_n) for a layer shape: secure, decryptable, bounded."""
     out = []
@@ -113,6 +126,12 @@ def candidates(s: Shape, max_extra_limbs: int = 2):
                     if macs > MAX_MACS or wb + iob > MAX_BYTES:
                         continue
                     out.append(Cand(N, L, ci, c_n))
+                    # the direct path ignores c_n; its time hardly depends on
+                    # c_i (outputs dominate), so one candidate per (N, L): the
+                    # widest channel partition
+                    if (c_n == 1 and ci == cis[-1] and _taps(s) <= DIRECT_MAX_TAPS and N % 1024 == 0
+                            and iob <= MAX_BYTES):
+                        out.append(Cand(N, L, ci, 1, True))
     return out
 
 
@@ -129,17 +148,25 @@ def default_candidate(s: Shape):
 
 
 def features(s: Shape, c: Cand) -> np.ndarray:
+    """log2 N, L, log2 c_i, log2 c_n, log2 of the input and output ciphertext
+    counts, log2 of the multiply-adds (pointwise coeff-MACs on the NTT path,
+    tap multiply-adds of every output coefficient on the direct path) and the
+    path: 0 NTT (standard layer), 1 NTT (depthwise layer), 2 direct."""
     d = _plan(c.N, c.L, s, c.ci, c.c_n)
     macs, _, _ = _sizes(d, c.N, c.L)
+    if c.direct:
+        macs = d.n_out * 2 * c.L * c.N * _taps(s)
+    path = 2.0 if c.direct else float(s.depthwise)
     return np.array([math.log2(c.N), c.L, math.log2(c.ci), math.log2(c.c_n),
-                     math.log2(d.n_in), math.log2(d.n_out), math.log2(macs), float(s.depthwise)],
+                     math.log2(d.n_in), math.log2(d.n_out), math.log2(macs), path],
                     dtype=np.float64)
 
 
 class Timer:
     """Times one image of a layer configuration on the GPU: forward NTT of the
     input ciphertexts, multiply-accumulate (with Walsh recombination) and
-    inverse NTT of the outputs, best of `reps` after a warm-up."""
+    inverse NTT of the outputs, or the direct convolution for a direct
+    candidate; best of `reps` after a warm-up."""
 
     def __init__(self, pool_words: int = MAX_BYTES // 4, reps: int = 3):
         import torch
@@ -168,7 +195,12 @@ class Timer:
         w = self.pool[n_ct:n_ct + n_w]
         out = self.pool[n_ct + n_w:n_ct + n_w + n_out]
 
+        wi8 = self.pool.view(self.torch.int8)[4 * n_ct:4 * n_ct + d.Co * (1 if s.depthwise else s.Ci) * s.k * s.k]
+
         def run():
+            if c.direct:
+                hyena_conv_direct(ctx, d, ct, wi8, out)
+                return
             hyena_ntt(ctx, ct)
             hyena_conv(ctx, d, ct, w, out)
             hyena_intt(ctx, out)
