@@ -123,6 +123,37 @@ int hyena_encrypt(const hyena_ctx *ctx, const int8_t *sk, const int32_t *msg,
 int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
                   size_t n, int32_t *msg);
 
+/*
+ * Batched client operations on the device (the same "Homomorphic Operations in
+ * BFV" section): bit for bit the ciphertexts of hyena_encrypt and the messages
+ * of hyena_decrypt, for n messages per call, every step in device kernels and
+ * the library's NTT. They allocate nothing and are asynchronous on `stream`.
+ *
+ * hyena_secret_prepare: d_sk device int8 [N] (the secret's coefficients, as
+ * from hyena_keygen); d_s_hat device uint32 [L][N] receives 2^32 NTT_i(s)
+ * mod q_i, the form the two calls below take. Must not overlap d_sk.
+ *
+ * hyena_encrypt_device: d_msg device int32 [n][N]; d_ct device uint32
+ * [n][2][L][N], 16-byte aligned, written whole; d_ct must not overlap d_msg
+ * or d_s_hat. a and e are drawn exactly as in hyena_encrypt from `seed`.
+ * Messages are taken as residues mod q_i (hyena_encrypt's range (-t/2, t/2]
+ * is not checked here).
+ *
+ * hyena_decrypt_device: d_ct device uint32 [n][2][L][N] with every residue
+ * below its prime (not checked: others give unspecified messages); d_work
+ * device uint32 [n][L][N], 16-byte aligned, overwritten; d_msg device int32
+ * [n][N]. d_work and d_msg must not overlap each other, d_ct or d_s_hat.
+ *
+ * Errors: EINVAL (NULL argument, host-only context, alignment, overlap,
+ * n L >= 2^31), EHIP. n = 0 does nothing.
+ */
+int hyena_secret_prepare(const hyena_ctx *ctx, const int8_t *d_sk, uint32_t *d_s_hat,
+                         hyena_stream_t stream);
+int hyena_encrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const int32_t *d_msg,
+                         size_t n, uint64_t seed, uint32_t *d_ct, hyena_stream_t stream);
+int hyena_decrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const uint32_t *d_ct,
+                         size_t n, uint32_t *d_work, int32_t *d_msg, hyena_stream_t stream);
+
 /* ------------------------------------------------------------------------
  * Planning and layout (host).
  * ---------------------------------------------------------------------- */

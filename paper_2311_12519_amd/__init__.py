@@ -78,6 +78,9 @@ _SIGS = {
     "hyena_intt": [_P, _P, _sz, _P],
     "hyena_conv": [_P, _P, _P, _P, _P, _P],
     "hyena_conv_direct": [_P, _P, _P, _P, _P, _P],
+    "hyena_secret_prepare": [_P, _P, _P, _P],
+    "hyena_encrypt_device": [_P, _P, _P, _sz, _u64, _P, _P],
+    "hyena_decrypt_device": [_P, _P, _P, _sz, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -294,6 +297,43 @@ def hyena_conv_direct(ctx: Ctx, desc: ConvDesc, d_ct, d_w, d_out, stream=None) -
     equals hyena_intt(hyena_conv(hyena_ntt(d_ct))) with per-channel outputs."""
     _check(lib().hyena_conv_direct(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct, "int32"),
                                    _dev_ptr(d_w, "int8"), _dev_ptr(d_out, "int32"), _stream(stream)))
+
+
+def _need(t, numel: int, what: str) -> None:
+    if t.numel() != numel:
+        raise ValueError(f"{what} has {t.numel()} elements, expected {numel}")
+
+
+def hyena_secret_prepare(ctx: Ctx, d_sk, d_s_hat, stream=None) -> None:
+    """d_s_hat <- 2^32 NTT(s) mod q_i from the device int8 secret d_sk [N]."""
+    _need(d_sk, ctx.N, "d_sk")
+    _need(d_s_hat, ctx.L * ctx.N, "d_s_hat")
+    _check(lib().hyena_secret_prepare(ctx.handle, _dev_ptr(d_sk, "int8"), _dev_ptr(d_s_hat, "int32"),
+                                      _stream(stream)))
+
+
+def hyena_encrypt_device(ctx: Ctx, d_s_hat, d_msg, seed: int, d_ct, stream=None) -> None:
+    """Encrypt the n messages d_msg [n][N] into d_ct [n][2][L][N]; the same
+    ciphertexts as hyena_encrypt with the same secret and seed."""
+    n = d_msg.numel() // ctx.N
+    _need(d_msg, n * ctx.N, "d_msg")
+    _need(d_ct, n * 2 * ctx.L * ctx.N, "d_ct")
+    _need(d_s_hat, ctx.L * ctx.N, "d_s_hat")
+    _check(lib().hyena_encrypt_device(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_msg, "int32"), n, seed,
+                                      _dev_ptr(d_ct, "int32"), _stream(stream)))
+
+
+def hyena_decrypt_device(ctx: Ctx, d_s_hat, d_ct, d_work, d_msg, stream=None) -> None:
+    """Decrypt the n ciphertexts d_ct [n][2][L][N] into d_msg [n][N]; d_work
+    is an int32 workspace of n*L*N elements (overwritten)."""
+    n = d_ct.numel() // (2 * ctx.L * ctx.N)
+    _need(d_ct, n * 2 * ctx.L * ctx.N, "d_ct")
+    _need(d_msg, n * ctx.N, "d_msg")
+    _need(d_s_hat, ctx.L * ctx.N, "d_s_hat")
+    if d_work.numel() < n * ctx.L * ctx.N:
+        raise ValueError(f"d_work has {d_work.numel()} elements, needs {n * ctx.L * ctx.N}")
+    _check(lib().hyena_decrypt_device(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_ct, "int32"), n,
+                                      _dev_ptr(d_work, "int32"), _dev_ptr(d_msg, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -1,0 +1,23 @@
+// BFV client-side definitions shared by the host operations (crypto.cpp) and
+// their batched device versions (client.hip), so both draw the same randomness
+// and use the same constants ("Homomorphic Operations in BFV" section).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+// Output number ctr of a SplitMix64 generator seeded with key: the counter-based
+// generator behind the secret key and the encryption randomness.
+__host__ __device__ inline uint64_t hy_sm64(uint64_t key, uint64_t ctr) {
+    uint64_t z = key + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr int kErrBound = 32;   // error bound B = 10 sigma; the sampler has 2B thresholds
+
+std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c);   // floor(q / t) mod q_i
+void bfv_error_thresholds(uint64_t *t64);                        // the 2B sampler thresholds
+void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B);   // decryption, per limb

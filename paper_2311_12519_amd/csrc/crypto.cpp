@@ -4,21 +4,13 @@
 #include <cstring>
 #include <thread>
 
-#include "internal.h"
+#include "bfv.h"
 
 namespace {
 
-constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+inline uint64_t sm64(uint64_t key, uint64_t ctr) { return hy_sm64(key, ctr); }
 
-// Output number ctr of a SplitMix64 generator seeded with key.
-inline uint64_t sm64(uint64_t key, uint64_t ctr) {
-    uint64_t z = key + (ctr + 1) * kGamma;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-constexpr int kB = 32;          // error bound B = 10 sigma
+constexpr int kB = kErrBound;    // error bound B = 10 sigma
 constexpr double kSigma = 3.2;  // error standard deviation
 
 // Thresholds of the rounded Gaussian on [-B, B]: cumulative weights
@@ -114,6 +106,26 @@ std::vector<uint32_t> secret_ntt(const hyena_ctx *c, const int8_t *sk) {
 
 }  // namespace
 
+// Shared with the batch versions on the device (client.hip), so that both
+// compute with the same constants.
+std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c) { return delta_residues(c); }
+void bfv_error_thresholds(uint64_t *t64) {
+    for (int k = 0; k < 2 * kB; k++) t64[k] = cdt().t[k];
+}
+void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B) {
+    const uint64_t t = 1ull << c->log2_t;
+    for (uint32_t i = 0; i < c->L; i++) {
+        const uint32_t q = c->q[i];
+        uint64_t Mi = 1;  // (q / q_i) mod q_i
+        for (uint32_t j = 0; j < c->L; j++)
+            if (j != i) Mi = Mi * (c->q[j] % q) % q;
+        const uint64_t yi = h_powmod((uint32_t)Mi, q - 2, q);
+        const uint64_t ty = (t % q) * yi;  // t * y_i (< 2^51), exact
+        A[i] = ty / q;
+        B[i] = ty % q;
+    }
+}
+
 extern "C" int hyena_keygen(const hyena_ctx *c, uint64_t seed, int8_t *sk) {
     if (!c || !sk) return set_error(HYENA_EINVAL, "hyena_keygen: NULL argument");
     for (uint32_t j = 0; j < c->N; j++) {
@@ -171,16 +183,7 @@ extern "C" int hyena_decrypt(const hyena_ctx *c, const int8_t *sk, const uint32_
     const uint64_t t = 1ull << c->log2_t;
     const auto s_hat = secret_ntt(c, sk);
     std::vector<uint64_t> A(L), B(L);
-    for (uint32_t i = 0; i < L; i++) {
-        const uint32_t q = c->q[i];
-        uint64_t Mi = 1;  // (q / q_i) mod q_i
-        for (uint32_t j = 0; j < L; j++)
-            if (j != i) Mi = Mi * (c->q[j] % q) % q;
-        const uint64_t yi = h_powmod((uint32_t)Mi, q - 2, q);
-        const uint64_t ty = (t % q) * yi;  // t * y_i (< 2^51), exact
-        A[i] = ty / q;
-        B[i] = ty % q;
-    }
+    bfv_hps_constants(c, A.data(), B.data());
     for (size_t k = 0; k < n * L; k++) {
         const uint32_t q = c->q[k % L];
         for (uint32_t j = 0; j < N; j++)

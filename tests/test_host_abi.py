@@ -151,3 +151,19 @@ def test_device_calls_refused_on_host_only_context():
     ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
     rc = hy.lib().hyena_ntt(ctx.handle, ctypes.c_void_p(0), 0, ctypes.c_void_p(0))
     assert rc == hy.HYENA_EINVAL
+
+
+def test_client_device_calls_refused_on_host_only_context():
+    """The batched client entry points check their arguments before any launch:
+    NULL arrays and host-only contexts are refused, n = 0 is a no-op."""
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    L = hy.lib()
+    fake = ctypes.c_void_p(0x10000)      # never dereferenced: every call below fails its checks first
+    null = ctypes.c_void_p(0)
+    assert L.hyena_secret_prepare(ctx.handle, null, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_secret_prepare(ctx.handle, fake, fake, null) == hy.HYENA_EINVAL   # host-only
+    assert L.hyena_encrypt_device(ctx.handle, fake, null, 1, 5, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_encrypt_device(ctx.handle, fake, fake, 1, 5, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, null, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, fake, fake, null) == hy.HYENA_EINVAL
+    assert "host-only" in L.hyena_last_error().decode()
