@@ -103,6 +103,8 @@ def parse():
                     help="skip the supplementary tuned run with primes below 2^30")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the supplementary direct-versus-NTT run on MobileNetV1's depthwise layers")
+    ap.add_argument("--no-client", action="store_true",
+                    help="skip the supplementary client-side run (device encryption and decryption)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -461,6 +463,8 @@ def main():
         }
     if head_mode == "tuned":
         out["kernels"]["wht"] = wht_bandwidth(ctx, layers, hy, torch)
+    if not args.no_client:   # before alt_primes, which releases this run's buffers
+        out["client"] = client_side(args, ctx, layers, hy, torch, head["ms_per_step"], n_layer_runs)
     layers_host = [Layer() for _ in layers]   # what the random part of the baseline needs
     for h, o in zip(layers_host, layers):
         h.lay, h.w = o.lay, o.w
@@ -568,6 +572,84 @@ def direct_depthwise(args, hy, wl, torch):
                         "3 primes < 2^31",
             "layers": n_layers, "images": n_img, "ntt_path_ms": t_ntt, "direct_ms": t_dir,
             "speedup_direct_vs_ntt": t_ntt / t_dir, "outputs_equal": True}
+
+
+def client_side(args, ctx, layers, hy, torch, step_ms, n_layer_runs):
+    """Supplementary figure: the client's share of one step. In the protocol
+    the client holds each layer's input activations (after the nonlinear part)
+    and receives each layer's output: it encrypts every layer's input and
+    decrypts every layer's output, here on the same GPU
+    (hyena_encrypt_device / hyena_decrypt_device: bit for bit the host
+    library's ciphertexts and messages). Reported: ciphertexts and bytes each
+    way (the step's communication), the device time of both sides (per layer
+    the best of 3 runs, summed), layers/s with the client included, and the
+    host library's rate on a sample for comparison. Check: every encrypted
+    input decrypts back to its message, on every coefficient."""
+    N, L, n_img = ctx.N, ctx.L, args.images
+    log("supplementary run: client-side encryption and decryption on the device ...")
+    dev = torch.device("cuda:0")
+    words = 2 * L * N                      # uint32 words per ciphertext
+    sk = hy.hyena_keygen(ctx, 2024)
+    d_s_hat = torch.empty(L * N, dtype=torch.int32, device=dev)
+    hy.hyena_secret_prepare(ctx, torch.from_numpy(sk).to(dev), d_s_hat)
+    n_in = [o.ct.numel() // words for o in layers]
+    n_out = [o.out.numel() // words for o in layers]
+    t = 1 << 20
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    msg_in = torch.randint(-t // 2 + 1, t // 2 + 1, (max(n_in), N), generator=g, device=dev, dtype=torch.int32)
+    msg_chk = torch.empty((max(n_in), N), dtype=torch.int32, device=dev)
+    msg_out = torch.empty((max(n_out), N), dtype=torch.int32, device=dev)
+    work = torch.empty(max(max(n_in), max(n_out)) * L * N, dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        best = 1e30
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    t_enc = t_dec = 0.0
+    for li, o in enumerate(layers):
+        n, m = n_in[li], n_out[li]
+        ct = o.ct.view(-1)
+        t_enc += timed(lambda: hy.hyena_encrypt_device(ctx, d_s_hat, msg_in[:n], 1000 + li, work[:n * L * N], ct))
+        hy.hyena_decrypt_device(ctx, d_s_hat, ct, work[:n * L * N], msg_chk[:n])
+        if not torch.equal(msg_chk[:n], msg_in[:n]):
+            raise SystemExit(f"device encryption of layer {o.lay.name} does not decrypt to its messages")
+        t_dec += timed(lambda: hy.hyena_decrypt_device(ctx, d_s_hat, o.out.view(-1), work[:m * L * N],
+                                                       msg_out[:m]))
+        o.ct.copy_(o.ct0)
+    # the host library (multithreaded C++) on a sample of 16 ciphertexts
+    k = 16
+    msg_h = msg_in[:k].cpu().numpy()
+    t0 = time.perf_counter()
+    ct_h = hy.hyena_encrypt(ctx, sk, msg_h, 5)
+    t1 = time.perf_counter()
+    hy.hyena_decrypt(ctx, sk, ct_h)
+    t2 = time.perf_counter()
+    up, down = sum(n_in), sum(n_out)
+    b_ct = words * 4
+    enc_bytes = up * (b_ct + 4 * N)          # read the messages, write the ciphertexts
+    dec_bytes = down * (b_ct + 4 * N)        # read the ciphertexts, write the messages
+    with_client = step_ms + t_enc + t_dec
+    log(f"client: encrypt {up} ct {t_enc:.3f} ms, decrypt {down} ct {t_dec:.3f} ms")
+    return {"workload": f"inputs and outputs of the same {len(layers)} VGG-16 layers, {n_img} images",
+            "ciphertexts_up": up, "ciphertexts_down": down,
+            "bytes_up": up * b_ct, "bytes_down": down * b_ct,
+            "encrypt_ms": t_enc, "decrypt_ms": t_dec,
+            "encrypt_ct_per_s": up / (t_enc * 1e-3), "decrypt_ct_per_s": down / (t_dec * 1e-3),
+            "encrypt_GBs": enc_bytes / (t_enc * 1e-3) / 1e9, "decrypt_GBs": dec_bytes / (t_dec * 1e-3) / 1e9,
+            "algorithmic_bytes": {"encrypt": enc_bytes, "decrypt": dec_bytes},
+            "step_ms": step_ms, "step_with_client_ms": with_client,
+            "layers_per_s_with_client": n_layer_runs / (with_client * 1e-3),
+            "roundtrip_checked_ciphertexts": up,
+            "host_library": {"sample_ciphertexts": k, "threads": min(16, os.cpu_count() or 1),
+                             "encrypt_ct_per_s": k / (t1 - t0), "decrypt_ct_per_s": k / (t2 - t1)}}
 
 
 def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):

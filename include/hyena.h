@@ -130,14 +130,16 @@ int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
  * the library's NTT. They allocate nothing and are asynchronous on `stream`.
  *
  * hyena_secret_prepare: d_sk device int8 [N] (the secret's coefficients, as
- * from hyena_keygen); d_s_hat device uint32 [L][N] receives 2^32 NTT_i(s)
- * mod q_i, the form the two calls below take. Must not overlap d_sk.
+ * from hyena_keygen); d_s_hat device uint32 [L][N], 16-byte aligned, receives
+ * 2^32 NTT_i(s) mod q_i, the form the two calls below take. Must not overlap
+ * d_sk.
  *
- * hyena_encrypt_device: d_msg device int32 [n][N]; d_ct device uint32
- * [n][2][L][N], 16-byte aligned, written whole; d_ct must not overlap d_msg
- * or d_s_hat. a and e are drawn exactly as in hyena_encrypt from `seed`.
- * Messages are taken as residues mod q_i (hyena_encrypt's range (-t/2, t/2]
- * is not checked here).
+ * hyena_encrypt_device: d_msg device int32 [n][N]; d_work device uint32
+ * [n][L][N], 16-byte aligned, overwritten (a, then a s); d_ct device uint32
+ * [n][2][L][N], written whole. d_work and d_ct must not overlap each other,
+ * d_msg or d_s_hat. a and e are drawn exactly as in hyena_encrypt from
+ * `seed`. Messages are taken as residues mod q_i (hyena_encrypt's range
+ * (-t/2, t/2] is not checked here).
  *
  * hyena_decrypt_device: d_ct device uint32 [n][2][L][N] with every residue
  * below its prime (not checked: others give unspecified messages); d_work
@@ -150,7 +152,8 @@ int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
 int hyena_secret_prepare(const hyena_ctx *ctx, const int8_t *d_sk, uint32_t *d_s_hat,
                          hyena_stream_t stream);
 int hyena_encrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const int32_t *d_msg,
-                         size_t n, uint64_t seed, uint32_t *d_ct, hyena_stream_t stream);
+                         size_t n, uint64_t seed, uint32_t *d_work, uint32_t *d_ct,
+                         hyena_stream_t stream);
 int hyena_decrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const uint32_t *d_ct,
                          size_t n, uint32_t *d_work, int32_t *d_msg, hyena_stream_t stream);
 

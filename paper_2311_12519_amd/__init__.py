@@ -79,7 +79,7 @@ _SIGS = {
     "hyena_conv": [_P, _P, _P, _P, _P, _P],
     "hyena_conv_direct": [_P, _P, _P, _P, _P, _P],
     "hyena_secret_prepare": [_P, _P, _P, _P],
-    "hyena_encrypt_device": [_P, _P, _P, _sz, _u64, _P, _P],
+    "hyena_encrypt_device": [_P, _P, _P, _sz, _u64, _P, _P, _P],
     "hyena_decrypt_device": [_P, _P, _P, _sz, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
@@ -312,15 +312,18 @@ def hyena_secret_prepare(ctx: Ctx, d_sk, d_s_hat, stream=None) -> None:
                                       _stream(stream)))
 
 
-def hyena_encrypt_device(ctx: Ctx, d_s_hat, d_msg, seed: int, d_ct, stream=None) -> None:
+def hyena_encrypt_device(ctx: Ctx, d_s_hat, d_msg, seed: int, d_work, d_ct, stream=None) -> None:
     """Encrypt the n messages d_msg [n][N] into d_ct [n][2][L][N]; the same
-    ciphertexts as hyena_encrypt with the same secret and seed."""
+    ciphertexts as hyena_encrypt with the same secret and seed. d_work is an
+    int32 workspace of n*L*N elements (overwritten)."""
     n = d_msg.numel() // ctx.N
     _need(d_msg, n * ctx.N, "d_msg")
     _need(d_ct, n * 2 * ctx.L * ctx.N, "d_ct")
     _need(d_s_hat, ctx.L * ctx.N, "d_s_hat")
+    if d_work.numel() < n * ctx.L * ctx.N:
+        raise ValueError(f"d_work has {d_work.numel()} elements, needs {n * ctx.L * ctx.N}")
     _check(lib().hyena_encrypt_device(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_msg, "int32"), n, seed,
-                                      _dev_ptr(d_ct, "int32"), _stream(stream)))
+                                      _dev_ptr(d_work, "int32"), _dev_ptr(d_ct, "int32"), _stream(stream)))
 
 
 def hyena_decrypt_device(ctx: Ctx, d_s_hat, d_ct, d_work, d_msg, stream=None) -> None:

@@ -21,3 +21,11 @@ constexpr int kErrBound = 32;   // error bound B = 10 sigma; the sampler has 2B 
 std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c);   // floor(q / t) mod q_i
 void bfv_error_thresholds(uint64_t *t64);                        // the 2B sampler thresholds
 void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B);   // decryption, per limb
+
+// Forward NTT of P polynomials with a gathered source and a pointwise product:
+// dst[p][i] = NTT_i(src[p][i]) . mul[i] mod q_i, src[p][i] at
+// src + p src_stride + i N, dst contiguous [P][L][N], mul [L][N] holding
+// m 2^32 mod q_i (Montgomery form). src may equal dst with src_stride = L N;
+// otherwise they must not overlap. dst and mul 16-byte aligned (ntt.hip).
+int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
+                       const uint32_t *mul, hipStream_t s);

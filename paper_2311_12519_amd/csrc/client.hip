@@ -3,7 +3,7 @@
 // as the host hyena_encrypt / hyena_decrypt, for many messages per call, with
 // every step in device kernels and the library's NTT.
 //
-// Encryption of message m (limb i, coefficient j):
+// Encryption of message m (limb i, coefficient j), NTT(s) prepared once:
 //   a  = floor(q_i sm64(seed, 2((m L + i) N + j)) / 2^64)
 //   c1 = [-a]_{q_i},  c0 = [Delta_i lift(msg) + INTT(NTT(a) . NTT(s)) + lift(e)]_{q_i}
 // with e the rounded Gaussian drawn from sm64(seed, 2(m N + j) + 1).
@@ -23,6 +23,7 @@ struct ClientConst {
     uint32_t dm[HYENA_MAX_LIMBS];   // Delta_i 2^32 mod q_i (Montgomery form)
     uint64_t A[HYENA_MAX_LIMBS];    // floor(t y_i / q_i)
     uint64_t B[HYENA_MAX_LIMBS];    // t y_i mod q_i
+    uint64_t rcp[HYENA_MAX_LIMBS];  // floor((2^64 - 1) / q_i) = floor(2^64 / q_i)
 };
 
 __device__ __forceinline__ uint32_t ccsub(uint32_t x, uint32_t q) { return min(x, x - q); }
@@ -36,11 +37,25 @@ __device__ __forceinline__ uint32_t cmont(uint32_t a, uint32_t b, const LimbCons
 
 __device__ __forceinline__ uint32_t caddmod(uint32_t a, uint32_t b, uint32_t q) { return ccsub(a + b, q); }
 
-// x mod q for any int32 x (the host's lift)
+// x mod q for any int32 x (the host's lift); no division when |x| < q
 __device__ __forceinline__ uint32_t clift(int32_t x, uint32_t q) {
-    if (x >= 0) return (uint32_t)x % q;
-    const uint32_t r = (uint32_t)(-(int64_t)x) % q;
-    return r ? q - r : 0;
+    const uint32_t a = x >= 0 ? (uint32_t)x : (uint32_t)(-(int64_t)x);
+    const uint32_t r = a < q ? a : a % q;
+    return x >= 0 || r == 0 ? r : q - r;
+}
+
+// floor(x / q) and x mod q, exactly, for x < 2^63, with rcp = floor(2^64 / q):
+// x rcp / 2^64 lies in (x/q - 1/2, x/q], so the estimate is the quotient or
+// one below it and a single correction makes it exact.
+__device__ __forceinline__ uint64_t cdivmod(uint64_t x, uint32_t q, uint64_t rcp, uint64_t &rem) {
+    uint64_t qh = __umul64hi(x, rcp);
+    uint64_t r = x - qh * q;
+    if (r >= q) {
+        qh++;
+        r -= q;
+    }
+    rem = r;
+    return qh;
 }
 
 // Blocks walk chunks of 256 coefficients; chunk c of a [P][L][N] array is
@@ -67,9 +82,9 @@ __global__ void __launch_bounds__(CTH) to_montgomery_kernel(uint32_t *s, uint32_
     }
 }
 
-// c0 <- a and c1 <- [-a] for n ciphertexts [n][2][L][N]
-__global__ void __launch_bounds__(CTH) sample_a_kernel(uint32_t *ct, size_t n, uint32_t logN, uint32_t L,
-                                                       uint64_t seed, LimbTable lt) {
+// work[m] <- a and c1 <- [-a] for n ciphertexts [n][2][L][N]
+__global__ void __launch_bounds__(CTH) sample_a_kernel(uint32_t *ct, uint32_t *work, size_t n, uint32_t logN,
+                                                       uint32_t L, uint64_t seed, LimbTable lt) {
     const uint32_t cpl = 1u << (logN - 8);   // chunks per limb-polynomial
     const size_t LN = (size_t)L << logN, chunks = n * L * cpl;
     for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
@@ -80,31 +95,16 @@ __global__ void __launch_bounds__(CTH) sample_a_kernel(uint32_t *ct, size_t n, u
         const size_t idx = (c << 8) + threadIdx.x;     // (m L + i) N + j
         const uint32_t q = lt.c[i].q;
         const uint32_t a = (uint32_t)__umul64hi(hy_sm64(seed, 2 * (uint64_t)idx), (uint64_t)q);
-        uint32_t *c0 = ct + m * 2 * LN + (size_t)i * ((size_t)1 << logN) + j;
-        c0[0] = a;
-        c0[LN] = a ? q - a : 0;
+        const size_t r = ((size_t)i << logN) + j;
+        work[m * LN + r] = a;
+        ct[m * 2 * LN + LN + r] = a ? q - a : 0;
     }
 }
 
-// x <- x s mod q for n polynomials x_m = base + m stride ([L][N] each); s in Montgomery form
-__global__ void __launch_bounds__(CTH) mul_secret_kernel(uint32_t *base, size_t stride, size_t n, const uint32_t *s_hat,
-                                                         uint32_t logN, uint32_t L, LimbTable lt) {
-    const uint32_t cpl = 1u << (logN - 8);
-    const size_t chunks = n * L * cpl;
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t poly = c >> (logN - 8);
-        const size_t m = poly / L;
-        const uint32_t i = (uint32_t)(poly - m * L);
-        const uint32_t r = (uint32_t)((poly - m * L) << logN) + ((uint32_t)(c & (cpl - 1)) << 8) + threadIdx.x;
-        uint32_t *p = base + m * stride + r;
-        *p = cmont(*p, s_hat[r], lt.c[i]);
-    }
-}
-
-// c0 <- [Delta_i lift(msg) + c0 + lift(e)]_{q_i}; e drawn once per (m, j) for all limbs
-__global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const int32_t *msg, size_t n, uint32_t logN,
-                                                             uint32_t L, uint64_t seed, LimbTable lt, ClientConst cc,
-                                                             Thresholds th) {
+// c0 <- [Delta_i lift(msg) + work + lift(e)]_{q_i} (work = a s); e drawn once per (m, j) for all limbs
+__global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const uint32_t *work, const int32_t *msg,
+                                                             size_t n, uint32_t logN, uint32_t L, uint64_t seed,
+                                                             LimbTable lt, ClientConst cc, Thresholds th) {
     const uint32_t cpl = 1u << (logN - 8);
     const size_t LN = (size_t)L << logN, chunks = n * cpl;
     for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
@@ -117,28 +117,14 @@ __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const
         for (int k = 0; k < 2 * kErrBound; k++) cnt += (u >= th.t[k]);
         const int32_t e = cnt - kErrBound;
         const int32_t x = msg[mj];
-        uint32_t *c0 = ct + m * 2 * LN + j;
         for (uint32_t i = 0; i < L; i++) {
             const LimbConst lc = lt.c[i];
             const uint32_t q = lc.q;
+            const size_t r = ((size_t)i << logN) + j;
             const uint32_t dm = cmont(cc.dm[i], clift(x, q), lc);
             const uint32_t le = e >= 0 ? (uint32_t)e : q - (uint32_t)(-e);
-            uint32_t *p = c0 + ((size_t)i << logN);
-            *p = caddmod(caddmod(dm, *p, q), le, q);
+            ct[m * 2 * LN + r] = caddmod(caddmod(dm, work[m * LN + r], q), le, q);
         }
-    }
-}
-
-// work[m] <- c1 of ciphertext m
-__global__ void __launch_bounds__(CTH) copy_c1_kernel(const uint32_t *ct, uint32_t *work, size_t n, uint32_t logN,
-                                                      uint32_t L) {
-    const uint32_t cpl = 1u << (logN - 8);
-    const size_t LN = (size_t)L << logN, chunks = n * L * cpl;
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t poly = c >> (logN - 8);
-        const size_t m = poly / L;
-        const uint32_t r = (uint32_t)((poly - m * L) << logN) + ((uint32_t)(c & (cpl - 1)) << 8) + threadIdx.x;
-        work[m * LN + r] = ct[m * 2 * LN + LN + r];
     }
 }
 
@@ -159,9 +145,9 @@ __global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *ct,
             const size_t r = ((size_t)i << logN) + j;
             const uint64_t v = caddmod(work[m * LN + r], ct[m * 2 * LN + r], q);
             ipart += v * cc.A[i];
-            const uint64_t vb = v * cc.B[i];          // < 2^62
-            ipart += vb / q;
-            fsum += ((vb % q) << 32) / q;             // fraction in 32.32
+            uint64_t rem, unused;
+            ipart += cdivmod(v * cc.B[i], q, cc.rcp[i], rem);        // v B_i < 2^62
+            fsum += cdivmod(rem << 32, q, cc.rcp[i], unused);         // fraction in 32.32
         }
         const uint64_t rr = (ipart + ((fsum + (1ull << 31)) >> 32)) & (t - 1);
         msg[mj] = (int32_t)(rr > t / 2 ? (int64_t)rr - (int64_t)t : (int64_t)rr);
@@ -191,7 +177,10 @@ ClientConst client_constants(const hyena_ctx *c) {
     ClientConst cc{};
     const auto delta = bfv_delta_residues(c);
     bfv_hps_constants(c, cc.A, cc.B);
-    for (uint32_t i = 0; i < c->L; i++) cc.dm[i] = to_montgomery(delta[i], c->q[i]);
+    for (uint32_t i = 0; i < c->L; i++) {
+        cc.dm[i] = to_montgomery(delta[i], c->q[i]);
+        cc.rcp[i] = ~0ull / c->q[i];
+    }
     return cc;
 }
 
@@ -213,37 +202,35 @@ extern "C" int hyena_secret_prepare(const hyena_ctx *c, const int8_t *d_sk, uint
 }
 
 extern "C" int hyena_encrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat, const int32_t *d_msg, size_t n,
-                                    uint64_t seed, uint32_t *d_ct, hyena_stream_t stream) {
+                                    uint64_t seed, uint32_t *d_work, uint32_t *d_ct, hyena_stream_t stream) {
     static const char *who = "hyena_encrypt_device";
-    if (!c || !d_s_hat || (n && (!d_msg || !d_ct))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (!c || !d_s_hat || (n && (!d_msg || !d_work || !d_ct)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
     if (int rc = check_ctx(c, who)) return rc;
     if (n == 0) return HYENA_OK;
     const uint32_t N = c->N, L = c->L;
     const size_t LN = (size_t)L * N;
     if (n > (((size_t)1 << 31) - 1) / L) return set_error(HYENA_EINVAL, std::string(who) + ": too many messages");
-    if ((uintptr_t)d_ct & 15u) return set_error(HYENA_EINVAL, std::string(who) + ": d_ct is not 16-byte aligned");
-    const size_t ct_bytes = n * 2 * LN * 4;
-    if (overlaps(d_ct, ct_bytes, d_msg, n * N * 4) || overlaps(d_ct, ct_bytes, d_s_hat, LN * 4))
-        return set_error(HYENA_EINVAL, std::string(who) + ": d_ct overlaps an input");
+    if ((uintptr_t)d_work & 15u) return set_error(HYENA_EINVAL, std::string(who) + ": d_work is not 16-byte aligned");
+    const size_t ct_bytes = n * 2 * LN * 4, work_bytes = n * LN * 4, msg_bytes = n * N * 4;
+    if (overlaps(d_ct, ct_bytes, d_msg, msg_bytes) || overlaps(d_ct, ct_bytes, d_s_hat, LN * 4) ||
+        overlaps(d_work, work_bytes, d_ct, ct_bytes) || overlaps(d_work, work_bytes, d_msg, msg_bytes) ||
+        overlaps(d_work, work_bytes, d_s_hat, LN * 4))
+        return set_error(HYENA_EINVAL, std::string(who) + ": d_work or d_ct overlaps another array");
     const hipStream_t s = (hipStream_t)stream;
     const ClientConst cc = client_constants(c);
     Thresholds th;
     bfv_error_thresholds(th.t);
     const size_t chunks = (n * L) << (c->logN - 8);
-    hipLaunchKernelGGL(sample_a_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, n, c->logN, L, seed, c->lt);
-    if (int rc = launched(who)) return rc;
-    // NTT, product with NTT(s) and inverse NTT of every c0 (which holds a)
-    std::vector<uint32_t *> c0(n);
-    std::vector<size_t> one(n, 1);
-    for (size_t m = 0; m < n; m++) c0[m] = d_ct + m * 2 * LN;
-    if (int rc = launch_ntt_segs(c, c0.data(), one.data(), (uint32_t)n, false, -1, s)) return rc;
-    hipLaunchKernelGGL(mul_secret_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, 2 * LN, n, d_s_hat, c->logN, L,
+    hipLaunchKernelGGL(sample_a_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, d_work, n, c->logN, L, seed,
                        c->lt);
     if (int rc = launched(who)) return rc;
-    if (int rc = launch_ntt_segs(c, c0.data(), one.data(), (uint32_t)n, true, -1, s)) return rc;
+    // a s = INTT(NTT(a) . NTT(s)) in the workspace, the product fused into the forward transform's store
+    if (int rc = launch_ntt_fwd_mul(c, d_work, LN, n, d_work, d_s_hat, s)) return rc;
+    if (int rc = launch_ntt(c, d_work, n, true, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
-    hipLaunchKernelGGL(encrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_msg, n, c->logN, L, seed,
-                       c->lt, cc, th);
+    hipLaunchKernelGGL(encrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_work, d_msg, n,
+                       c->logN, L, seed, c->lt, cc, th);
     return launched(who);
 }
 
@@ -265,13 +252,9 @@ extern "C" int hyena_decrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
         return set_error(HYENA_EINVAL, std::string(who) + ": d_work or d_msg overlaps another array");
     const hipStream_t s = (hipStream_t)stream;
     const ClientConst cc = client_constants(c);
-    const size_t chunks = (n * L) << (c->logN - 8);
-    hipLaunchKernelGGL(copy_c1_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, d_work, n, c->logN, L);
-    if (int rc = launched(who)) return rc;
-    if (int rc = launch_ntt(c, d_work, n, false, s)) return rc;
-    hipLaunchKernelGGL(mul_secret_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_work, LN, n, d_s_hat, c->logN, L,
-                       c->lt);
-    if (int rc = launched(who)) return rc;
+    // c1 s = INTT(NTT(c1) . NTT(s)): the forward transform reads c1 of every ciphertext in place
+    // and writes the product into the workspace
+    if (int rc = launch_ntt_fwd_mul(c, d_ct + LN, 2 * LN, n, d_work, d_s_hat, s)) return rc;
     if (int rc = launch_ntt(c, d_work, n, true, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
     hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_work, d_msg, n, c->logN,

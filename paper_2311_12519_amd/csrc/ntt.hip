@@ -18,7 +18,7 @@
 // conflicts of the strided passes. Polynomials must be 16-byte aligned.
 #include <algorithm>
 
-#include "internal.h"
+#include "bfv.h"
 
 namespace {
 
@@ -349,6 +349,61 @@ ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32
     else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lt.c[limb].qinv_neg, lds);
 }
 
+// Forward transform with a gathered source and a pointwise product on the
+// store, for the client operations: block p (limb-polynomial p of a [P][L][N]
+// result) reads limb p mod L of polynomial p / L at src + (p / L) src_stride,
+// transforms it as ntt_kernel does and stores NTT(a) . m mod q, with mul
+// holding m 2^32 mod q in [L][N] (Montgomery form). src may equal dst (the
+// whole polynomial is in registers before the first store).
+template <int LOGT, int E_LOG, int EP>
+__device__ __forceinline__ void store_runs_mul(const uint32_t (&x)[1 << E_LOG], uint32_t *__restrict__ a,
+                                               const uint32_t *__restrict__ mul, uint32_t q, uint32_t qn,
+                                               uint32_t tid) {
+    constexpr int GE = 1 << EP, NG = (1 << E_LOG) >> EP;
+    static_assert(GE >= 4, "runs of at least four residues");
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++) {
+        const size_t base = (size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EP;
+#pragma unroll
+        for (int r = 0; r < GE; r += 4) {
+            const uint4 m = *reinterpret_cast<const uint4 *>(mul + base + r);
+            *reinterpret_cast<uint4 *>(a + base + r) = make_uint4(
+                csub(mont_mul(x[kg * GE + r], m.x, q, qn), q), csub(mont_mul(x[kg * GE + r + 1], m.y, q, qn), q),
+                csub(mont_mul(x[kg * GE + r + 2], m.z, q, qn), q), csub(mont_mul(x[kg * GE + r + 3], m.w, q, qn), q));
+        }
+    }
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
+ntt_fwd_mul_kernel(const uint32_t *src, size_t src_stride, uint32_t *dst, const uint32_t *__restrict__ mul,
+                   const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << (LOGN - LOGT);
+    __shared__ uint32_t lds[N + N / 32];
+    const uint32_t p = blockIdx.x, limb = p % L, poly = p / L;
+    const uint32_t *a = src + (size_t)poly * src_stride + (size_t)limb * N;
+    const uint32_t *tw = tw_all + (size_t)limb * N;
+    const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg, tid = threadIdx.x;
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
+    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
+    store_runs_mul<LOGT, LOGN - LOGT, (E3 > 0 ? E3 : E2)>(x, dst + (size_t)p * N, mul + (size_t)limb * N, q, qn, tid);
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
+                          const uint32_t *mul, hipStream_t s) {
+    const dim3 grid((unsigned)(P * c->L)), block(1u << LOGT);
+    if (c->lazy_ntt)
+        hipLaunchKernelGGL((ntt_fwd_mul_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, src, src_stride,
+                           dst, mul, c->d_fw, c->lt, c->L);
+    else
+        hipLaunchKernelGGL((ntt_fwd_mul_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, src,
+                           src_stride, dst, mul, c->d_fw, c->lt, c->L);
+    return hipGetLastError();
+}
+
 // Persistent inverse transform: a grid of a few blocks per CU (a multiple of
 // L, so a block keeps one limb); block b transforms limb-polynomials b,
 // b + grid, ... and loads the next one's first-pass residues into registers
@@ -600,6 +655,26 @@ int launch_ntt_sched(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, int sc
 
 int launch_ntt(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, hipStream_t s) {
     return launch_ntt_sched(c, d, P, inv, -1, s);
+}
+
+int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
+                       const uint32_t *mul, hipStream_t s) {
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
+    if (P == 0) return HYENA_OK;
+    if (P * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
+    if (((uintptr_t)dst | (uintptr_t)mul) & 15u)
+        return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
+    hipError_t e;
+    switch (c->logN) {   // the default schedule of each N (one block per limb-polynomial)
+        case 10: e = launch_fwd_mul<10, 6, 4, 3, 3, 0>(c, src, src_stride, P, dst, mul, s); break;
+        case 11: e = launch_fwd_mul<11, 7, 4, 4, 3, 0>(c, src, src_stride, P, dst, mul, s); break;
+        case 12: e = launch_fwd_mul<12, 8, 4, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
+        case 13: e = launch_fwd_mul<13, 8, 5, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
+        case 14: e = launch_fwd_mul<14, 10, 4, 4, 4, 2>(c, src, src_stride, P, dst, mul, s); break;
+        default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
+    }
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
+    return HYENA_OK;
 }
 
 extern "C" int hyena_ntt_schedules(uint32_t N, int *first, int *count) {

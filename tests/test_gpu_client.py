@@ -54,7 +54,8 @@ def encrypt_dev(ctx, d_s_hat, msg, seed):
     import torch
     d_msg = torch.from_numpy(np.ascontiguousarray(msg, dtype=np.int32)).cuda()
     d_ct = torch.full((msg.shape[0] * 2 * ctx.L * ctx.N,), -1, dtype=torch.int32, device="cuda")
-    hy.hyena_encrypt_device(ctx, d_s_hat, d_msg, seed, d_ct)
+    d_work = torch.full((msg.shape[0] * ctx.L * ctx.N,), -1, dtype=torch.int32, device="cuda")
+    hy.hyena_encrypt_device(ctx, d_s_hat, d_msg, seed, d_work, d_ct)
     torch.cuda.synchronize()
     return d_ct, d_ct.cpu().numpy().view(np.uint32).reshape(msg.shape[0], 2, ctx.L, ctx.N)
 
@@ -81,8 +82,8 @@ def test_secret_prepare_matches_oracle(dev, N, L, bits):
         assert np.array_equal(got[i].astype(np.uint64), want), i
 
 
-# (N, L, prime bits, messages): several chunks per polynomial, one and several
-# NTT launches (a launch takes at most 48 ciphertexts), both prime sizes
+# (N, L, prime bits, messages): one and several chunks per polynomial, one and
+# several messages, both prime sizes
 ORACLE_CASES = [(1024, 1, 31, 1), (1024, 2, 31, 3), (4096, 2, 30, 2), (8192, 3, 31, 2)]
 
 
@@ -175,10 +176,13 @@ def test_client_device_rejects_bad_arguments(dev):
     d_s_hat = prepared(ctx, orc.keygen(N, 1))
     buf = torch.zeros(4 * 2 * L * N + 4, dtype=torch.int32, device="cuda")
     msg = torch.zeros(2 * N, dtype=torch.int32, device="cuda")
-    with pytest.raises(hy.HyenaError):               # d_ct not 16-byte aligned
-        hy.hyena_encrypt_device(ctx, d_s_hat, msg, 1, buf[1:1 + 2 * 2 * L * N])
+    work = torch.zeros(2 * L * N + 4, dtype=torch.int32, device="cuda")
+    with pytest.raises(hy.HyenaError):               # workspace not 16-byte aligned
+        hy.hyena_encrypt_device(ctx, d_s_hat, msg, 1, work[1:1 + 2 * L * N], buf[:2 * 2 * L * N])
     with pytest.raises(hy.HyenaError):               # d_ct overlapping d_msg
-        hy.hyena_encrypt_device(ctx, d_s_hat, buf[:2 * N], 1, buf[:2 * 2 * L * N])
+        hy.hyena_encrypt_device(ctx, d_s_hat, buf[:2 * N], 1, work[:2 * L * N], buf[:2 * 2 * L * N])
+    with pytest.raises(hy.HyenaError):               # workspace overlapping d_ct
+        hy.hyena_encrypt_device(ctx, d_s_hat, msg, 1, buf[2 * L * N:4 * L * N], buf[:2 * 2 * L * N])
     ct = buf[:2 * 2 * L * N]
     with pytest.raises(hy.HyenaError):               # workspace overlapping the ciphertexts
         hy.hyena_decrypt_device(ctx, d_s_hat, ct, buf[2 * 2 * L * N - 4 * L:], msg)
@@ -186,5 +190,5 @@ def test_client_device_rejects_bad_arguments(dev):
         hy.hyena_decrypt_device(ctx, d_s_hat, ct, buf[:L * N], msg)
     # no messages: nothing is launched, nothing written
     empty = torch.zeros(0, dtype=torch.int32, device="cuda")
-    hy.hyena_encrypt_device(ctx, d_s_hat, empty, 1, empty)
+    hy.hyena_encrypt_device(ctx, d_s_hat, empty, 1, empty, empty)
     hy.hyena_decrypt_device(ctx, d_s_hat, empty, empty, empty)

@@ -162,8 +162,8 @@ def test_client_device_calls_refused_on_host_only_context():
     null = ctypes.c_void_p(0)
     assert L.hyena_secret_prepare(ctx.handle, null, fake, null) == hy.HYENA_EINVAL
     assert L.hyena_secret_prepare(ctx.handle, fake, fake, null) == hy.HYENA_EINVAL   # host-only
-    assert L.hyena_encrypt_device(ctx.handle, fake, null, 1, 5, fake, null) == hy.HYENA_EINVAL
-    assert L.hyena_encrypt_device(ctx.handle, fake, fake, 1, 5, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_encrypt_device(ctx.handle, fake, null, 1, 5, fake, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_encrypt_device(ctx.handle, fake, fake, 1, 5, fake, fake, null) == hy.HYENA_EINVAL
     assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, null, fake, null) == hy.HYENA_EINVAL
     assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, fake, fake, null) == hy.HYENA_EINVAL
     assert "host-only" in L.hyena_last_error().decode()
