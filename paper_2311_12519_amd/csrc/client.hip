@@ -15,6 +15,8 @@ namespace {
 
 constexpr uint32_t CTH = 256;   // threads per block; one block covers 256 coefficients
 
+static_assert((kErrBound & (kErrBound - 1)) == 0 && 2 * kErrBound <= CTH, "sampler search over 2B thresholds");
+
 struct Thresholds {
     uint64_t t[2 * kErrBound];
 };
@@ -105,6 +107,9 @@ __global__ void __launch_bounds__(CTH) sample_a_kernel(uint32_t *ct, uint32_t *w
 __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const uint32_t *work, const int32_t *msg,
                                                              size_t n, uint32_t logN, uint32_t L, uint64_t seed,
                                                              LimbTable lt, ClientConst cc, Thresholds th) {
+    __shared__ uint64_t thr[2 * kErrBound];
+    if (threadIdx.x < 2 * kErrBound) thr[threadIdx.x] = th.t[threadIdx.x];
+    __syncthreads();
     const uint32_t cpl = 1u << (logN - 8);
     const size_t LN = (size_t)L << logN, chunks = n * cpl;
     for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
@@ -112,10 +117,14 @@ __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const
         const size_t mj = (c << 8) + threadIdx.x;      // m N + j
         const uint32_t j = (uint32_t)(mj & ((1u << logN) - 1));
         const uint64_t u = hy_sm64(seed, 2 * (uint64_t)mj + 1) >> 1;
-        int cnt = 0;
+        // #{k < 2B : u >= T[k]}: the thresholds are nondecreasing, so the count
+        // is the length of the prefix below u, found by binary search
+        uint32_t cnt = 0;
 #pragma unroll
-        for (int k = 0; k < 2 * kErrBound; k++) cnt += (u >= th.t[k]);
-        const int32_t e = cnt - kErrBound;
+        for (uint32_t step = kErrBound; step >= 1; step >>= 1)
+            if (u >= thr[cnt + step - 1]) cnt += step;
+        if (cnt == 2 * kErrBound - 1 && u >= thr[2 * kErrBound - 1]) cnt++;
+        const int32_t e = (int32_t)cnt - kErrBound;
         const int32_t x = msg[mj];
         for (uint32_t i = 0; i < L; i++) {
             const LimbConst lc = lt.c[i];
@@ -221,6 +230,8 @@ extern "C" int hyena_encrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     const ClientConst cc = client_constants(c);
     Thresholds th;
     bfv_error_thresholds(th.t);
+    for (int k = 0; k + 1 < 2 * kErrBound; k++)   // the kernel's binary search relies on it
+        if (th.t[k] > th.t[k + 1]) return set_error(HYENA_EINVAL, std::string(who) + ": sampler table not monotone");
     const size_t chunks = (n * L) << (c->logN - 8);
     hipLaunchKernelGGL(sample_a_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, d_work, n, c->logN, L, seed,
                        c->lt);
