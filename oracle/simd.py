@@ -1,0 +1,164 @@
+"""Oracle for the SIMD (batch-encoded) BFV pieces of the paper's own setting.
+
+TEST INFRASTRUCTURE ONLY, like the rest of ``oracle``: only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may use
+it. It shares no code with the GPU library and never imports it.
+
+What it computes, in the paper's terms:
+
+* SIMD batch encoding with a prime plaintext modulus p = 1 mod 2n (the
+  "Homomorphic Operations in BFV" section: slots are the CRT components of
+  R_p; step 1 of the "Optimal Parameter Selection" procedure), by its plain
+  definition: the plaintext polynomial m with m(zeta^{e_s}) = v_s mod p for
+  every slot s, zeta the least primitive 2n-th root of unity mod p.
+* The plaintext packing [1, -1] (first half of the slots 1, second half -1)
+  and its two equal nonzero coefficients h_{p,n}; the plaintext packing
+  [k, -k] and the search for the k that minimises k h_{p,n} mod p (steps 2
+  and 3 of the "Optimal Parameter Selection" procedure).
+* The worst-case noise factors of PMult quoted in that section: n p / 2 for a
+  general plaintext, (f0 + f1 + 2 (f0 - f1) c) / 2 for the Walsh form with the
+  [1, -1] (c = h) or [k, -k] (c = k h mod p) plaintext.
+* The model storage of the "Enabling Output Channel Packing" section's
+  example: one plaintext polynomial plus one word per kernel element, against
+  one plaintext polynomial per kernel element.
+* Galois automorphisms a(X) -> a(X^g) in R_q (the map behind HRot, "Homomorphic
+  Operations in BFV") and PMult by a plaintext in R_q (a negacyclic product).
+
+Readings where the paper is silent: slot s < n/2 holds the value at
+zeta^(3^s mod 2n) and slot n/2 + s the value at zeta^(-3^s mod 2n) (the
+generator-3 two-row layout of the batch encoder used with the paper's
+parameters; with the least primitive root it gives the paper's
+h_{2048,307201} = 84248); plaintext coefficients enter PMult as integers in
+[0, p), the representation the paper's "minimise k h mod p" criterion
+measures.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import find_psi, negacyclic_mul
+
+
+def primitive_root_2n(p: int, n: int) -> int:
+    """The least integer zeta >= 2 with zeta^n = -1 mod p."""
+    return find_psi(p, n)
+
+
+def slot_exponents(n: int) -> np.ndarray:
+    """e_s for s < n: 3^s mod 2n for the first row, -3^s mod 2n for the second."""
+    row = np.empty(n // 2, dtype=np.int64)
+    g = 1
+    for s in range(n // 2):
+        row[s] = g
+        g = g * 3 % (2 * n)
+    return np.concatenate([row, (2 * n - row) % (2 * n)])
+
+
+def _power_table(z: int, p: int, n: int) -> np.ndarray:
+    """z^e mod p for e < 2n."""
+    t = np.empty(2 * n, dtype=np.uint64)
+    x = 1
+    for e in range(2 * n):
+        t[e] = x
+        x = x * z % p
+    return t
+
+
+def encode(values, p: int, n: int) -> np.ndarray:
+    """The polynomial m (coefficients in [0, p)) with m(zeta^{e_s}) = v_s:
+    m_k = n^{-1} sum_s v_s zeta^{-e_s k} mod p (the inverse of the evaluation
+    at the n distinct roots of X^n + 1). p < 2^24 keeps every sum in 64 bits."""
+    assert p < (1 << 24) and (p - 1) % (2 * n) == 0
+    v = np.mod(np.asarray(values, dtype=np.int64), p).astype(np.uint64)
+    assert v.shape == (n,)
+    z = primitive_root_2n(p, n)
+    tinv = _power_table(pow(z, p - 2, p), p, n)
+    e = slot_exponents(n).astype(np.uint64)
+    ks = np.arange(n, dtype=np.uint64)
+    m = np.empty(n, dtype=np.uint64)
+    for k in range(n):
+        m[k] = int((v * tinv[(e * ks[k]) % np.uint64(2 * n)]).sum() % np.uint64(p))
+    return (m * np.uint64(pow(n, p - 2, p)) % np.uint64(p)).astype(np.uint32)
+
+
+def decode(m, p: int, n: int) -> np.ndarray:
+    """v_s = m(zeta^{e_s}) mod p."""
+    assert p < (1 << 24) and (p - 1) % (2 * n) == 0
+    m = np.asarray(m, dtype=np.uint64) % np.uint64(p)
+    z = primitive_root_2n(p, n)
+    t = _power_table(z, p, n)
+    e = slot_exponents(n).astype(np.uint64)
+    ks = np.arange(n, dtype=np.uint64)
+    out = np.empty(n, dtype=np.uint64)
+    for s in range(n):
+        out[s] = int((m * t[(e[s] * ks) % np.uint64(2 * n)]).sum() % np.uint64(p))
+    return out.astype(np.uint32)
+
+
+def pm_plaintext(n: int, p: int, k: int = 1) -> np.ndarray:
+    """The plaintext packing [k, -k]: k in the first n/2 slots, -k in the rest."""
+    return encode([k] * (n // 2) + [-k] * (n // 2), p, n)
+
+
+def h_pn(n: int, p: int) -> int:
+    """h_{p,n}: the common value of the two nonzero coefficients of the
+    plaintext packing [1, -1] (at X^{n/4} and X^{3n/4})."""
+    m = pm_plaintext(n, p)
+    nz = np.flatnonzero(m)
+    assert list(nz) == [n // 4, 3 * n // 4] and m[nz[0]] == m[nz[1]], nz
+    return int(m[nz[0]])
+
+
+def best_k(h: int, p: int, kmax: int):
+    """(k, k h mod p) with k in [1, kmax] minimising k h mod p (the least such k)."""
+    best = None
+    for k in range(1, kmax + 1):
+        c = k * h % p
+        if best is None or c < best[1]:
+            best = (k, c)
+    return best
+
+
+def noise_factor_conventional(n: int, p: int) -> float:
+    """Worst-case noise growth of PMult by a general plaintext: n p / 2."""
+    return n * p / 2
+
+
+def noise_factor_walsh(f0: int, f1: int, c: int) -> float:
+    """Worst-case noise growth of the Walsh form of PMult by [f0, f1]:
+    (f0 + f1 + 2 (f0 - f1) c) / 2, c the coefficient of the [1, -1] (or
+    [k, -k]) plaintext; magnitudes, so that signed kernel elements count by
+    their size."""
+    return (abs(f0 + f1) + 2 * abs(f0 - f1) * c) / 2
+
+
+def storage_bytes(n: int, elements: int, word_bytes: int = 8):
+    """(proposed, conventional) model storage: one plaintext polynomial of n
+    words plus one word per kernel element, against one plaintext polynomial
+    per kernel element."""
+    return n * word_bytes + elements * word_bytes, elements * n * word_bytes
+
+
+def automorphism(a, g: int, q: int) -> np.ndarray:
+    """a(X^g) in Z_q[X]/(X^n + 1) for odd g: coefficient j moves to j g mod 2n,
+    negated when that exponent is n or more (X^n = -1)."""
+    a = np.asarray(a, dtype=np.int64)
+    n = a.shape[0]
+    assert g % 2 == 1
+    out = np.zeros(n, dtype=np.int64)
+    for j in range(n):
+        e = j * g % (2 * n)
+        if e < n:
+            out[e] = (out[e] + a[j]) % q
+        else:
+            out[e - n] = (out[e - n] - a[j]) % q
+    return out.astype(np.uint32)
+
+
+def pmult(a, plain, q: int) -> np.ndarray:
+    """a * plain in Z_q[X]/(X^n + 1), the plaintext's coefficients taken as the
+    integers in [0, p) they are stored as."""
+    return negacyclic_mul(np.asarray(a, dtype=np.uint32), np.mod(np.asarray(plain, dtype=np.int64), q).astype(np.uint32),
+                          q)

@@ -1,0 +1,143 @@
+"""Pins of the SIMD oracle (oracle/simd.py) against the paper's worked
+examples, closed forms and brute force; CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from oracle import simd
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "simd_parameter_example.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        out[k] = float(v) if "." in v else int(v)
+    return out
+
+
+def test_h_of_the_papers_example():
+    g = golden()
+    n, p = g["n"], g["p"]
+    m = simd.pm_plaintext(n, p)
+    assert list(np.flatnonzero(m)) == [n // 4, 3 * n // 4]        # two nonzero coefficients, equal
+    assert simd.h_pn(n, p) == g["h"]
+    assert g["h"].bit_length() == g["h_bits"]
+
+
+def test_h_is_a_square_root_of_minus_one_half():
+    """Closed form: the [1, -1] plaintext is h (X^{n/4} + X^{3n/4}); at a root
+    w = zeta^{n/4} of unity of order 8 it takes h (w + w^3), and (w + w^3)^2 =
+    -2, so 2 h^2 + 1 = 0 mod p, for any (n, p)."""
+    for n, p in [(2048, 307201), (1024, 12289), (1024, 307201), (4096, 65537)]:
+        if (p - 1) % (2 * n):
+            continue
+        h = simd.h_pn(n, p)
+        assert (2 * h * h + 1) % p == 0, (n, p)
+
+
+def test_best_k_of_the_papers_example():
+    g = golden()
+    k, kh = simd.best_k(g["h"], g["p"], 61)
+    assert k == g["k"] and kh == g["k"] * g["h"] % g["p"] == 5125
+    # the paper does not state the search bound: k = 11 is the minimiser for
+    # k <= 61 only (62 h mod p = 959)
+    assert simd.best_k(g["h"], g["p"], 62) == (62, 959)
+    # brute force over the same range, written out
+    vals = [(j * g["h"]) % g["p"] for j in range(1, 62)]
+    assert vals.index(min(vals)) + 1 == 11
+
+
+def test_noise_bits_of_the_papers_example():
+    g = golden()
+    n, p, h = g["n"], g["p"], g["h"]
+    assert math.ceil(math.log2(simd.noise_factor_conventional(n, p))) == g["noise_bits_general"]
+    for lo, hi in [(0, 255), (-128, 127)]:                        # 8-bit kernel elements, either sign convention
+        worst = max(simd.noise_factor_walsh(a, b, h) for a in (lo, hi) for b in (lo, hi))
+        assert math.ceil(math.log2(worst)) == g["noise_bits_walsh"]
+        worst_k = max(simd.noise_factor_walsh(a, b, g["k"] * h % p) for a in (lo, hi) for b in (lo, hi))
+        assert math.ceil(math.log2(worst_k)) == g["noise_bits_walsh_k"]
+
+
+def test_storage_of_the_papers_example():
+    g = golden()
+    prop, conv = simd.storage_bytes(g["n"], g["kernel_elements"])
+    assert round(prop / 1024, 1) == g["storage_proposed_KB"]
+    assert conv / 1024 == g["storage_conventional_KB"]
+
+
+@pytest.mark.parametrize("n,p", [(1024, 12289), (2048, 307201)])
+def test_encode_is_evaluation_at_the_roots(n, p):
+    """decode(encode(v)) = v; slot-wise products are negacyclic products
+    (encoding is the CRT of Z_p[X]/(X^n+1) at the n roots of X^n + 1);
+    constants encode to constants."""
+    rng = np.random.default_rng(n)
+    u = rng.integers(0, p, n)
+    v = rng.integers(0, p, n)
+    mu, mv = simd.encode(u, p, n), simd.encode(v, p, n)
+    assert np.array_equal(simd.decode(mu, p, n), u)
+    assert np.array_equal(orc.negacyclic_mul(mu, mv, p), simd.encode(u * v % p, p, n))
+    c = simd.encode([7] * n, p, n)
+    assert c[0] == 7 and not c[1:].any()
+    # the slot exponents are the n distinct odd residues mod 2n
+    e = simd.slot_exponents(n)
+    assert sorted(e.tolist()) == list(range(1, 2 * n, 2))
+
+
+def test_slot_layout_under_galois_maps():
+    """X -> X^3 rotates both rows by one slot; X -> X^{2n-1} swaps the rows
+    (pins the generator-3 two-row slot layout)."""
+    n, p = 1024, 12289
+    rng = np.random.default_rng(3)
+    v = rng.integers(0, p, n)
+    m = simd.encode(v, p, n)
+    rot = simd.decode(simd.automorphism(m, 3, p), p, n)
+    h = n // 2
+    assert np.array_equal(rot[:h], np.roll(v[:h], -1)) and np.array_equal(rot[h:], np.roll(v[h:], -1))
+    sw = simd.decode(simd.automorphism(m, 2 * n - 1, p), p, n)
+    assert np.array_equal(sw[:h], v[h:]) and np.array_equal(sw[h:], v[:h])
+
+
+def test_automorphism_brute_force_and_group_laws():
+    """a(X^g) by substitution and reduction of the full polynomial for tiny n;
+    monomials map to signed monomials; sigma_g2 o sigma_g1 = sigma_{g1 g2}."""
+    q = 97
+    rng = np.random.default_rng(5)
+    for n in (8, 16):
+        a = rng.integers(0, q, n)
+        for g in (3, 5, 2 * n - 1, 7):
+            full = np.zeros(n * g + 1, dtype=np.int64)
+            for j in range(n):
+                full[j * g] += a[j]
+            red = np.zeros(n, dtype=np.int64)                     # X^n = -1
+            for e, c in enumerate(full):
+                red[e % n] += c if (e // n) % 2 == 0 else -c
+            assert np.array_equal(simd.automorphism(a, g, q), np.mod(red, q))
+        g1, g2 = 3, 5
+        assert np.array_equal(simd.automorphism(simd.automorphism(a, g1, q), g2, q),
+                              simd.automorphism(a, g1 * g2 % (2 * n), q))
+        ginv = pow(3, -1, 2 * n)
+        assert np.array_equal(simd.automorphism(simd.automorphism(a, 3, q), ginv, q), a)
+
+
+def test_pmult_by_the_pm_plaintext_is_two_shifts():
+    """PMult by h (X^{n/4} + X^{3n/4}) equals h times the sum of the two
+    negacyclic shifts of the ciphertext polynomial (brute force)."""
+    n, p, q = 1024, 12289, orc.ntt_primes(1024, 1, 31)[0]
+    rng = np.random.default_rng(9)
+    a = rng.integers(0, q, n).astype(np.uint32)
+    w = simd.pm_plaintext(n, p, 3)
+    h3 = int(w[n // 4])
+    got = simd.pmult(a, w, q)
+    sh = np.zeros(n, dtype=object)
+    for j in range(n):
+        for e in (n // 4, 3 * n // 4):
+            t = j + e
+            sh[t % n] += int(a[j]) if t < n else -int(a[j])
+    assert np.array_equal(got.astype(object), np.array([(h3 * x) % q for x in sh], dtype=object))
