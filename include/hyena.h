@@ -61,6 +61,11 @@ enum {
 /* hyena_create flags */
 #define HYENA_ALLOW_INSECURE 0x1u /* skip the 128-bit security ceiling on log2 q */
 #define HYENA_HOST_ONLY 0x2u      /* no device tables: only the host calls may be used */
+#define HYENA_PLAINTEXT_PRIME 0x4u /* primes may be any prime below 2^31 with q = 1 mod 2N:
+                                      a context over the SIMD plaintext modulus p (L = 1)
+                                      for hyena_simd_encode/decode and the NTT; no
+                                      security ceiling applies (it is not a ciphertext
+                                      modulus) */
 
 typedef struct hyena_ctx hyena_ctx;
 
@@ -319,6 +324,60 @@ int hyena_conv_default_schedule(const hyena_conv_desc *desc);
 int hyena_conv_tiled(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                      const uint32_t *d_ct_ntt, const uint32_t *d_wntt,
                      uint32_t *d_out_ntt, int sched, hyena_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The paper's own SIMD setting (batch encoding with a prime plaintext modulus
+ * p = 1 mod 2n): the parameter selection of the "Optimal Parameter Selection"
+ * section and the building blocks of its convolution ("Homomorphic
+ * Operations in BFV": PMult, the automorphisms behind HRot). Slot s < n/2
+ * holds the value at zeta^(3^s mod 2n), slot n/2 + s the value at
+ * zeta^(-3^s mod 2n), zeta the least primitive 2n-th root of unity mod p.
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Host. h_{p,n}: the two equal nonzero coefficients (at X^(n/4), X^(3n/4)) of
+ * the plaintext packing [1, -1] (1 in the first n/2 slots, -1 in the rest);
+ * k in [1, kmax] minimising k h mod p (the least such k) and kh = k h mod p,
+ * the coefficients of the plaintext packing [k, -k]. n a power of two >= 8,
+ * p prime < 2^31, p = 1 mod 2n. Outputs may be NULL. Errors: EINVAL.
+ */
+int hyena_simd_params(uint32_t n, uint32_t p, uint32_t kmax, uint32_t *h, uint32_t *k,
+                      uint32_t *kh);
+
+/*
+ * Batch encoding on the device, for a context created with
+ * HYENA_PLAINTEXT_PRIME and L = 1 (its prime is p, its N is n):
+ * hyena_simd_encode: d_slots device uint32 [P][N] slot values (reduced mod p
+ * if not below it) -> d_coef device uint32 [P][N], 16-byte aligned, the
+ * plaintext polynomials m with m(zeta^e_s) = v_s. hyena_simd_decode: the
+ * inverse; d_coef (16-byte aligned) is overwritten with its NTT. The two
+ * arrays must not overlap. Errors: EINVAL (also for L != 1), EHIP.
+ */
+int hyena_simd_encode(const hyena_ctx *ctx, const uint32_t *d_slots, size_t P, uint32_t *d_coef,
+                      hyena_stream_t stream);
+int hyena_simd_decode(const hyena_ctx *ctx, uint32_t *d_coef, size_t P, uint32_t *d_slots,
+                      hyena_stream_t stream);
+
+/*
+ * Galois automorphism a(X) -> a(X^g) mod (X^N + 1, q_i) of P polynomials
+ * [P][L][N] (coefficient domain), g odd (EINVAL otherwise). On slots,
+ * g = 3^r rotates both rows by r, g = 2N - 1 swaps them. d_in, d_out device
+ * uint32 [P][L][N], not overlapping. Errors: EINVAL, EHIP.
+ */
+int hyena_automorphism(const hyena_ctx *ctx, const uint32_t *d_in, size_t P, uint32_t g,
+                       uint32_t *d_out, hyena_stream_t stream);
+
+/*
+ * PMult by a sparse plaintext w = sum_t coefs[t] X^exps[t] (at most 16
+ * monomials; exps[t] < 2N, coefs[t] the plaintext integers, e.g. in [0, p)):
+ *   d_out = w * d_in  mod (X^N + 1, q_i), for P polynomials [P][L][N].
+ * With the two monomials kh X^(N/4) + kh X^(3N/4) this is PMult by the
+ * [k, -k] plaintext. exps, coefs: host arrays. d_in, d_out device, not
+ * overlapping. Errors: EINVAL, EHIP.
+ */
+int hyena_pmult_sparse(const hyena_ctx *ctx, const uint32_t *d_in, size_t P, uint32_t n_terms,
+                       const uint32_t *exps, const uint32_t *coefs, uint32_t *d_out,
+                       hyena_stream_t stream);
 
 /*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):

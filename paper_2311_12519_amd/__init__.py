@@ -28,6 +28,7 @@ HYENA_ENOMEM = -5
 
 HYENA_ALLOW_INSECURE = 0x1
 HYENA_HOST_ONLY = 0x2
+HYENA_PLAINTEXT_PRIME = 0x4
 HYENA_PRIMES_30BIT = 0x100
 HYENA_FUSE_WHT = 0x1
 HYENA_BATCH_PERSISTENT = 0x1
@@ -81,6 +82,11 @@ _SIGS = {
     "hyena_secret_prepare": [_P, _P, _P, _P],
     "hyena_encrypt_device": [_P, _P, _P, _sz, _u64, _P, _P, _P],
     "hyena_decrypt_device": [_P, _P, _P, _sz, _P, _P, _P],
+    "hyena_simd_params": [_u32, _u32, _u32, _P, _P, _P],
+    "hyena_simd_encode": [_P, _P, _sz, _P, _P],
+    "hyena_simd_decode": [_P, _P, _sz, _P, _P],
+    "hyena_automorphism": [_P, _P, _sz, _u32, _P, _P],
+    "hyena_pmult_sparse": [_P, _P, _sz, _u32, _P, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -337,6 +343,57 @@ def hyena_decrypt_device(ctx: Ctx, d_s_hat, d_ct, d_work, d_msg, stream=None) ->
         raise ValueError(f"d_work has {d_work.numel()} elements, needs {n * ctx.L * ctx.N}")
     _check(lib().hyena_decrypt_device(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_ct, "int32"), n,
                                       _dev_ptr(d_work, "int32"), _dev_ptr(d_msg, "int32"), _stream(stream)))
+
+
+def hyena_simd_params(n: int, p: int, kmax: int):
+    """(h_{p,n}, k, k h mod p): the [1, -1] plaintext's coefficient and the
+    k in [1, kmax] minimising k h mod p."""
+    h, k, kh = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().hyena_simd_params(n, p, kmax, ctypes.byref(h), ctypes.byref(k), ctypes.byref(kh)))
+    return h.value, k.value, kh.value
+
+
+def _polys(ctx: Ctx, t, limbs: int) -> int:
+    P = t.numel() // (limbs * ctx.N)
+    if P * limbs * ctx.N != t.numel():
+        raise ValueError("tensor size is not a multiple of the polynomial size")
+    return P
+
+
+def hyena_simd_encode(ctx: Ctx, d_slots, d_coef, stream=None) -> None:
+    """Slots [P][N] (mod p) -> plaintext polynomials [P][N] (plaintext-prime context)."""
+    P = _polys(ctx, d_slots, 1)
+    _need(d_coef, P * ctx.N, "d_coef")
+    _check(lib().hyena_simd_encode(ctx.handle, _dev_ptr(d_slots, "int32"), P, _dev_ptr(d_coef, "int32"),
+                                   _stream(stream)))
+
+
+def hyena_simd_decode(ctx: Ctx, d_coef, d_slots, stream=None) -> None:
+    """Plaintext polynomials [P][N] -> slots [P][N]; d_coef is overwritten with its NTT."""
+    P = _polys(ctx, d_coef, 1)
+    _need(d_slots, P * ctx.N, "d_slots")
+    _check(lib().hyena_simd_decode(ctx.handle, _dev_ptr(d_coef, "int32"), P, _dev_ptr(d_slots, "int32"),
+                                   _stream(stream)))
+
+
+def hyena_automorphism(ctx: Ctx, d_in, g: int, d_out, stream=None) -> None:
+    """d_out = d_in(X^g) for polynomials [P][L][N]."""
+    P = _polys(ctx, d_in, ctx.L)
+    _need(d_out, d_in.numel(), "d_out")
+    _check(lib().hyena_automorphism(ctx.handle, _dev_ptr(d_in, "int32"), P, g, _dev_ptr(d_out, "int32"),
+                                    _stream(stream)))
+
+
+def hyena_pmult_sparse(ctx: Ctx, d_in, exps, coefs, d_out, stream=None) -> None:
+    """d_out = (sum_t coefs[t] X^exps[t]) * d_in for polynomials [P][L][N]."""
+    P = _polys(ctx, d_in, ctx.L)
+    _need(d_out, d_in.numel(), "d_out")
+    e = np.ascontiguousarray(exps, dtype=np.uint32)
+    c = np.ascontiguousarray(coefs, dtype=np.uint32)
+    if e.shape != c.shape:
+        raise ValueError("exps and coefs differ in length")
+    _check(lib().hyena_pmult_sparse(ctx.handle, _dev_ptr(d_in, "int32"), P, e.shape[0], _np_ptr(e, np.uint32),
+                                    _np_ptr(c, np.uint32), _dev_ptr(d_out, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -136,11 +136,13 @@ extern "C" int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint
     if (primes) {
         for (uint32_t i = 0; i < L; i++) {
             uint32_t q = primes[i];
-            if (q <= (1u << 29) || q >= (1u << 31) || q % (2 * N) != 1 || !is_prime_u32(q)) {
+            const uint32_t lo = (flags & HYENA_PLAINTEXT_PRIME) ? 2u : (1u << 29);
+            if (q <= lo || q >= (1u << 31) || q % (2 * N) != 1 || !is_prime_u32(q)) {
                 delete c;
                 return set_error(HYENA_EUNSUPPORTED,
                                  "hyena_create: prime " + std::to_string(q) +
-                                     " is not a prime in (2^29, 2^31) with q = 1 mod 2N");
+                                     " is not a prime in (" + (lo == 2 ? "2" : "2^29") +
+                                     ", 2^31) with q = 1 mod 2N");
             }
             for (uint32_t j = 0; j < i; j++)
                 if (primes[j] == q) {
@@ -149,6 +151,9 @@ extern "C" int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint
                 }
             c->q.push_back(q);
         }
+    } else if (flags & HYENA_PLAINTEXT_PRIME) {
+        delete c;
+        return set_error(HYENA_EINVAL, "hyena_create: HYENA_PLAINTEXT_PRIME needs the prime");
     } else {
         const uint32_t bits = (flags & HYENA_PRIMES_30BIT) ? 30 : 31;
         uint64_t q = ((1ull << bits) - 1) / (2 * N) * (2 * N) + 1;
@@ -161,7 +166,7 @@ extern "C" int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint
             }
         }
     }
-    if (!(flags & HYENA_ALLOW_INSECURE)) {
+    if (!(flags & (HYENA_ALLOW_INSECURE | HYENA_PLAINTEXT_PRIME))) {
         double logq = 0;
         for (uint32_t q : c->q) logq += std::log2((double)q);
         uint32_t ceil = security_ceiling(N);

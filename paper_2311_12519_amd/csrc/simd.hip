@@ -1,0 +1,242 @@
+// The SIMD (batch-encoded) pieces of the paper's own setting on gfx950: the
+// parameter selection of the "Optimal Parameter Selection" section (h_{p,n}
+// and the k minimising k h_{p,n} mod p), batch encoding with a prime
+// plaintext modulus p = 1 mod 2n, the Galois automorphisms behind HRot, and
+// PMult by a sparse plaintext such as the [k, -k] one (two monomials).
+//
+// Slot layout: slot s < n/2 holds the value at zeta^(3^s mod 2n), slot n/2 + s
+// the value at zeta^(-3^s mod 2n), zeta the least primitive 2n-th root of
+// unity mod p (the context's psi). X -> X^3 rotates both rows by one slot,
+// X -> X^(2n-1) swaps them.
+#include "internal.h"
+
+namespace {
+
+constexpr uint32_t STH = 256;                 // threads per block, one coefficient each
+constexpr uint32_t MAX_TERMS = 16;            // monomials of a sparse plaintext
+
+__device__ __forceinline__ uint32_t scsub(uint32_t x, uint32_t q) { return min(x, x - q); }
+
+// a b 2^-32 mod q in [0, q) for a, b < q
+__device__ __forceinline__ uint32_t smont(uint32_t a, uint32_t b, uint32_t q, uint32_t qn) {
+    const uint64_t t = (uint64_t)a * b;
+    const uint32_t m = (uint32_t)t * qn;
+    return scsub((uint32_t)(((uint64_t)m * q + t) >> 32), q);
+}
+
+__device__ __forceinline__ uint32_t brev(uint32_t x, uint32_t logn) { return __brev(x) >> (32 - logn); }
+
+// NTT index (evaluation at psi^(2 brv(k) + 1)) of slot s
+__device__ __forceinline__ uint32_t slot_to_ntt(uint32_t s, uint32_t logN) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1, h = N / 2;
+    const uint32_t r = s < h ? s : s - h;
+    uint32_t e = 1, b = 3;                     // 3^r mod 2N by squaring
+    for (uint32_t x = r; x; x >>= 1) {
+        if (x & 1) e = (e * b) & mask;
+        b = (b * b) & mask;
+    }
+    if (s >= h) e = (2 * N - e) & mask;
+    return brev((e - 1) >> 1, logN);
+}
+
+// Blocks walk chunks of 256 coefficients of a [P][N] (or [P][L][N]) array.
+__global__ void __launch_bounds__(STH) slots_to_ntt_kernel(const uint32_t *slots, uint32_t *ntt, size_t P,
+                                                           uint32_t logN, uint32_t p) {
+    const size_t chunks = P << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t poly = c >> (logN - 8);
+        const uint32_t s = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t v = slots[(poly << logN) + s];
+        ntt[(poly << logN) + slot_to_ntt(s, logN)] = v < p ? v : v % p;
+    }
+}
+
+__global__ void __launch_bounds__(STH) ntt_to_slots_kernel(const uint32_t *ntt, uint32_t *slots, size_t P,
+                                                           uint32_t logN) {
+    const size_t chunks = P << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t poly = c >> (logN - 8);
+        const uint32_t s = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        slots[(poly << logN) + s] = ntt[(poly << logN) + slot_to_ntt(s, logN)];
+    }
+}
+
+// out = in(X^g) per limb-polynomial, gathered: output coefficient i comes from
+// j = i g^-1 mod 2N (sign + if j < N, else from j - N with sign -)
+__global__ void __launch_bounds__(STH) automorphism_kernel(const uint32_t *in, uint32_t *out, size_t polys,
+                                                           uint32_t logN, uint32_t L, uint32_t ginv, LimbTable lt) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1;
+    const size_t chunks = polys << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t poly = c >> (logN - 8);   // limb-polynomial index, limb = poly mod L
+        const uint32_t q = lt.c[(uint32_t)(poly % L)].q;
+        const uint32_t i = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t j = (i * ginv) & mask;
+        const size_t base = poly << logN;
+        uint32_t v;
+        if (j < N) {
+            v = in[base + j];
+        } else {
+            const uint32_t a = in[base + j - N];
+            v = a ? q - a : 0;
+        }
+        out[base + i] = v;
+    }
+}
+
+struct Sparse {
+    uint32_t n;                       // monomials
+    uint32_t e[MAX_TERMS];            // exponents, < 2N
+    uint32_t cm[HYENA_MAX_LIMBS][MAX_TERMS];   // c_t 2^32 mod q_i (Montgomery form)
+};
+
+// out = sum_t c_t X^{e_t} in, per limb-polynomial: coefficient i takes
+// +c_t in[d] for d = i - e_t mod 2N below N, -c_t in[d - N] otherwise
+__global__ void __launch_bounds__(STH) pmult_sparse_kernel(const uint32_t *in, uint32_t *out, size_t polys,
+                                                           uint32_t logN, uint32_t L, LimbTable lt, Sparse sp) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1;
+    const size_t chunks = polys << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t poly = c >> (logN - 8);
+        const uint32_t limb = (uint32_t)(poly % L);
+        const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg;
+        const uint32_t i = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const size_t base = poly << logN;
+        uint32_t acc = 0;
+        for (uint32_t t = 0; t < sp.n; t++) {
+            const uint32_t d = (i - sp.e[t]) & mask;
+            uint32_t a = in[base + (d & (N - 1))];
+            if (d >= N) a = a ? q - a : 0;
+            acc = scsub(acc + smont(a, sp.cm[limb][t], q, qn), q);
+        }
+        out[base + i] = acc;
+    }
+}
+
+unsigned sgrid(size_t chunks) { return (unsigned)std::min<size_t>(chunks, 8192); }
+
+bool soverlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return na && nb && a0 < b0 + nb && b0 < a0 + na;
+}
+
+int slaunched(const char *who) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string(who) + ": " + hipGetErrorString(e));
+    return HYENA_OK;
+}
+
+int device_ctx(const hyena_ctx *c, const char *who) {
+    if (!c->d_fw) return set_error(HYENA_EINVAL, std::string(who) + ": context was created host-only");
+    return HYENA_OK;
+}
+
+bool is_prime_small(uint32_t x) {
+    if (x < 2) return false;
+    for (uint64_t f = 2; f * f <= x; f++)
+        if (x % f == 0) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" int hyena_simd_params(uint32_t n, uint32_t p, uint32_t kmax, uint32_t *h_out, uint32_t *k_out,
+                                 uint32_t *kh_out) {
+    if (n < 8 || (n & (n - 1)) || n > (1u << 20)) return set_error(HYENA_EINVAL, "hyena_simd_params: n must be a power of two >= 8");
+    if (p >= (1u << 31) || (p - 1) % (2 * n) != 0 || !is_prime_small(p))
+        return set_error(HYENA_EINVAL, "hyena_simd_params: p must be a prime below 2^31 with p = 1 mod 2n");
+    if (kmax < 1) return set_error(HYENA_EINVAL, "hyena_simd_params: kmax must be at least 1");
+    // zeta: the least primitive 2n-th root of unity; w = zeta^(n/4) has order 8 and
+    // the [1, -1] plaintext is h (X^(n/4) + X^(3n/4)) with h (w + w^3) = 1
+    uint32_t z = 2;
+    while (h_powmod(z, n, p) != p - 1) z++;
+    const uint32_t w = h_powmod(z, n / 4, p);
+    const uint32_t s = (uint32_t)(((uint64_t)w + h_powmod(w, 3, p)) % p);
+    const uint32_t h = h_powmod(s, p - 2, p);
+    uint32_t bk = 1, bkh = h;
+    for (uint32_t k = 2; k <= kmax; k++) {
+        const uint32_t v = (uint32_t)((uint64_t)k * h % p);
+        if (v < bkh) bk = k, bkh = v;
+    }
+    if (h_out) *h_out = h;
+    if (k_out) *k_out = bk;
+    if (kh_out) *kh_out = bkh;
+    return HYENA_OK;
+}
+
+extern "C" int hyena_simd_encode(const hyena_ctx *c, const uint32_t *d_slots, size_t P, uint32_t *d_coef,
+                                 hyena_stream_t stream) {
+    static const char *who = "hyena_simd_encode";
+    if (!c || (P && (!d_slots || !d_coef))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (c->L != 1) return set_error(HYENA_EINVAL, std::string(who) + ": the context must hold the plaintext prime alone");
+    if (P == 0) return HYENA_OK;
+    if (P > 0x7fffffffull) return set_error(HYENA_EINVAL, std::string(who) + ": too many polynomials");
+    const size_t bytes = P * c->N * 4;
+    if (soverlap(d_slots, bytes, d_coef, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_coef overlaps d_slots");
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(slots_to_ntt_kernel, dim3(sgrid(P << (c->logN - 8))), dim3(STH), 0, s, d_slots, d_coef, P,
+                       c->logN, c->q[0]);
+    if (int rc = slaunched(who)) return rc;
+    return launch_ntt(c, d_coef, P, true, s);
+}
+
+extern "C" int hyena_simd_decode(const hyena_ctx *c, uint32_t *d_coef, size_t P, uint32_t *d_slots,
+                                 hyena_stream_t stream) {
+    static const char *who = "hyena_simd_decode";
+    if (!c || (P && (!d_slots || !d_coef))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (c->L != 1) return set_error(HYENA_EINVAL, std::string(who) + ": the context must hold the plaintext prime alone");
+    if (P == 0) return HYENA_OK;
+    if (P > 0x7fffffffull) return set_error(HYENA_EINVAL, std::string(who) + ": too many polynomials");
+    const size_t bytes = P * c->N * 4;
+    if (soverlap(d_slots, bytes, d_coef, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_slots overlaps d_coef");
+    const hipStream_t s = (hipStream_t)stream;
+    if (int rc = launch_ntt(c, d_coef, P, false, s)) return rc;
+    hipLaunchKernelGGL(ntt_to_slots_kernel, dim3(sgrid(P << (c->logN - 8))), dim3(STH), 0, s, d_coef, d_slots, P,
+                       c->logN);
+    return slaunched(who);
+}
+
+extern "C" int hyena_automorphism(const hyena_ctx *c, const uint32_t *d_in, size_t P, uint32_t g, uint32_t *d_out,
+                                  hyena_stream_t stream) {
+    static const char *who = "hyena_automorphism";
+    if (!c || (P && (!d_in || !d_out))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (!(g & 1)) return set_error(HYENA_EINVAL, std::string(who) + ": g must be odd");
+    if (P == 0) return HYENA_OK;
+    const size_t polys = P * c->L;
+    const size_t bytes = polys * c->N * 4;
+    if (soverlap(d_in, bytes, d_out, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps d_in");
+    // g^-1 mod 2N (g odd): Newton's iteration x <- x (2 - g x) doubles the correct low bits
+    const uint32_t mask = 2 * c->N - 1;
+    uint32_t x = g;   // correct to 3 bits (g g = 1 mod 8)
+    for (int it = 0; it < 5; it++) x *= 2u - g * x;
+    const uint32_t ginv = x & mask;
+    hipLaunchKernelGGL(automorphism_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, (hipStream_t)stream,
+                       d_in, d_out, polys, c->logN, c->L, ginv, c->lt);
+    return slaunched(who);
+}
+
+extern "C" int hyena_pmult_sparse(const hyena_ctx *c, const uint32_t *d_in, size_t P, uint32_t n_terms,
+                                  const uint32_t *exps, const uint32_t *coefs, uint32_t *d_out, hyena_stream_t stream) {
+    static const char *who = "hyena_pmult_sparse";
+    if (!c || (P && (!d_in || !d_out)) || (n_terms && (!exps || !coefs)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (n_terms > MAX_TERMS) return set_error(HYENA_EINVAL, std::string(who) + ": more than 16 monomials");
+    if (P == 0) return HYENA_OK;
+    const size_t polys = P * c->L;
+    const size_t bytes = polys * c->N * 4;
+    if (soverlap(d_in, bytes, d_out, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps d_in");
+    Sparse sp{};
+    sp.n = n_terms;
+    for (uint32_t t = 0; t < n_terms; t++) {
+        if (exps[t] >= 2 * c->N) return set_error(HYENA_EINVAL, std::string(who) + ": exponent not below 2N");
+        sp.e[t] = exps[t];
+        for (uint32_t i = 0; i < c->L; i++) sp.cm[i][t] = to_montgomery(coefs[t] % c->q[i], c->q[i]);
+    }
+    hipLaunchKernelGGL(pmult_sparse_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, (hipStream_t)stream,
+                       d_in, d_out, polys, c->logN, c->L, c->lt, sp);
+    return slaunched(who);
+}

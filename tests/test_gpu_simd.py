@@ -1,0 +1,168 @@
+"""GPU parity of the SIMD-setting kernels (batch encoding, Galois
+automorphisms, PMult by a sparse plaintext) against oracle/simd.py, bit for
+bit, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import paper_2311_12519_amd as hy
+from oracle import simd
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def from_dev(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint32)
+
+
+_CTX = {}
+
+
+def ptx(n, p):
+    key = ("p", n, p)
+    if key not in _CTX:
+        _CTX[key] = hy.hyena_create(n, 1, primes=[p], flags=hy.HYENA_PLAINTEXT_PRIME)
+    return _CTX[key]
+
+
+def ctx_for(N, L, bits):
+    key = (N, L, bits)
+    if key not in _CTX:
+        flags = (hy.HYENA_PRIMES_30BIT if bits == 30 else 0) | hy.HYENA_ALLOW_INSECURE
+        _CTX[key] = hy.hyena_create(N, L, flags=flags)
+    return _CTX[key]
+
+
+# (n, p): the paper's Gazelle parameters, the NewHope prime, a Fermat prime at n = 8192
+SIMD_CASES = [(2048, 307201), (1024, 12289), (8192, 65537)]
+
+
+@pytest.mark.parametrize("n,p", SIMD_CASES)
+def test_simd_encode_decode_match_oracle(dev, n, p):
+    say(f"simd encode/decode n={n} p={p}")
+    ctx = ptx(n, p)
+    rng = np.random.default_rng(n)
+    P = 3
+    v = rng.integers(0, p, size=(P, n)).astype(np.uint32)
+    v[0, :3] = [0, p - 1, 1]
+    d_v = to_dev(v)
+    d_m = to_dev(np.zeros((P, n), dtype=np.uint32))
+    hy.hyena_simd_encode(ctx, d_v, d_m)
+    m = from_dev(d_m).reshape(P, n)
+    for r in range(P):
+        assert np.array_equal(m[r], simd.encode(v[r], p, n)), r
+    d_s = to_dev(np.zeros((P, n), dtype=np.uint32))
+    hy.hyena_simd_decode(ctx, d_m, d_s)
+    assert np.array_equal(from_dev(d_s).reshape(P, n), v)
+
+
+def test_simd_pm_plaintext_and_pmult_semantics_on_gpu(dev):
+    """All on the GPU over Z_p: encoding [k, -k] gives kh (X^{n/4} + X^{3n/4})
+    with the library's (h, k); PMult of encode(v) by that sparse plaintext
+    decodes to (k v | -k v) slot-wise; a rotation by X^3 rotates both rows."""
+    n, p = 2048, 307201
+    say("simd [k,-k] plaintext semantics")
+    ctx = ptx(n, p)
+    h, k, kh = hy.hyena_simd_params(n, p, 61)
+    pattern = np.array([k] * (n // 2) + [p - k] * (n // 2), dtype=np.uint32)
+    d_pat, d_w = to_dev(pattern), to_dev(np.zeros(n, dtype=np.uint32))
+    hy.hyena_simd_encode(ctx, d_pat, d_w)
+    w = from_dev(d_w)
+    want = np.zeros(n, dtype=np.uint32)
+    want[[n // 4, 3 * n // 4]] = kh
+    assert np.array_equal(w, want)
+    rng = np.random.default_rng(4)
+    v = rng.integers(0, p, n).astype(np.uint32)
+    d_v, d_m, d_o = to_dev(v), to_dev(np.zeros(n, np.uint32)), to_dev(np.zeros(n, np.uint32))
+    hy.hyena_simd_encode(ctx, d_v, d_m)
+    hy.hyena_pmult_sparse(ctx, d_m, [n // 4, 3 * n // 4], [kh, kh], d_o)
+    d_s = to_dev(np.zeros(n, np.uint32))
+    hy.hyena_simd_decode(ctx, d_o, d_s)
+    got = from_dev(d_s).astype(np.int64)
+    half = n // 2
+    assert np.array_equal(got[:half], v[:half].astype(np.int64) * k % p)
+    assert np.array_equal(got[half:], (-v[half:].astype(np.int64) * k) % p)
+    hy.hyena_simd_encode(ctx, d_v, d_m)
+    hy.hyena_automorphism(ctx, d_m, 3, d_o)
+    hy.hyena_simd_decode(ctx, d_o, d_s)
+    got = from_dev(d_s)
+    assert np.array_equal(got[:half], np.roll(v[:half], -1)) and np.array_equal(got[half:], np.roll(v[half:], -1))
+
+
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 30), (8192, 3, 31), (1024, 1, 31)])
+def test_automorphism_matches_oracle(dev, N, L, bits):
+    say(f"automorphism N={N} L={L}")
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N + L)
+    P = 2
+    a = np.empty((P, L, N), dtype=np.uint32)
+    for i, q in enumerate(ctx.primes):
+        a[:, i, :] = rng.integers(0, q, size=(P, N))
+        a[0, i, :3] = [0, q - 1, 1]
+    d_a, d_o = to_dev(a), to_dev(np.zeros_like(a))
+    for g in (3, 5, 2 * N - 1, pow(3, 123, 2 * N), 2 * N + 3):
+        hy.hyena_automorphism(ctx, d_a, g, d_o)
+        got = from_dev(d_o).reshape(P, L, N)
+        for r in range(P):
+            for i, q in enumerate(ctx.primes):
+                assert np.array_equal(got[r, i], simd.automorphism(a[r, i], g % (2 * N), q)), (g, r, i)
+
+
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 30), (8192, 3, 31)])
+def test_pmult_sparse_matches_oracle(dev, N, L, bits):
+    """The [k, -k] plaintext of the paper's parameters (two monomials), and a
+    plaintext of 16 monomials with exponents up to 2N - 1 (signs)."""
+    say(f"pmult_sparse N={N} L={L}")
+    ctx = ctx_for(N, L, bits)
+    rng = np.random.default_rng(N * L)
+    P = 2
+    a = np.empty((P, L, N), dtype=np.uint32)
+    for i, q in enumerate(ctx.primes):
+        a[:, i, :] = rng.integers(0, q, size=(P, N))
+    d_a, d_o = to_dev(a), to_dev(np.zeros_like(a))
+    _, _, kh = hy.hyena_simd_params(2048, 307201, 61)
+    cases = [([N // 4, 3 * N // 4], [kh, kh]),
+             (sorted(rng.choice(2 * N, 16, replace=False).tolist()), rng.integers(0, 307201, 16).tolist())]
+    for exps, coefs in cases:
+        hy.hyena_pmult_sparse(ctx, d_a, exps, coefs, d_o)
+        got = from_dev(d_o).reshape(P, L, N)
+        for i, q in enumerate(ctx.primes):
+            w = np.zeros(N, dtype=np.int64)
+            for e, c in zip(exps, coefs):                 # X^e = -X^{e-N} for e >= N
+                if e < N:
+                    w[e] = (w[e] + c) % q
+                else:
+                    w[e - N] = (w[e - N] - c) % q
+            for r in range(P):
+                assert np.array_equal(got[r, i], simd.pmult(a[r, i], w, q)), (len(exps), r, i)
+
+
+def test_simd_calls_reject_bad_arguments(dev):
+    import torch
+    ctx = ptx(2048, 307201)
+    cctx = ctx_for(2048, 2, 30)
+    buf = torch.zeros(4 * 2048 * 2, dtype=torch.int32, device="cuda")
+    with pytest.raises(hy.HyenaError):                    # encode needs a single-prime context
+        hy.hyena_simd_encode(cctx, buf[:2 * 2048], buf[4 * 2048:6 * 2048])
+    with pytest.raises(hy.HyenaError):                    # overlapping arrays
+        hy.hyena_simd_encode(ctx, buf[:2048], buf[1024:3072])
+    with pytest.raises(hy.HyenaError):                    # even g
+        hy.hyena_automorphism(cctx, buf[:2 * 2048], 4, buf[4 * 2048:6 * 2048])
+    with pytest.raises(hy.HyenaError):                    # exponent not below 2N
+        hy.hyena_pmult_sparse(cctx, buf[:2 * 2048], [4096], [1], buf[4 * 2048:6 * 2048])
+    with pytest.raises(hy.HyenaError):                    # more than 16 monomials
+        hy.hyena_pmult_sparse(cctx, buf[:2 * 2048], list(range(17)), [1] * 17, buf[4 * 2048:6 * 2048])

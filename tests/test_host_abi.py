@@ -167,3 +167,41 @@ def test_client_device_calls_refused_on_host_only_context():
     assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, null, fake, null) == hy.HYENA_EINVAL
     assert L.hyena_decrypt_device(ctx.handle, fake, fake, 1, fake, fake, null) == hy.HYENA_EINVAL
     assert "host-only" in L.hyena_last_error().decode()
+
+
+def test_simd_params_match_the_papers_example_and_the_oracle():
+    """hyena_simd_params (closed form h = (w + w^3)^-1, w = zeta^(n/4)) against
+    the paper's worked example and the oracle's brute-force encoding."""
+    import os
+    from oracle import simd
+    g = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "simd_parameter_example.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            g[k] = v
+    h, k, kh = hy.hyena_simd_params(int(g["n"]), int(g["p"]), 61)
+    assert (h, k) == (int(g["h"]), int(g["k"])) and kh == k * h % int(g["p"])
+    for n, p in [(1024, 12289), (4096, 65537), (1024, 307201)]:
+        h, k, kh = hy.hyena_simd_params(n, p, 200)
+        assert h == simd.h_pn(n, p)
+        assert (k, kh) == simd.best_k(h, p, 200)
+    for bad in [(2048, 307203, 61), (4096, 12289, 61), (6, 13, 5), (2048, 307201, 0)]:
+        with pytest.raises(hy.HyenaError):
+            hy.hyena_simd_params(*bad)
+
+
+def test_plaintext_prime_context_and_simd_calls_on_host_only_context():
+    ctx = hy.hyena_create(2048, 1, primes=[307201], flags=HOST | hy.HYENA_PLAINTEXT_PRIME)
+    assert ctx.primes == [307201] and ctx.psi == [41]     # the least primitive 4096-th root
+    with pytest.raises(hy.HyenaError):                    # without the flag the prime is refused
+        hy.hyena_create(2048, 1, primes=[307201], flags=HOST)
+    with pytest.raises(hy.HyenaError):                    # the flag needs the prime
+        hy.hyena_create(2048, 1, flags=HOST | hy.HYENA_PLAINTEXT_PRIME)
+    L = hy.lib()
+    fake = ctypes.c_void_p(0x10000)
+    null = ctypes.c_void_p(0)
+    assert L.hyena_simd_encode(ctx.handle, fake, 1, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_simd_decode(ctx.handle, fake, 1, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_automorphism(ctx.handle, fake, 1, 3, fake, null) == hy.HYENA_EINVAL
+    e = (ctypes.c_uint32 * 1)(512)
+    assert L.hyena_pmult_sparse(ctx.handle, fake, 1, 1, e, e, fake, null) == hy.HYENA_EINVAL
