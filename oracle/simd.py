@@ -162,3 +162,70 @@ def pmult(a, plain, q: int) -> np.ndarray:
     integers in [0, p) they are stored as."""
     return negacyclic_mul(np.asarray(a, dtype=np.uint32), np.mod(np.asarray(plain, dtype=np.int64), q).astype(np.uint32),
                           q)
+
+
+# ---------------------------------------------------------------------------
+# HRot: Galois automorphism + key switching with a decomposition base
+# ("Homomorphic Operations in BFV": HRot and its decomposition base, which
+# trades noise against computation; hoisting: decompose once, rotate many)
+# ---------------------------------------------------------------------------
+
+def n_digits(log2_base: int, bits: int = 31) -> int:
+    """Digits per residue for base 2^log2_base (residues below 2^bits)."""
+    return -(-bits // log2_base)
+
+
+def galois_keygen(primes, s, g: int, log2_base: int, seed: int) -> np.ndarray:
+    """Key-switching key for s(X^g) -> s: uint32 [L*D][2][L][N], coefficient
+    domain. Key (i, j) (index i*D + j) is an encryption under s, drawn like the
+    encryption of message number i*D + j, of s(X^g) 2^{j log2_base} on limb i
+    and 0 on the other limbs (the CRT basis element of limb i is 1 mod q_i and
+    0 mod the others): b1 = -a, b0 = a s + e + gadget."""
+    from . import _lift, _uniform_mod, sample_error, sm64
+    s = np.asarray(s, dtype=np.int64)
+    N, L = s.shape[0], len(primes)
+    D = n_digits(log2_base)
+    jn = np.arange(N, dtype=np.uint64)
+    out = np.empty((L * D, 2, L, N), dtype=np.uint32)
+    for key in range(L * D):
+        i, j = divmod(key, D)
+        e = sample_error(seed, np.uint64(2) * (np.uint64(key * N) + jn) + np.uint64(1))
+        for k, qk in enumerate(primes):
+            a = _uniform_mod(sm64(seed, np.uint64(2) * (np.uint64((key * L + k) * N) + jn)), qk).astype(np.uint32)
+            as_ = negacyclic_mul(a, _lift(s, qk), qk).astype(np.uint64)
+            v = as_ + _lift(e, qk).astype(np.uint64)
+            if k == i:
+                sg = automorphism(_lift(s, qk), g, qk).astype(np.uint64)
+                v = v + sg * np.uint64(pow(2, log2_base * j, qk))
+            out[key, 0, k] = (v % np.uint64(qk)).astype(np.uint32)
+            out[key, 1, k] = ((np.uint64(qk) - a.astype(np.uint64)) % np.uint64(qk)).astype(np.uint32)
+    return out
+
+
+def hrot(primes, ct, g: int, keys, log2_base: int) -> np.ndarray:
+    """Hoisted HRot of one ciphertext [2][L][N] (coefficient domain):
+    c0' = c0(X^g) + sum_{i,j} d_ij(X^g) b0_ij,  c1' = sum_{i,j} d_ij(X^g) b1_ij,
+    d_ij the base-2^log2_base digits of limb i's residues of c1 (decomposed
+    before the automorphism, so that one decomposition serves every g)."""
+    ct = np.asarray(ct, dtype=np.uint32)
+    L, N = ct.shape[1], ct.shape[2]
+    D = n_digits(log2_base)
+    mask = (1 << log2_base) - 1
+    out = np.empty_like(ct)
+    for k, qk in enumerate(primes):
+        acc0 = automorphism(ct[0, k], g, qk).astype(np.int64)
+        acc1 = np.zeros(N, dtype=np.int64)
+        for i in range(L):
+            for j in range(D):
+                d = (ct[1, i].astype(np.int64) >> (log2_base * j)) & mask
+                dg = automorphism(d % qk, g, qk)
+                acc0 = (acc0 + negacyclic_mul(dg, keys[i * D + j, 0, k], qk)) % qk
+                acc1 = (acc1 + negacyclic_mul(dg, keys[i * D + j, 1, k], qk)) % qk
+        out[0, k], out[1, k] = acc0, acc1
+    return out
+
+
+def hrot_noise_bound(N: int, L: int, log2_base: int, B: int) -> int:
+    """Added noise of one key switching: sum over the L*D keys of
+    d_ij(X^g) e_ij, each coefficient at most N (2^b - 1) B."""
+    return L * n_digits(log2_base) * N * ((1 << log2_base) - 1) * B

@@ -141,3 +141,49 @@ def test_pmult_by_the_pm_plaintext_is_two_shifts():
             t = j + e
             sh[t % n] += int(a[j]) if t < n else -int(a[j])
     assert np.array_equal(got.astype(object), np.array([(h3 * x) % q for x in sh], dtype=object))
+
+
+@pytest.mark.parametrize("log2_base", [8, 16, 29])
+def test_hrot_decrypts_to_the_automorphism_of_the_message(log2_base):
+    """HRot(Enc(m), g) decrypts to m(X^g) (coefficients mod t); its noise stays
+    within fresh noise plus the key-switching bound; g = 1 is the identity on
+    messages; two rotations by 3 equal one by 9."""
+    N, L = 1024, 2
+    primes = orc.ntt_primes(N, L, 30)
+    s = orc.keygen(N, 21)
+    rng = np.random.default_rng(log2_base)
+    t = 1 << 20
+    m = rng.integers(-t // 2 + 1, t // 2 + 1, size=(1, N))
+    ct = orc.encrypt(primes, 20, s, m, 99)[0]
+    bound = orc.B_ERR + simd.hrot_noise_bound(N, L, log2_base, orc.B_ERR)
+    for g in (3, 2 * N - 1, 1):
+        keys = simd.galois_keygen(primes, s, g, log2_base, 1000 + g)
+        r = simd.hrot(primes, ct, g, keys, log2_base)
+        want = np.array([((x + t // 2 - 1) % t) - t // 2 + 1 for x in simd.automorphism(m[0] % t, g, t).astype(np.int64)])
+        assert np.array_equal(orc.decrypt(primes, 20, s, r[None])[0], want), g
+        assert orc.noise_inf(primes, 20, s, r, want) <= bound
+    k3 = simd.galois_keygen(primes, s, 3, log2_base, 7)
+    k9 = simd.galois_keygen(primes, s, 9, log2_base, 8)
+    twice = simd.hrot(primes, simd.hrot(primes, ct, 3, k3, log2_base), 3, k3, log2_base)
+    once = simd.hrot(primes, ct, 9, k9, log2_base)
+    dec = orc.decrypt(primes, 20, s, np.stack([twice, once]))
+    assert np.array_equal(dec[0], dec[1])
+
+
+def test_galois_key_is_an_encryption_of_the_gadget():
+    """b0 + b1 s - gadget is the error: small, and the same integer on every limb."""
+    N, L, b = 1024, 2, 16
+    primes = orc.ntt_primes(N, L, 30)
+    s = orc.keygen(N, 5)
+    keys = simd.galois_keygen(primes, s, 5, b, 3)
+    for key in range(L * simd.n_digits(b)):
+        i, j = divmod(key, simd.n_digits(b))
+        errs = []
+        for k, q in enumerate(primes):
+            v = (keys[key, 0, k].astype(np.int64) + orc.negacyclic_mul(keys[key, 1, k], np.mod(s.astype(np.int64), q).astype(np.uint32), q)) % q
+            if k == i:
+                v = (v - simd.automorphism(np.mod(s.astype(np.int64), q), 5, q).astype(np.int64) * pow(2, b * j, q)) % q
+            v = np.where(v > q // 2, v - q, v)
+            assert np.abs(v).max() <= orc.B_ERR
+            errs.append(v)
+        assert np.array_equal(errs[0], errs[1])
