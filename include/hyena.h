@@ -380,6 +380,39 @@ int hyena_pmult_sparse(const hyena_ctx *ctx, const uint32_t *d_in, size_t P, uin
                        hyena_stream_t stream);
 
 /*
+ * HRot (Galois automorphism + key switching, "Homomorphic Operations in BFV",
+ * with the decomposition base that trades noise against computation and
+ * hoisting: decompose once, rotate many times). Digits are base 2^log2_base
+ * (1 <= log2_base <= 29) of each limb's residues, D = ceil(31 / log2_base)
+ * per limb (RNS-BV: the CRT basis element of limb i is 1 mod q_i, 0 mod the
+ * others).
+ *
+ * hyena_galois_keygen (host, test setup like hyena_encrypt): key-switching key
+ * for s(X^g) -> s, ksk host uint32 [L*D][2][L][N], coefficient domain: key
+ * (i, j) = (a s + e + [k == i] s(X^g) 2^(j log2_base), -a) on limb k, a and e
+ * drawn as for the encryption of message number i*D + j with `seed`.
+ *
+ * hyena_ksk_prepare: in place on device keys [n_polys][L][N] (n_polys = 2*L*D
+ * per key), 16-byte aligned: 2^32 NTT(key) mod q_i, the form
+ * hyena_hrot_hoisted takes.
+ *
+ * hyena_hrot_hoisted: n_ct ciphertexts d_ct [n_ct][2][L][N] (coefficient
+ * domain) rotated by the n_rot <= 64 odd exponents gs (host array):
+ *   d_out[m][r] = (c0(X^g) + sum_ij d_ij(X^g) b0_ij, sum_ij d_ij(X^g) b1_ij),
+ * d_ij the digits of c1 (one decomposition and one forward NTT per ciphertext
+ * serve every rotation). d_ksk: device, prepared keys [n_rot][L*D][2][L][N];
+ * d_work: device uint32 [n_ct][L*D + 1][L][N], 16-byte aligned, overwritten;
+ * d_out: device uint32 [n_ct][n_rot][2][L][N], 16-byte aligned. d_work and
+ * d_out must not overlap each other or the inputs. Errors: EINVAL, EHIP.
+ */
+int hyena_galois_keygen(const hyena_ctx *ctx, const int8_t *sk, uint32_t g, uint32_t log2_base,
+                        uint64_t seed, uint32_t *ksk);
+int hyena_ksk_prepare(const hyena_ctx *ctx, uint32_t *d_ksk, size_t n_polys, hyena_stream_t stream);
+int hyena_hrot_hoisted(const hyena_ctx *ctx, const uint32_t *d_ct, size_t n_ct, uint32_t n_rot,
+                       const uint32_t *gs, uint32_t log2_base, const uint32_t *d_ksk,
+                       uint32_t *d_work, uint32_t *d_out, hyena_stream_t stream);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -87,6 +87,9 @@ _SIGS = {
     "hyena_simd_decode": [_P, _P, _sz, _P, _P],
     "hyena_automorphism": [_P, _P, _sz, _u32, _P, _P],
     "hyena_pmult_sparse": [_P, _P, _sz, _u32, _P, _P, _P, _P],
+    "hyena_galois_keygen": [_P, _P, _u32, _u32, _u64, _P],
+    "hyena_ksk_prepare": [_P, _P, _sz, _P],
+    "hyena_hrot_hoisted": [_P, _P, _sz, _u32, _P, _u32, _P, _P, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -394,6 +397,42 @@ def hyena_pmult_sparse(ctx: Ctx, d_in, exps, coefs, d_out, stream=None) -> None:
         raise ValueError("exps and coefs differ in length")
     _check(lib().hyena_pmult_sparse(ctx.handle, _dev_ptr(d_in, "int32"), P, e.shape[0], _np_ptr(e, np.uint32),
                                     _np_ptr(c, np.uint32), _dev_ptr(d_out, "int32"), _stream(stream)))
+
+
+def n_digits(log2_base: int) -> int:
+    """Digits per residue in base 2^log2_base (residues below 2^31); bases
+    outside [1, 29] are refused by the library calls themselves."""
+    return -(-31 // max(1, log2_base))
+
+
+def hyena_galois_keygen(ctx: Ctx, sk: np.ndarray, g: int, log2_base: int, seed: int) -> np.ndarray:
+    """Host key-switching key for s(X^g) -> s: uint32 [L*D][2][L][N]."""
+    D = n_digits(log2_base)
+    ksk = np.zeros((ctx.L * D, 2, ctx.L, ctx.N), dtype=np.uint32)
+    _check(lib().hyena_galois_keygen(ctx.handle, _np_ptr(np.ascontiguousarray(sk, dtype=np.int8), np.int8), g,
+                                     log2_base, seed, _np_ptr(ksk, np.uint32)))
+    return ksk
+
+
+def hyena_ksk_prepare(ctx: Ctx, d_ksk, stream=None) -> None:
+    """In place: keys [..][L][N] -> 2^32 NTT(keys)."""
+    P = _polys(ctx, d_ksk, ctx.L)
+    _check(lib().hyena_ksk_prepare(ctx.handle, _dev_ptr(d_ksk, "int32"), P, _stream(stream)))
+
+
+def hyena_hrot_hoisted(ctx: Ctx, d_ct, gs, log2_base: int, d_ksk, d_work, d_out, stream=None) -> None:
+    """Rotate every ciphertext of d_ct [n][2][L][N] by every g in gs."""
+    D, LN = n_digits(log2_base), ctx.L * ctx.N
+    n = _polys(ctx, d_ct, 2 * ctx.L)
+    g = np.ascontiguousarray(gs, dtype=np.uint32)
+    R = g.shape[0]
+    _need(d_ksk, R * ctx.L * D * 2 * LN, "d_ksk")
+    _need(d_out, n * R * 2 * LN, "d_out")
+    if d_work.numel() < n * (ctx.L * D + 1) * LN:
+        raise ValueError(f"d_work has {d_work.numel()} elements, needs {n * (ctx.L * D + 1) * LN}")
+    _check(lib().hyena_hrot_hoisted(ctx.handle, _dev_ptr(d_ct, "int32"), n, R, _np_ptr(g, np.uint32), log2_base,
+                                    _dev_ptr(d_ksk, "int32"), _dev_ptr(d_work, "int32"), _dev_ptr(d_out, "int32"),
+                                    _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -223,3 +223,47 @@ extern "C" int hyena_decrypt(const hyena_ctx *c, const int8_t *sk, const uint32_
     });
     return HYENA_OK;
 }
+
+// Key-switching key for s(X^g) -> s with digits in base 2^log2_base (RNS-BV):
+// key (i, j) = (a s + e + [k == i] s(X^g) 2^(j log2_base), -a) on every limb k,
+// a and e drawn as for the encryption of message number i D + j.
+extern "C" int hyena_galois_keygen(const hyena_ctx *c, const int8_t *sk, uint32_t g, uint32_t log2_base,
+                                   uint64_t seed, uint32_t *ksk) {
+    if (!c || !sk || !ksk) return set_error(HYENA_EINVAL, "hyena_galois_keygen: NULL argument");
+    if (!(g & 1)) return set_error(HYENA_EINVAL, "hyena_galois_keygen: g must be odd");
+    if (log2_base < 1 || log2_base > 29) return set_error(HYENA_EINVAL, "hyena_galois_keygen: log2_base must be in [1, 29]");
+    const uint32_t N = c->N, L = c->L, D = (31 + log2_base - 1) / log2_base;
+    // s(X^g): coefficient j moves to j g mod 2N, negated past N
+    std::vector<int> sg(N, 0);
+    for (uint32_t j = 0; j < N; j++) {
+        const uint64_t e = (uint64_t)j * g % (2 * N);
+        if (e < N) sg[e] += sk[j];
+        else sg[e - N] -= sk[j];
+    }
+    const auto s_hat = secret_ntt(c, sk);
+    const Cdt &gs = cdt();
+    parallel_for((size_t)L * D, [&](size_t key) {
+        const uint32_t i = (uint32_t)(key / D), j = (uint32_t)(key % D);
+        std::vector<int> e(N);
+        for (uint32_t x = 0; x < N; x++) e[x] = gs.sample(sm64(seed, 2 * ((uint64_t)key * N + x) + 1));
+        std::vector<uint32_t> a(N), as(N);
+        for (uint32_t k = 0; k < L; k++) {
+            const uint32_t q = c->q[k];
+            for (uint32_t x = 0; x < N; x++) a[x] = uniform_mod(sm64(seed, 2 * (((uint64_t)key * L + k) * N + x)), q);
+            as = a;
+            host_ntt(c, k, as.data());
+            for (uint32_t x = 0; x < N; x++) as[x] = h_mulmod(as[x], s_hat[(size_t)k * N + x], q);
+            host_intt(c, k, as.data());
+            const uint32_t pw = (uint32_t)((((unsigned __int128)1) << (log2_base * j)) % q);
+            uint32_t *b0 = ksk + ((key * 2 + 0) * L + k) * (size_t)N;
+            uint32_t *b1 = ksk + ((key * 2 + 1) * L + k) * (size_t)N;
+            for (uint32_t x = 0; x < N; x++) {
+                uint64_t v = (uint64_t)as[x] + lift(e[x], q);
+                if (k == i) v += h_mulmod(lift(sg[x], q), pw, q);
+                b0[x] = (uint32_t)(v % q);
+                b1[x] = a[x] ? q - a[x] : 0;
+            }
+        }
+    });
+    return HYENA_OK;
+}

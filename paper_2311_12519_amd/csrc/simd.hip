@@ -113,6 +113,80 @@ __global__ void __launch_bounds__(STH) pmult_sparse_kernel(const uint32_t *in, u
     }
 }
 
+// x <- x 2^32 mod q (a Montgomery product by 2^64 mod q), [polys][L][N]
+__global__ void __launch_bounds__(STH) scale_montgomery_kernel(uint32_t *x, size_t polys, uint32_t logN, uint32_t L,
+                                                               LimbTable lt) {
+    const size_t chunks = polys << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const LimbConst &lc = lt.c[(uint32_t)((c >> (logN - 8)) % L)];
+        uint32_t *p = x + (c << 8) + threadIdx.x;
+        *p = smont(*p, lc.r64, lc.q, lc.qinv_neg);
+    }
+}
+
+constexpr uint32_t MAX_ROT = 64;
+
+struct RotArgs {
+    uint32_t n_rot, D, b;
+    uint32_t g[MAX_ROT];
+};
+
+// work[m][i D + j][k] <- digit j (base 2^b) of c1's residues on limb i, the
+// same integer on every limb k; work[m][L D][k] <- c0 on limb k
+__global__ void __launch_bounds__(STH) decompose_kernel(const uint32_t *ct, uint32_t *work, size_t n_ct,
+                                                        uint32_t logN, uint32_t L, RotArgs ra) {
+    const uint32_t N = 1u << logN, mask = (1u << ra.b) - 1, T = L * ra.D + 1;
+    const size_t LN = (size_t)L << logN, chunks = (n_ct * L) << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t mk = c >> (logN - 8);                   // m L + k
+        const size_t m = mk / L;
+        const uint32_t k = (uint32_t)(mk - m * L);
+        const uint32_t x = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t *c0 = ct + m * 2 * LN, *c1 = c0 + LN;
+        uint32_t *w = work + m * T * LN + (size_t)k * N + x;
+        for (uint32_t i = 0; i < L; i++) {
+            const uint32_t v = c1[(size_t)i * N + x];
+            for (uint32_t j = 0; j < ra.D; j++) w[(size_t)(i * ra.D + j) * LN] = (v >> (ra.b * j)) & mask;
+        }
+        w[(size_t)(T - 1) * LN] = c0[(size_t)k * N + x];
+    }
+}
+
+// NTT domain: out[m][r][0][k][s] = c0^[s_r] + sum_t d_t^[s_r] K_r,t,0[k][s],
+//             out[m][r][1][k][s] = sum_t d_t^[s_r] K_r,t,1[k][s],
+// s_r the NTT index of the exponent (2 brv(s) + 1) g_r mod 2N (the
+// automorphism X -> X^g_r permutes evaluation points); K in Montgomery form
+__global__ void __launch_bounds__(STH) keyswitch_kernel(const uint32_t *work, const uint32_t *ksk, uint32_t *out,
+                                                        size_t n_ct, uint32_t logN, uint32_t L, LimbTable lt,
+                                                        RotArgs ra) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1, TD = L * ra.D;
+    const size_t LN = (size_t)L << logN;
+    const size_t chunks = ((n_ct * ra.n_rot) * L) << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t mrk = c >> (logN - 8);                  // (m n_rot + r) L + k
+        const uint32_t k = (uint32_t)(mrk % L);
+        const size_t mr = mrk / L;
+        const uint32_t r = (uint32_t)(mr % ra.n_rot);
+        const size_t m = mr / ra.n_rot;
+        const uint32_t s = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t e = ((2 * brev(s, logN) + 1) * ra.g[r]) & mask;
+        const uint32_t sr = brev(e >> 1, logN);
+        const LimbConst &lc = lt.c[k];
+        const uint32_t q = lc.q, qn = lc.qinv_neg;
+        const uint32_t *wm = work + m * (TD + 1) * LN + (size_t)k * N;
+        const uint32_t *kr = ksk + (size_t)r * TD * 2 * LN + (size_t)k * N + s;
+        uint32_t acc0 = wm[(size_t)TD * LN + sr], acc1 = 0;
+        for (uint32_t t = 0; t < TD; t++) {
+            const uint32_t d = wm[(size_t)t * LN + sr];
+            acc0 = scsub(acc0 + smont(d, kr[(size_t)(2 * t) * LN], q, qn), q);
+            acc1 = scsub(acc1 + smont(d, kr[(size_t)(2 * t + 1) * LN], q, qn), q);
+        }
+        uint32_t *o = out + mr * 2 * LN + (size_t)k * N + s;
+        o[0] = acc0;
+        o[LN] = acc1;
+    }
+}
+
 unsigned sgrid(size_t chunks) { return (unsigned)std::min<size_t>(chunks, 8192); }
 
 bool soverlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -239,4 +313,55 @@ extern "C" int hyena_pmult_sparse(const hyena_ctx *c, const uint32_t *d_in, size
     hipLaunchKernelGGL(pmult_sparse_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, (hipStream_t)stream,
                        d_in, d_out, polys, c->logN, c->L, c->lt, sp);
     return slaunched(who);
+}
+
+extern "C" int hyena_ksk_prepare(const hyena_ctx *c, uint32_t *d_ksk, size_t n_polys, hyena_stream_t stream) {
+    static const char *who = "hyena_ksk_prepare";
+    if (!c || (n_polys && !d_ksk)) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (n_polys == 0) return HYENA_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    if (int rc = launch_ntt(c, d_ksk, n_polys, false, s)) return rc;
+    const size_t polys = n_polys * c->L;
+    hipLaunchKernelGGL(scale_montgomery_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, s, d_ksk, polys,
+                       c->logN, c->L, c->lt);
+    return slaunched(who);
+}
+
+extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint32_t n_rot,
+                                  const uint32_t *gs, uint32_t log2_base, const uint32_t *d_ksk, uint32_t *d_work,
+                                  uint32_t *d_out, hyena_stream_t stream) {
+    static const char *who = "hyena_hrot_hoisted";
+    if (!c || (n_ct && n_rot && (!d_ct || !gs || !d_ksk || !d_work || !d_out)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (n_rot > MAX_ROT) return set_error(HYENA_EINVAL, std::string(who) + ": more than 64 rotations");
+    if (log2_base < 1 || log2_base > 29) return set_error(HYENA_EINVAL, std::string(who) + ": log2_base must be in [1, 29]");
+    if (n_ct == 0 || n_rot == 0) return HYENA_OK;
+    RotArgs ra{};
+    ra.n_rot = n_rot;
+    ra.b = log2_base;
+    ra.D = (31 + log2_base - 1) / log2_base;
+    for (uint32_t r = 0; r < n_rot; r++) {
+        if (!(gs[r] & 1)) return set_error(HYENA_EINVAL, std::string(who) + ": every g must be odd");
+        ra.g[r] = gs[r] & (2 * c->N - 1);
+    }
+    const size_t LN = (size_t)c->L * c->N, T = (size_t)c->L * ra.D + 1;
+    if (n_ct * T > 0x7fffffffull / c->L || n_ct * n_rot * 2 > 0x7fffffffull / c->L)
+        return set_error(HYENA_EINVAL, std::string(who) + ": too many ciphertexts");
+    const size_t ct_b = n_ct * 2 * LN * 4, work_b = n_ct * T * LN * 4, out_b = n_ct * n_rot * 2 * LN * 4,
+                 ksk_b = (size_t)n_rot * (T - 1) * 2 * LN * 4;
+    if (soverlap(d_work, work_b, d_ct, ct_b) || soverlap(d_work, work_b, d_out, out_b) ||
+        soverlap(d_work, work_b, d_ksk, ksk_b) || soverlap(d_out, out_b, d_ct, ct_b) ||
+        soverlap(d_out, out_b, d_ksk, ksk_b))
+        return set_error(HYENA_EINVAL, std::string(who) + ": d_work or d_out overlaps another array");
+    const hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(decompose_kernel, dim3(sgrid((n_ct * c->L) << (c->logN - 8))), dim3(STH), 0, s, d_ct, d_work,
+                       n_ct, c->logN, c->L, ra);
+    if (int rc = slaunched(who)) return rc;
+    if (int rc = launch_ntt(c, d_work, n_ct * T, false, s)) return rc;
+    hipLaunchKernelGGL(keyswitch_kernel, dim3(sgrid(((n_ct * n_rot) * c->L) << (c->logN - 8))), dim3(STH), 0, s,
+                       d_work, d_ksk, d_out, n_ct, c->logN, c->L, c->lt, ra);
+    if (int rc = slaunched(who)) return rc;
+    return launch_ntt(c, d_out, n_ct * n_rot * 2, true, s);
 }

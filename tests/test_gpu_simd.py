@@ -166,3 +166,74 @@ def test_simd_calls_reject_bad_arguments(dev):
         hy.hyena_pmult_sparse(cctx, buf[:2 * 2048], [4096], [1], buf[4 * 2048:6 * 2048])
     with pytest.raises(hy.HyenaError):                    # more than 16 monomials
         hy.hyena_pmult_sparse(cctx, buf[:2 * 2048], list(range(17)), [1] * 17, buf[4 * 2048:6 * 2048])
+
+
+def _hrot_setup(N, L, b, gs, n_ct, seed):
+    import torch
+    ctx = ctx_for(N, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(N, seed)
+    rng = np.random.default_rng(seed)
+    t = 1 << 20
+    msg = rng.integers(-t // 2 + 1, t // 2 + 1, size=(n_ct, N))
+    ct = orc.encrypt(primes, 20, s, msg, seed + 1)
+    keys = np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 500 + g) for g in gs])
+    d_k = to_dev(keys)
+    hy.hyena_ksk_prepare(ctx, d_k)
+    D = hy.n_digits(b)
+    d_ct = to_dev(ct)
+    d_work = torch.empty(n_ct * (L * D + 1) * L * N, dtype=torch.int32, device="cuda")
+    d_out = torch.empty(n_ct * len(gs) * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_hrot_hoisted(ctx, d_ct, gs, b, d_k, d_work, d_out)
+    return ctx, s, msg, ct, keys, from_dev(d_out).reshape(n_ct, len(gs), 2, L, N)
+
+
+@pytest.mark.parametrize("b", [8, 16, 29])
+def test_hrot_hoisted_matches_oracle(dev, b):
+    """Every rotated ciphertext equals the oracle's hoisted HRot bit for bit and
+    decrypts to the automorphism of its message."""
+    N, L = 1024, 2
+    gs = [3, 2 * N - 1, 9, 1]
+    say(f"hrot hoisted N={N} L={L} b={b}")
+    ctx, s, msg, ct, keys, got = _hrot_setup(N, L, b, gs, 2, 40 + b)
+    t = 1 << 20
+    for m in range(2):
+        for r, g in enumerate(gs):
+            assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
+            want = simd.automorphism(msg[m] % t, g, t).astype(np.int64)
+            want = np.where(want > t // 2, want - t, want)
+            assert np.array_equal(orc.decrypt(ctx.primes, 20, s, got[m, r][None])[0], want), (m, g)
+
+
+def test_hrot_hoisted_papers_parameters_nine_rotations(dev):
+    """n = 2048 with a 60-bit q (two 30-bit primes), the 3x3 kernel's nine
+    rotations (powers of 3, with the row swap), 4 ciphertexts: sampled
+    (ciphertext, rotation) pairs against the oracle, every one by decryption."""
+    N, L, b = 2048, 2, 16
+    gs = [pow(3, r, 2 * N) for r in range(8)] + [2 * N - 1]
+    say("hrot hoisted n=2048, 9 rotations")
+    ctx, s, msg, ct, keys, got = _hrot_setup(N, L, b, gs, 4, 7)
+    for m, r in [(0, 0), (3, 8), (2, 5)]:
+        assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], gs[r], keys[r], b)), (m, r)
+    t = 1 << 20
+    dec = hy.hyena_decrypt(ctx, s, got.reshape(-1, 2, L, N)).reshape(4, len(gs), N)
+    for m in range(4):
+        for r, g in enumerate(gs):
+            want = simd.automorphism(msg[m] % t, g, t).astype(np.int64)
+            assert np.array_equal(dec[m, r], np.where(want > t // 2, want - t, want)), (m, r)
+
+
+def test_hrot_rejects_bad_arguments(dev):
+    import torch
+    ctx = ctx_for(1024, 2, 30)
+    L, N = 2, 1024
+    ct = torch.zeros(2 * L * N, dtype=torch.int32, device="cuda")
+    k = torch.zeros(2 * 2 * L * N * 2, dtype=torch.int32, device="cuda")
+    work = torch.zeros((2 * 2 + 1) * L * N, dtype=torch.int32, device="cuda")
+    out = torch.zeros(2 * L * N, dtype=torch.int32, device="cuda")
+    with pytest.raises(hy.HyenaError):                     # even g
+        hy.hyena_hrot_hoisted(ctx, ct, [4], 16, k, work, out)
+    with pytest.raises(hy.HyenaError):                     # base out of range
+        hy.hyena_hrot_hoisted(ctx, ct, [3], 30, k, work, out)
+    with pytest.raises(hy.HyenaError):                     # output overlapping the workspace
+        hy.hyena_hrot_hoisted(ctx, ct, [3], 16, k, work, work[:2 * L * N])

@@ -205,3 +205,16 @@ def test_plaintext_prime_context_and_simd_calls_on_host_only_context():
     assert L.hyena_automorphism(ctx.handle, fake, 1, 3, fake, null) == hy.HYENA_EINVAL
     e = (ctypes.c_uint32 * 1)(512)
     assert L.hyena_pmult_sparse(ctx.handle, fake, 1, 1, e, e, fake, null) == hy.HYENA_EINVAL
+
+
+def test_galois_keygen_matches_oracle():
+    """Host key-switching keys equal the oracle's bit for bit (same draws)."""
+    from oracle import simd
+    primes = orc.ntt_primes(1024, 2, 30)
+    ctx = hy.hyena_create(1024, 2, primes=primes, flags=HOST | hy.HYENA_ALLOW_INSECURE)
+    s = orc.keygen(1024, 12)
+    for g, b in [(3, 16), (2047, 29), (9, 8)]:
+        assert np.array_equal(hy.hyena_galois_keygen(ctx, s, g, b, 77 + g), simd.galois_keygen(primes, s, g, b, 77 + g))
+    for g, b in [(4, 16), (3, 0), (3, 30)]:
+        with pytest.raises(hy.HyenaError):
+            hy.hyena_galois_keygen(ctx, s, g, b, 1)
