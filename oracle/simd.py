@@ -229,3 +229,56 @@ def hrot_noise_bound(N: int, L: int, log2_base: int, B: int) -> int:
     """Added noise of one key switching: sum over the L*D keys of
     d_ij(X^g) e_ij, each coefficient at most N (2^b - 1) B."""
     return L * n_digits(log2_base) * N * ((1 << log2_base) - 1) * B
+
+
+# ---------------------------------------------------------------------------
+# BFV with a prime plaintext modulus p and the pieces of the SIMD convolution
+# ---------------------------------------------------------------------------
+
+def encrypt_p(primes, p: int, s, msgs, seed: int) -> np.ndarray:
+    """Symmetric BFV with plaintext modulus p ("Homomorphic Operations in BFV":
+    c0 = [Delta m + a s + e]_q, c1 = [-a]_q, Delta = floor(q / p)), drawn like
+    the power-of-two encryption (same counters); msgs: [n][N] integers (their
+    residues mod p are the message; Delta multiplies the integer as given)."""
+    from . import _lift, _uniform_mod, sample_error, sm64
+    msgs = np.asarray(msgs, dtype=np.int64)
+    n, N = msgs.shape
+    L = len(primes)
+    delta = math.prod(primes) // p
+    out = np.empty((n, 2, L, N), dtype=np.uint32)
+    j = np.arange(N, dtype=np.uint64)
+    for m in range(n):
+        e = sample_error(seed, np.uint64(2) * (np.uint64(m * N) + j) + np.uint64(1))
+        for i, qi in enumerate(primes):
+            a = _uniform_mod(sm64(seed, np.uint64(2) * (np.uint64((m * L + i) * N) + j)), qi).astype(np.uint32)
+            as_ = negacyclic_mul(a, _lift(s, qi), qi).astype(object)
+            dm = (np.mod(msgs[m], qi).astype(object) * (delta % qi)) % qi
+            out[m, 0, i] = ((dm + as_ + _lift(e, qi).astype(object)) % qi).astype(np.uint32)
+            out[m, 1, i] = ((np.uint64(qi) - a.astype(np.uint64)) % np.uint64(qi)).astype(np.uint32)
+    return out
+
+
+def decrypt_p(primes, p: int, s, ct) -> np.ndarray:
+    """m = [round(p [c0 + c1 s]_q / q)]_p in [0, p) (no tie: q and p odd)."""
+    from . import decrypt_phase
+    q = math.prod(primes)
+    ct = np.asarray(ct)
+    out = np.empty((ct.shape[0], ct.shape[-1]), dtype=np.int64)
+    for m in range(ct.shape[0]):
+        out[m] = [((p * v + q // 2) // q) % p for v in decrypt_phase(primes, s, ct[m])]
+    return out
+
+
+def cmult_accumulate(ins, W, primes) -> np.ndarray:
+    """CMult and HAdd of ciphertexts by integer scalars: out[o] = sum_r W[o][r]
+    in[r] mod q_i, ins [R][2][L][N], W [O][R] (signed integers)."""
+    ins = np.asarray(ins, dtype=np.uint32)
+    W = np.asarray(W, dtype=np.int64)
+    out = np.empty((W.shape[0],) + ins.shape[1:], dtype=np.uint32)
+    for o in range(W.shape[0]):
+        for i, q in enumerate(primes):
+            acc = np.zeros(ins.shape[1:2] + ins.shape[3:], dtype=object)
+            for r in range(ins.shape[0]):
+                acc = acc + int(W[o, r]) * ins[r, :, i, :].astype(object)
+            out[o, :, i, :] = (acc % q).astype(np.uint32)
+    return out

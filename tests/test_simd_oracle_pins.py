@@ -187,3 +187,34 @@ def test_galois_key_is_an_encryption_of_the_gadget():
             assert np.abs(v).max() <= orc.B_ERR
             errs.append(v)
         assert np.array_equal(errs[0], errs[1])
+
+
+def test_encrypt_p_reduces_to_the_power_of_two_encryption_and_round_trips():
+    """With p = 2^20 the general-modulus encryption equals the pinned
+    power-of-two one bit for bit (same draws, same Delta); with the paper's
+    prime p it decrypts back to the message."""
+    N, L = 1024, 2
+    primes = orc.ntt_primes(N, L, 30)
+    s = orc.keygen(N, 4)
+    rng = np.random.default_rng(2)
+    t = 1 << 20
+    m = rng.integers(-t // 2 + 1, t // 2 + 1, size=(2, N))
+    assert np.array_equal(simd.encrypt_p(primes, t, s, m, 17), orc.encrypt(primes, 20, s, m, 17))
+    p = 307201
+    mp = rng.integers(0, p, size=(2, N))
+    assert np.array_equal(simd.decrypt_p(primes, p, s, simd.encrypt_p(primes, p, s, mp, 5)), mp)
+
+
+def test_cmult_accumulate_is_linear_and_matches_decryption():
+    """Dec(sum_r W_r ct_r) = sum_r W_r m_r mod p (BFV is additively homomorphic
+    and CMult by integers scales messages), for small signed weights."""
+    N, L, p = 1024, 2, 12289
+    primes = orc.ntt_primes(N, L, 30)
+    s = orc.keygen(N, 6)
+    rng = np.random.default_rng(8)
+    m = rng.integers(0, p, size=(3, N))
+    ct = simd.encrypt_p(primes, p, s, m, 9)
+    W = np.array([[1, -2, 3], [0, 5, -7]])
+    acc = simd.cmult_accumulate(ct, W, primes)
+    dec = simd.decrypt_p(primes, p, s, acc)
+    assert np.array_equal(dec, (W @ m) % p)
