@@ -282,3 +282,59 @@ def cmult_accumulate(ins, W, primes) -> np.ndarray:
                 acc = acc + int(W[o, r]) * ins[r, :, i, :].astype(object)
             out[o, :, i, :] = (acc % q).astype(np.uint32)
     return out
+
+
+def frame_slots(x, frame_h: int, frame_w: int) -> np.ndarray:
+    """Slot rows of a SIMD input ciphertext packing c_n = 2 channels: channel c
+    of x [2][H][W] sits in row c at (1 + i) frame_w + (1 + j) of a
+    frame_h x frame_w frame (a zero border of at least one, power-of-two
+    width, as the paper's packing assumes)."""
+    x = np.asarray(x, dtype=np.int64)
+    C, H, W = x.shape
+    assert C == 2 and H + 2 <= frame_h and W + 2 <= frame_w
+    rows = np.zeros((2, frame_h * frame_w), dtype=np.int64)
+    for c in range(2):
+        f = np.zeros((frame_h, frame_w), dtype=np.int64)
+        f[1:1 + H, 1:1 + W] = x[c]
+        rows[c] = f.reshape(-1)
+    return rows.reshape(-1)
+
+
+def conv_rotations(n: int, frame_w: int):
+    """Galois exponents of the nine 3x3 offsets (di - 1) frame_w + (dj - 1):
+    X -> X^(3^r) moves slot s + r to slot s in both rows."""
+    return [pow(3, ((di - 1) * frame_w + (dj - 1)) % (n // 2), 2 * n) for di in range(3) for dj in range(3)]
+
+
+def simd_conv_cn2(primes, ct, w, k: int, kh: int, frame_w: int, rot_keys, swap_keys, log2_base: int) -> np.ndarray:
+    """The paper's convolution with c_n = 2 input channels per ciphertext
+    ("Enabling Output Channel Packing", Eq. (hadamard2), and the [k, -k]
+    plaintext of "Optimal Parameter Selection"), for a 3x3 kernel w [Co][2][3][3]:
+    1. HRot of the input by the nine kernel offsets (hoisted);
+    2. CMult + HAdd: A_o = sum_r k (f0 + f1)_r rot_r, B_o = sum_r (f0 - f1)_r rot_r;
+    3. one PMult of B_o by the [k, -k] plaintext kh (X^{n/4} + X^{3n/4}), added to A_o:
+       row 0 then holds 2k sum f0 x0, row 1 2k sum f1 x1 (the 1/2 of Eq.
+       (hadamard2) is left out: every output carries the same factor 2, like k);
+    4. HRot by X^{2n-1} (the row swap) and HAdd, aligning the two rows' partial
+       sums: both rows of output o hold 2k conv(x)_o.
+    rot_keys: {g: key} for the nine exponents of conv_rotations; swap_keys: the
+    key for 2n - 1. Returns [Co][2][L][N]."""
+    ct = np.asarray(ct, dtype=np.uint32)
+    n = ct.shape[-1]
+    gs = conv_rotations(n, frame_w)
+    rots = np.stack([hrot(primes, ct, g, rot_keys[g], log2_base) for g in gs])
+    w = np.asarray(w, dtype=np.int64)
+    Co = w.shape[0]
+    out = np.empty((Co,) + ct.shape, dtype=np.uint32)
+    wpm = np.zeros(n, dtype=np.int64)
+    wpm[n // 4] = wpm[3 * n // 4] = kh
+    for o in range(Co):
+        f0, f1 = w[o, 0].reshape(9), w[o, 1].reshape(9)
+        A, B = cmult_accumulate(rots, np.stack([k * (f0 + f1), f0 - f1]), primes)
+        Z = np.empty_like(A)
+        for part in range(2):
+            for i, q in enumerate(primes):
+                Z[part, i] = (A[part, i].astype(np.uint64) + pmult(B[part, i], wpm, q)) % np.uint64(q)
+        Zs = hrot(primes, Z, 2 * n - 1, swap_keys, log2_base)
+        out[o] = cmult_accumulate(np.stack([Z, Zs]), np.array([[1, 1]]), primes)[0]
+    return out

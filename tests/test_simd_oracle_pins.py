@@ -218,3 +218,30 @@ def test_cmult_accumulate_is_linear_and_matches_decryption():
     acc = simd.cmult_accumulate(ct, W, primes)
     dec = simd.decrypt_p(primes, p, s, acc)
     assert np.array_equal(dec, (W @ m) % p)
+
+
+def test_simd_conv_cn2_decrypts_to_2k_times_the_convolution():
+    """The paper's SIMD convolution (c_n = 2) through encryption: decrypting and
+    decoding output o gives 2k conv(x)_o mod p in both rows, at every position
+    of the image (brute-force convolution)."""
+    n, L, p, b = 1024, 3, 12289, 8
+    fh, fw = 16, 32
+    primes = orc.ntt_primes(n, L, 30)
+    s = orc.keygen(n, 31)
+    h = simd.h_pn(n, p)
+    k, kh = simd.best_k(h, p, 61)
+    rng = np.random.default_rng(12)
+    H, W, Co = fh - 2, fw - 2, 2
+    x = rng.integers(-8, 8, size=(2, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2, 3, 3))
+    ct = simd.encrypt_p(primes, p, s, simd.encode(simd.frame_slots(x, fh, fw), p, n)[None], 70)[0]
+    gs = simd.conv_rotations(n, fw)
+    rk = {g: simd.galois_keygen(primes, s, g, b, 900 + i) for i, g in enumerate(gs)}
+    sk_ = simd.galois_keygen(primes, s, 2 * n - 1, b, 999)
+    out = simd.simd_conv_cn2(primes, ct, w, k, kh, fw, rk, sk_, b)
+    y = orc.direct_conv(x, w, 3)
+    for o in range(Co):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, out[o][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
