@@ -413,6 +413,17 @@ int hyena_hrot_hoisted(const hyena_ctx *ctx, const uint32_t *d_ct, size_t n_ct, 
                        uint32_t *d_work, uint32_t *d_out, hyena_stream_t stream);
 
 /*
+ * CMult and HAdd by integer scalars without intermediate reduction ("Lazy
+ * Reduction"): d_out[o] = sum_r W[o][r] d_in[r] mod q_i for ciphertexts
+ * d_in [R][2][L][N] (either domain), d_w device int32 [O][R] with
+ * |W| <= 2^16 (not checked; larger weights give wrong sums), R <= 4096,
+ * d_out [O][2][L][N] not overlapping the inputs. With R = 0 the outputs are
+ * zero ciphertexts. Errors: EINVAL, EHIP.
+ */
+int hyena_cmult_accumulate(const hyena_ctx *ctx, const uint32_t *d_in, uint32_t R,
+                           const int32_t *d_w, uint32_t O, uint32_t *d_out, hyena_stream_t stream);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -90,6 +90,7 @@ _SIGS = {
     "hyena_galois_keygen": [_P, _P, _u32, _u32, _u64, _P],
     "hyena_ksk_prepare": [_P, _P, _sz, _P],
     "hyena_hrot_hoisted": [_P, _P, _sz, _u32, _P, _u32, _P, _P, _P, _P],
+    "hyena_cmult_accumulate": [_P, _P, _u32, _P, _u32, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -433,6 +434,17 @@ def hyena_hrot_hoisted(ctx: Ctx, d_ct, gs, log2_base: int, d_ksk, d_work, d_out,
     _check(lib().hyena_hrot_hoisted(ctx.handle, _dev_ptr(d_ct, "int32"), n, R, _np_ptr(g, np.uint32), log2_base,
                                     _dev_ptr(d_ksk, "int32"), _dev_ptr(d_work, "int32"), _dev_ptr(d_out, "int32"),
                                     _stream(stream)))
+
+
+def hyena_cmult_accumulate(ctx: Ctx, d_in, d_w, d_out, stream=None) -> None:
+    """d_out[o] = sum_r W[o][r] d_in[r] for ciphertexts [R][2][L][N], W int32 [O][R]."""
+    R = _polys(ctx, d_in, 2 * ctx.L)
+    if d_w.dim() != 2 or d_w.shape[1] != R:
+        raise ValueError("d_w must be [O][R]")
+    O = d_w.shape[0]
+    _need(d_out, O * 2 * ctx.L * ctx.N, "d_out")
+    _check(lib().hyena_cmult_accumulate(ctx.handle, _dev_ptr(d_in, "int32"), R, _dev_ptr(d_w, "int32"), O,
+                                        _dev_ptr(d_out, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

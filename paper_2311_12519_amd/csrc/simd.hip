@@ -187,6 +187,32 @@ __global__ void __launch_bounds__(STH) keyswitch_kernel(const uint32_t *work, co
     }
 }
 
+// out[o] = sum_r W[o][r] in[r] mod q_i for ciphertexts [R][2][L][N]: products
+// of residues by small signed integers summed exactly in a signed 64-bit word
+// (|W| <= 2^16, R <= 4096: |sum| < 2^59 <= q 2^30), one reduction per output
+// coefficient (CMult and HAdd without reduction, "Lazy Reduction")
+__global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *in, const int32_t *W, uint32_t *out,
+                                                        uint32_t R, uint32_t O, uint32_t logN, uint32_t L,
+                                                        LimbTable lt) {
+    const size_t PLN = (size_t)2 * L << logN;               // words per ciphertext
+    const size_t chunks = ((size_t)O * 2 * L) << (logN - 8);
+    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const size_t op = c >> (logN - 8);                  // o (2 L) + part L + limb
+        const uint32_t o = (uint32_t)(op / (2 * L));
+        const uint32_t limb = (uint32_t)(op % L);
+        const size_t idx = ((op % (2 * L)) << logN) + ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const int32_t *w = W + (size_t)o * R;
+        int64_t acc = 0;
+        for (uint32_t r = 0; r < R; r++) acc += (int64_t)w[r] * (int64_t)in[(size_t)r * PLN + idx];
+        const LimbConst &lc = lt.c[limb];
+        const uint64_t t = (uint64_t)(acc + ((int64_t)lc.q << 30));          // in [0, q 2^31)
+        // t 2^-32 mod q by one Montgomery reduction, then times 2^64 mod q
+        const uint32_t m = (uint32_t)t * lc.qinv_neg;
+        const uint32_t y = scsub((uint32_t)(((uint64_t)m * lc.q + t) >> 32), lc.q);
+        out[(size_t)o * PLN + idx] = smont(y, lc.r64, lc.q, lc.qinv_neg);
+    }
+}
+
 unsigned sgrid(size_t chunks) { return (unsigned)std::min<size_t>(chunks, 8192); }
 
 bool soverlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -364,4 +390,21 @@ extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size
                        d_work, d_ksk, d_out, n_ct, c->logN, c->L, c->lt, ra);
     if (int rc = slaunched(who)) return rc;
     return launch_ntt(c, d_out, n_ct * n_rot * 2, true, s);
+}
+
+extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, uint32_t R, const int32_t *d_w,
+                                      uint32_t O, uint32_t *d_out, hyena_stream_t stream) {
+    static const char *who = "hyena_cmult_accumulate";
+    if (!c || (R && O && (!d_in || !d_w || !d_out))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (R > 4096) return set_error(HYENA_EINVAL, std::string(who) + ": more than 4096 inputs");
+    for (uint32_t q : c->q)   // the bias q 2^30 must cover sums up to 2^59
+        if (q <= (1u << 29)) return set_error(HYENA_EINVAL, std::string(who) + ": primes must exceed 2^29");
+    if (O == 0) return HYENA_OK;
+    const size_t PLNb = (size_t)2 * c->L * c->N * 4;
+    if (soverlap(d_out, O * PLNb, d_in, R * PLNb) || soverlap(d_out, O * PLNb, d_w, (size_t)O * R * 4))
+        return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps an input");
+    hipLaunchKernelGGL(cmult_acc_kernel, dim3(sgrid(((size_t)O * 2 * c->L) << (c->logN - 8))), dim3(STH), 0,
+                       (hipStream_t)stream, d_in, d_w, d_out, R, O, c->logN, c->L, c->lt);
+    return slaunched(who);
 }

@@ -237,3 +237,58 @@ def test_hrot_rejects_bad_arguments(dev):
         hy.hyena_hrot_hoisted(ctx, ct, [3], 30, k, work, out)
     with pytest.raises(hy.HyenaError):                     # output overlapping the workspace
         hy.hyena_hrot_hoisted(ctx, ct, [3], 16, k, work, work[:2 * L * N])
+
+
+def test_simd_conv_cn2_on_gpu_matches_oracle(dev):
+    """The paper's SIMD convolution with c_n = 2 at its parameters (n = 2048,
+    p = 307201, k = 11), composed from the library's calls (hoisted HRot,
+    CMult-accumulate, PMult by the [k, -k] plaintext, row-swap HRot, HAdd): the
+    output ciphertexts equal the oracle's composition bit for bit and decrypt
+    to 2k conv(x) at every image position."""
+    import torch
+    n, L, p, b = 2048, 3, 307201, 8
+    fh, fw, Co = 32, 32, 4
+    say("simd conv c_n=2 n=2048")
+    ctx = ctx_for(n, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(n, 8)
+    h, k, kh = hy.hyena_simd_params(n, p, 61)
+    rng = np.random.default_rng(21)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(2, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2, 3, 3))
+    ct = simd.encrypt_p(primes, p, s, simd.encode(simd.frame_slots(x, fh, fw), p, n)[None], 5)[0]
+    gs = simd.conv_rotations(n, fw)
+    keys = np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 300 + i) for i, g in enumerate(gs)])
+    skey = hy.hyena_galois_keygen(ctx, s, 2 * n - 1, b, 399)
+    want = simd.simd_conv_cn2(primes, ct, w, k, kh, fw, {g: keys[i] for i, g in enumerate(gs)}, skey, b)
+    LN, D = L * n, hy.n_digits(b)
+    dk, dsk = to_dev(keys), to_dev(skey)
+    hy.hyena_ksk_prepare(ctx, dk)
+    hy.hyena_ksk_prepare(ctx, dsk)
+    i32 = dict(dtype=torch.int32, device="cuda")
+    rots = torch.empty(9 * 2 * LN, **i32)
+    work = torch.empty(max(1, Co) * (L * D + 1) * LN, **i32)
+    hy.hyena_hrot_hoisted(ctx, to_dev(ct), gs, b, dk, work, rots)
+    f0, f1 = w[:, 0].reshape(Co, 9), w[:, 1].reshape(Co, 9)
+    Wab = torch.from_numpy(np.concatenate([k * (f0 + f1), f0 - f1]).astype(np.int32)).cuda()   # A block, B block
+    AB = torch.empty(2 * Co * 2 * LN, **i32)
+    hy.hyena_cmult_accumulate(ctx, rots, Wab, AB)
+    PB = torch.empty(Co * 2 * LN, **i32)
+    hy.hyena_pmult_sparse(ctx, AB[Co * 2 * LN:], [n // 4, 3 * n // 4], [kh, kh], PB)
+    pair = torch.from_numpy(np.concatenate([np.eye(Co), np.eye(Co)], axis=1).astype(np.int32)).cuda()
+    ZP = torch.cat([AB[:Co * 2 * LN], PB])
+    Z = torch.empty(Co * 2 * LN, **i32)
+    hy.hyena_cmult_accumulate(ctx, ZP, pair, Z)
+    Zs = torch.empty(Co * 2 * LN, **i32)
+    hy.hyena_hrot_hoisted(ctx, Z, [2 * n - 1], b, dsk, work, Zs)
+    out = torch.empty(Co * 2 * LN, **i32)
+    hy.hyena_cmult_accumulate(ctx, torch.cat([Z, Zs]), pair, out)
+    got = from_dev(out).reshape(Co, 2, L, n)
+    assert np.array_equal(got, want)
+    y = orc.direct_conv(x, w, 3)
+    for o in range(Co):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, got[o][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
