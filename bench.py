@@ -40,6 +40,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -105,6 +106,8 @@ def parse():
                     help="skip the supplementary direct-versus-NTT run on MobileNetV1's depthwise layers")
     ap.add_argument("--no-client", action="store_true",
                     help="skip the supplementary client-side run (device encryption and decryption)")
+    ap.add_argument("--no-simd", action="store_true",
+                    help="skip the supplementary run of the SIMD-setting kernels (HRot, batch encoding, PMult)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -473,6 +476,8 @@ def main():
         parity += alt_parity
     if args.mode in ("all", "tuned") and not args.no_direct:
         out["direct_depthwise"] = direct_depthwise(args, hy, wl, torch)
+    if not args.no_simd:
+        out["simd"] = simd_kernels(hy, torch)
     if not args.no_cpu_baseline:
         import oracle as orc
         log("cpu baseline (oracle), with the parity check of the sampled outputs ...")
@@ -650,6 +655,195 @@ def client_side(args, ctx, layers, hy, torch, step_ms, n_layer_runs):
             "roundtrip_checked_ciphertexts": up,
             "host_library": {"sample_ciphertexts": k, "threads": min(16, os.cpu_count() or 1),
                              "encrypt_ct_per_s": k / (t1 - t0), "decrypt_ct_per_s": k / (t2 - t1)}}
+
+
+def simd_kernels(hy, torch):
+    """Supplementary figure: the kernels of the paper's own SIMD setting at its
+    parameters (n = 2048, a 60-bit q as two primes below 2^30, p = 307201):
+    hoisted HRot of 2048 ciphertexts by the nine rotations of a 3x3 kernel over
+    a 32-wide slot row, for three decomposition bases (more digits: more work,
+    less noise), batch encoding and decoding, PMult by the [k, -k] plaintext and
+    one automorphism, each the best of 3 runs (HIP events). Check: sampled
+    rotated ciphertexts decrypt to the automorphism of their messages."""
+    N, L, p, n_ct = 2048, 2, 307201, 2048
+    log("supplementary run: SIMD-setting kernels (n = 2048) ...")
+    dev = torch.device("cuda:0")
+    ctx = hy.hyena_create(N, L, flags=hy.HYENA_PRIMES_30BIT | hy.HYENA_ALLOW_INSECURE)
+    pctx = hy.hyena_create(N, 1, primes=[p], flags=hy.HYENA_PLAINTEXT_PRIME)
+    LN = L * N
+    sk = hy.hyena_keygen(ctx, 11)
+    t = 1 << 20
+    rng = np.random.default_rng(5)
+    msg = rng.integers(-t // 2 + 1, t // 2 + 1, size=(n_ct, N)).astype(np.int32)
+    d_sk = torch.from_numpy(sk).to(dev)
+    d_s = torch.empty(LN, dtype=torch.int32, device=dev)
+    hy.hyena_secret_prepare(ctx, d_sk, d_s)
+    d_msg = torch.from_numpy(msg).to(dev)
+    d_ct = torch.empty(n_ct * 2 * LN, dtype=torch.int32, device=dev)
+    tmp = torch.empty(n_ct * LN, dtype=torch.int32, device=dev)
+    hy.hyena_encrypt_device(ctx, d_s, d_msg, 3, tmp, d_ct)
+    offs = [(di - 1) * 32 + (dj - 1) for di in range(3) for dj in range(3)]
+    gs = [pow(3, o % (N // 2), 2 * N) for o in offs]
+
+    def best(fn, reps=3):
+        b = 1e30
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            b = min(b, e0.elapsed_time(e1))
+        return b
+
+    res = {"workload": f"n=2048, q = 2 primes < 2^30, p = {p}, {n_ct} ciphertexts x 9 rotations", "hrot": {}}
+    d_out = torch.empty(n_ct * len(gs) * 2 * LN, dtype=torch.int32, device=dev)
+    for b in (8, 11, 16):
+        D = hy.n_digits(b)
+        keys = np.stack([hy.hyena_galois_keygen(ctx, sk, g, b, 100 + g) for g in gs])
+        d_k = torch.from_numpy(keys.view(np.int32)).to(dev)
+        hy.hyena_ksk_prepare(ctx, d_k)
+        work = torch.empty(n_ct * (L * D + 1) * LN, dtype=torch.int32, device=dev)
+        ms = best(lambda: hy.hyena_hrot_hoisted(ctx, d_ct, gs, b, d_k, work, d_out))
+        # semantic check on sampled outputs (host decryption)
+        outv = d_out.view(n_ct, len(gs), 2, L, N)
+        for m, r in [(0, 0), (n_ct - 1, 8), (777, 4)]:
+            got = hy.hyena_decrypt(ctx, sk, outv[m, r].cpu().numpy().view(np.uint32)[None])[0]
+            a = msg[m].astype(np.int64) % t
+            want = np.zeros(N, dtype=np.int64)
+            g = gs[r]
+            for j in range(N):
+                e = j * g % (2 * N)
+                if e < N:
+                    want[e] = (want[e] + a[j]) % t
+                else:
+                    want[e - N] = (want[e - N] - a[j]) % t
+            want = np.where(want > t // 2, want - t, want)
+            if not np.array_equal(got, want):
+                raise SystemExit(f"hoisted HRot (b={b}) output ({m}, {r}) does not decrypt to m(X^g)")
+        # HBM floor: read the work array once, write the rotations, read the keys once
+        alg = n_ct * (L * D + 1) * LN * 4 + n_ct * len(gs) * 2 * LN * 4 + keys.nbytes
+        res["hrot"][f"b={b}"] = {"digits_per_limb": D, "ms": ms, "rotations_per_s": n_ct * len(gs) / (ms * 1e-3),
+                                 "noise_bound_bits": math.log2(L * D * N * ((1 << b) - 1) * 32),
+                                 "algorithmic_GBs": alg / (ms * 1e-3) / 1e9}
+        del d_k, work
+    # batch encoding / decoding over Z_p
+    slots = torch.from_numpy(rng.integers(0, p, size=(n_ct, N)).astype(np.int32)).to(dev)
+    coef = torch.empty_like(slots)
+    back = torch.empty_like(slots)
+    res["encode_ms"] = best(lambda: hy.hyena_simd_encode(pctx, slots, coef))
+    res["decode_ms"] = best(lambda: (hy.hyena_simd_encode(pctx, slots, coef), hy.hyena_simd_decode(pctx, coef, back)))
+    res["decode_ms"] -= res["encode_ms"]
+    if not torch.equal(back, slots):
+        raise SystemExit("SIMD decode(encode(v)) != v")
+    _, k, kh = hy.hyena_simd_params(N, p, 61)
+    # PMult by the [k, -k] plaintext and one automorphism over the rotated ciphertexts
+    d_o = torch.empty_like(d_out)
+    pm = best(lambda: hy.hyena_pmult_sparse(ctx, d_out, [N // 4, 3 * N // 4], [kh, kh], d_o))
+    au = best(lambda: hy.hyena_automorphism(ctx, d_out, 3, d_o))
+    nbytes = 2 * d_out.numel() * 4
+    res["pmult_pm_k"] = {"k": k, "kh": kh, "bytes": nbytes, "ms": pm, "GBs": nbytes / (pm * 1e-3) / 1e9}
+    res["automorphism"] = {"bytes": nbytes, "ms": au, "GBs": nbytes / (au * 1e-3) / 1e9}
+    res["encode_polys_per_s"] = n_ct / (res["encode_ms"] * 1e-3)
+    del d_o, d_out
+    hy.hyena_destroy(pctx)
+    hy.hyena_destroy(ctx)
+    res["conv_layer"] = simd_conv_layer(hy, torch, best, k, kh)
+    log(f"simd: hrot b=16 {res['hrot']['b=16']['ms']:.3f} ms for {n_ct}x9, encode {res['encode_ms']:.3f} ms")
+    return res
+
+
+def simd_conv_layer(hy, torch, best, k, kh):
+    """One convolution layer in the paper's SIMD setting with c_n = 2: 30x30
+    images (32x32 frames, one channel per slot row), 64 -> 64 channels, 3x3,
+    n = 2048, three primes below 2^30 (a 90-bit q: the noise of 288 scaled
+    rotations plus the [k, -k] PMult needs more than the paper's 60 bits with
+    this key switching), decomposition base 2^8. Steps: hoisted HRot of the
+    32 input ciphertexts by the nine offsets; CMult-accumulate of the A and B
+    Walsh components of every output channel over the 288 rotations; PMult of
+    B by the [k, -k] plaintext; A + PMult(B); row-swap HRot; HAdd. Inputs are
+    random valid residues (the time does not depend on them; parity of the
+    same composition is a GPU test). The coefficient-encoded path (NTT, MAC,
+    inverse NTT) of the same layer at the same n and q is timed beside it."""
+    N, L, b, Ci, Co, fw = 2048, 3, 8, 64, 64, 32
+    dev = torch.device("cuda:0")
+    ctx = hy.hyena_create(N, L, flags=hy.HYENA_PRIMES_30BIT | hy.HYENA_ALLOW_INSECURE)
+    LN, D, n_in = L * N, hy.n_digits(b), Ci // 2
+    i32 = dict(dtype=torch.int32, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    ct = torch.empty((n_in, 2, L, N), **i32)
+    for i, q in enumerate(ctx.primes):
+        ct[:, :, i, :] = torch.randint(0, q, ct[:, :, i, :].shape, generator=g, device=dev, dtype=torch.int64).to(torch.int32)
+    ct = ct.view(-1)
+    sk = hy.hyena_keygen(ctx, 5)
+    gs = [pow(3, ((di - 1) * fw + (dj - 1)) % (N // 2), 2 * N) for di in range(3) for dj in range(3)]
+    keys = torch.from_numpy(np.stack([hy.hyena_galois_keygen(ctx, sk, gg, b, 10 + i) for i, gg in enumerate(gs)]).view(np.int32)).to(dev)
+    skey = torch.from_numpy(hy.hyena_galois_keygen(ctx, sk, 2 * N - 1, b, 99).view(np.int32)).to(dev)
+    hy.hyena_ksk_prepare(ctx, keys)
+    hy.hyena_ksk_prepare(ctx, skey)
+    rng = np.random.default_rng(9)
+    w = rng.integers(-8, 8, size=(Co, Ci, 9))
+    f0, f1 = w[:, 0::2, :].reshape(Co, -1), w[:, 1::2, :].reshape(Co, -1)   # [Co][32 ciphertexts x 9 rotations]
+    W_A = torch.from_numpy((k * (f0 + f1)).astype(np.int32)).to(dev)
+    W_B = torch.from_numpy((f0 - f1).astype(np.int32)).to(dev)
+    pair = torch.from_numpy(np.concatenate([np.eye(Co), np.eye(Co)], axis=1).astype(np.int32)).to(dev)
+    rots = torch.empty(n_in * 9 * 2 * LN, **i32)
+    work = torch.empty(max(n_in, Co) * (L * D + 1) * LN, **i32)
+    AP = torch.empty(2 * Co * 2 * LN, **i32)     # [A | PMult(B)]
+    Bb = torch.empty(Co * 2 * LN, **i32)
+    Zb = torch.empty(2 * Co * 2 * LN, **i32)     # [Z | swapped Z]
+    out = torch.empty(Co * 2 * LN, **i32)
+    half = Co * 2 * LN
+    ev = []
+
+    def layer(mark=False):
+        def m():
+            if mark:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                ev.append(e)
+        m()
+        hy.hyena_hrot_hoisted(ctx, ct, gs, b, keys, work, rots)
+        m()
+        hy.hyena_cmult_accumulate(ctx, rots, W_A, AP[:half])
+        hy.hyena_cmult_accumulate(ctx, rots, W_B, Bb)
+        m()
+        hy.hyena_pmult_sparse(ctx, Bb, [N // 4, 3 * N // 4], [kh, kh], AP[half:])
+        hy.hyena_cmult_accumulate(ctx, AP, pair, Zb[:half])
+        m()
+        hy.hyena_hrot_hoisted(ctx, Zb[:half], [2 * N - 1], b, skey, work, Zb[half:])
+        hy.hyena_cmult_accumulate(ctx, Zb, pair, out)
+        m()
+
+    ms = best(layer)
+    ev.clear()
+    layer(mark=True)
+    torch.cuda.synchronize()
+    st = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    res = {"workload": "30x30, 64 -> 64 channels, 3x3, n=2048, 3 primes < 2^30, base 2^8, c_n = 2",
+           "ms": ms, "input_ciphertexts": n_in, "rotations": n_in * 9 + Co, "output_ciphertexts": Co,
+           "stages_ms": {"hrot_inputs": st[0], "cmult_accumulate": st[1], "pmult_and_add": st[2],
+                         "row_swap_hrot_and_add": st[3]}}
+    # the coefficient-encoded path of the same layer at the same n and q
+    d = hy.hyena_conv_plan(ctx, 30, 30, Ci, Co, 3, c_n=1, flags=hy.HYENA_FUSE_WHT)
+    wt = torch.from_numpy(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8)).to(dev)
+    wn = torch.empty(hy.wntt_words(ctx, d), **i32)
+    hy.hyena_encode_weights(ctx, d, wt, wn)
+    cin = torch.empty(d.n_in * 2 * LN, **i32)
+    cin.copy_(ct[:cin.numel()].repeat(cin.numel() // ct.numel() + 1)[:cin.numel()])
+    cout = torch.empty(d.n_out * 2 * LN, **i32)
+
+    def coeff():
+        hy.hyena_ntt(ctx, cin)
+        hy.hyena_conv(ctx, d, cin, wn, cout)
+        hy.hyena_intt(ctx, cout)
+
+    res["coefficient_path"] = {"ms": best(coeff), "input_ciphertexts": d.n_in, "output_ciphertexts": d.n_out,
+                               "channels_per_ciphertext": d.ci}
+    hy.hyena_destroy(ctx)
+    log(f"simd conv layer {ms:.3f} ms (coefficient path {res['coefficient_path']['ms']:.3f} ms)")
+    return res
 
 
 def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):
