@@ -124,6 +124,8 @@ extern "C" int hyena_conv_direct(const hyena_ctx *c, const hyena_conv_desc *d, c
     if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv_direct: descriptor not planned");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv_direct: context was created host-only");
     if (c->N % DCHUNK) return set_error(HYENA_EUNSUPPORTED, "hyena_conv_direct: N must be a multiple of 1024");
+    for (uint32_t q : c->q)   // the bias q 2^29 must cover every signed sum
+        if (q <= (1u << 29)) return set_error(HYENA_EINVAL, "hyena_conv_direct: primes must exceed 2^29");
     if (d->O >= c->N) return set_error(HYENA_EINVAL, "hyena_conv_direct: kernel exponents exceed N");
     const uint32_t batch = d->batch ? d->batch : 1;
     const size_t rows = (size_t)batch * d->tiles;
