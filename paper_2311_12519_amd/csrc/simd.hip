@@ -66,13 +66,13 @@ __global__ void __launch_bounds__(STH) ntt_to_slots_kernel(const uint32_t *ntt, 
 __global__ void __launch_bounds__(STH) automorphism_kernel(const uint32_t *in, uint32_t *out, size_t polys,
                                                            uint32_t logN, uint32_t L, uint32_t ginv, LimbTable lt) {
     const uint32_t N = 1u << logN, mask = 2 * N - 1;
-    const size_t chunks = polys << (logN - 8);
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t poly = c >> (logN - 8);   // limb-polynomial index, limb = poly mod L
-        const uint32_t q = lt.c[(uint32_t)(poly % L)].q;
-        const uint32_t i = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+    const uint32_t chunks = (uint32_t)(polys << (logN - 8));   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t poly = c >> (logN - 8);   // limb-polynomial index, limb = poly mod L
+        const uint32_t q = lt.c[poly % L].q;
+        const uint32_t i = ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
         const uint32_t j = (i * ginv) & mask;
-        const size_t base = poly << logN;
+        const size_t base = (size_t)poly << logN;
         uint32_t v;
         if (j < N) {
             v = in[base + j];
@@ -95,13 +95,13 @@ struct Sparse {
 __global__ void __launch_bounds__(STH) pmult_sparse_kernel(const uint32_t *in, uint32_t *out, size_t polys,
                                                            uint32_t logN, uint32_t L, LimbTable lt, Sparse sp) {
     const uint32_t N = 1u << logN, mask = 2 * N - 1;
-    const size_t chunks = polys << (logN - 8);
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t poly = c >> (logN - 8);
-        const uint32_t limb = (uint32_t)(poly % L);
+    const uint32_t chunks = (uint32_t)(polys << (logN - 8));   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t poly = c >> (logN - 8);
+        const uint32_t limb = poly % L;
         const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg;
-        const uint32_t i = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
-        const size_t base = poly << logN;
+        const uint32_t i = ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const size_t base = (size_t)poly << logN;
         uint32_t acc = 0;
         for (uint32_t t = 0; t < sp.n; t++) {
             const uint32_t d = (i - sp.e[t]) & mask;
@@ -136,14 +136,14 @@ struct RotArgs {
 __global__ void __launch_bounds__(STH) decompose_kernel(const uint32_t *ct, uint32_t *work, size_t n_ct,
                                                         uint32_t logN, uint32_t L, RotArgs ra) {
     const uint32_t N = 1u << logN, mask = (1u << ra.b) - 1, T = L * ra.D + 1;
-    const size_t LN = (size_t)L << logN, chunks = (n_ct * L) << (logN - 8);
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t mk = c >> (logN - 8);                   // m L + k
-        const size_t m = mk / L;
-        const uint32_t k = (uint32_t)(mk - m * L);
-        const uint32_t x = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
-        const uint32_t *c0 = ct + m * 2 * LN, *c1 = c0 + LN;
-        uint32_t *w = work + m * T * LN + (size_t)k * N + x;
+    const size_t LN = (size_t)L << logN;
+    const uint32_t chunks = (uint32_t)((n_ct * L) << (logN - 8));   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t mk = c >> (logN - 8);                 // m L + k
+        const uint32_t m = mk / L, k = mk % L;
+        const uint32_t x = ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t *c0 = ct + (size_t)m * 2 * LN, *c1 = c0 + LN;
+        uint32_t *w = work + (size_t)m * T * LN + (size_t)k * N + x;
         for (uint32_t i = 0; i < L; i++) {
             const uint32_t v = c1[(size_t)i * N + x];
             for (uint32_t j = 0; j < ra.D; j++) w[(size_t)(i * ra.D + j) * LN] = (v >> (ra.b * j)) & mask;
@@ -161,27 +161,41 @@ __global__ void __launch_bounds__(STH) keyswitch_kernel(const uint32_t *work, co
                                                         RotArgs ra) {
     const uint32_t N = 1u << logN, mask = 2 * N - 1, TD = L * ra.D;
     const size_t LN = (size_t)L << logN;
-    const size_t chunks = ((n_ct * ra.n_rot) * L) << (logN - 8);
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t mrk = c >> (logN - 8);                  // (m n_rot + r) L + k
-        const uint32_t k = (uint32_t)(mrk % L);
-        const size_t mr = mrk / L;
-        const uint32_t r = (uint32_t)(mr % ra.n_rot);
-        const size_t m = mr / ra.n_rot;
-        const uint32_t s = ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+    // (m n_rot + r) L + k < 2^31 (checked on the host): 32-bit index arithmetic
+    const uint32_t chunks = (uint32_t)(((n_ct * ra.n_rot) * L) << (logN - 8));
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t mrk = c >> (logN - 8);                // (m n_rot + r) L + k
+        const uint32_t k = mrk % L, mr = mrk / L;
+        const uint32_t r = mr % ra.n_rot, m = mr / ra.n_rot;
+        const uint32_t s = ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
         const uint32_t e = ((2 * brev(s, logN) + 1) * ra.g[r]) & mask;
         const uint32_t sr = brev(e >> 1, logN);
         const LimbConst &lc = lt.c[k];
         const uint32_t q = lc.q, qn = lc.qinv_neg;
-        const uint32_t *wm = work + m * (TD + 1) * LN + (size_t)k * N;
+        const uint32_t *wm = work + (size_t)m * (TD + 1) * LN + (size_t)k * N + sr;
         const uint32_t *kr = ksk + (size_t)r * TD * 2 * LN + (size_t)k * N + s;
-        uint32_t acc0 = wm[(size_t)TD * LN + sr], acc1 = 0;
-        for (uint32_t t = 0; t < TD; t++) {
-            const uint32_t d = wm[(size_t)t * LN + sr];
+        uint32_t acc0 = wm[(size_t)TD * LN], acc1 = 0;
+        uint32_t t = 0;
+        for (; t + 4 <= TD; t += 4) {   // the twelve loads of four digit terms first
+            uint32_t d[4], k0[4], k1[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                d[u] = wm[(size_t)(t + u) * LN];
+                k0[u] = kr[(size_t)(2 * (t + u)) * LN];
+                k1[u] = kr[(size_t)(2 * (t + u) + 1) * LN];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                acc0 = scsub(acc0 + smont(d[u], k0[u], q, qn), q);
+                acc1 = scsub(acc1 + smont(d[u], k1[u], q, qn), q);
+            }
+        }
+        for (; t < TD; t++) {
+            const uint32_t d = wm[(size_t)t * LN];
             acc0 = scsub(acc0 + smont(d, kr[(size_t)(2 * t) * LN], q, qn), q);
             acc1 = scsub(acc1 + smont(d, kr[(size_t)(2 * t + 1) * LN], q, qn), q);
         }
-        uint32_t *o = out + mr * 2 * LN + (size_t)k * N + s;
+        uint32_t *o = out + (size_t)mr * 2 * LN + (size_t)k * N + s;
         o[0] = acc0;
         o[LN] = acc1;
     }
@@ -195,14 +209,14 @@ __global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *in, cons
                                                         uint32_t R, uint32_t O, uint32_t logN, uint32_t L,
                                                         LimbTable lt) {
     const size_t PLN = (size_t)2 * L << logN;               // words per ciphertext
-    const size_t chunks = ((size_t)O * 2 * L) << (logN - 8);
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t op = c >> (logN - 8);                  // o (2 L) + part L + limb
-        const uint32_t o = (uint32_t)(op / (2 * L));
-        const uint32_t limb = (uint32_t)(op % L);
-        const size_t idx = ((op % (2 * L)) << logN) + ((uint32_t)(c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+    const uint32_t chunks = (uint32_t)(((size_t)O * 2 * L) << (logN - 8));   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t op = c >> (logN - 8);                // o (2 L) + part L + limb
+        const uint32_t o = op / (2 * L), limb = op % L;
+        const size_t idx = ((size_t)(op % (2 * L)) << logN) + ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
         const int32_t *w = W + (size_t)o * R;
         int64_t acc = 0;
+#pragma unroll 8
         for (uint32_t r = 0; r < R; r++) acc += (int64_t)w[r] * (int64_t)in[(size_t)r * PLN + idx];
         const LimbConst &lc = lt.c[limb];
         const uint64_t t = (uint64_t)(acc + ((int64_t)lc.q << 30));          // in [0, q 2^31)
@@ -306,6 +320,7 @@ extern "C" int hyena_automorphism(const hyena_ctx *c, const uint32_t *d_in, size
     if (!(g & 1)) return set_error(HYENA_EINVAL, std::string(who) + ": g must be odd");
     if (P == 0) return HYENA_OK;
     const size_t polys = P * c->L;
+    if (polys > (0x7fffffffull >> (c->logN - 8))) return set_error(HYENA_EINVAL, std::string(who) + ": too many polynomials");
     const size_t bytes = polys * c->N * 4;
     if (soverlap(d_in, bytes, d_out, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps d_in");
     // g^-1 mod 2N (g odd): Newton's iteration x <- x (2 - g x) doubles the correct low bits
@@ -327,6 +342,7 @@ extern "C" int hyena_pmult_sparse(const hyena_ctx *c, const uint32_t *d_in, size
     if (n_terms > MAX_TERMS) return set_error(HYENA_EINVAL, std::string(who) + ": more than 16 monomials");
     if (P == 0) return HYENA_OK;
     const size_t polys = P * c->L;
+    if (polys > (0x7fffffffull >> (c->logN - 8))) return set_error(HYENA_EINVAL, std::string(who) + ": too many polynomials");
     const size_t bytes = polys * c->N * 4;
     if (soverlap(d_in, bytes, d_out, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps d_in");
     Sparse sp{};
@@ -373,7 +389,8 @@ extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size
         ra.g[r] = gs[r] & (2 * c->N - 1);
     }
     const size_t LN = (size_t)c->L * c->N, T = (size_t)c->L * ra.D + 1;
-    if (n_ct * T > 0x7fffffffull / c->L || n_ct * n_rot * 2 > 0x7fffffffull / c->L)
+    if (n_ct * T > 0x7fffffffull / c->L || n_ct * n_rot * 2 > 0x7fffffffull / c->L ||
+        ((n_ct * n_rot * c->L) << (c->logN - 8)) > 0x7fffffffull)
         return set_error(HYENA_EINVAL, std::string(who) + ": too many ciphertexts");
     const size_t ct_b = n_ct * 2 * LN * 4, work_b = n_ct * T * LN * 4, out_b = n_ct * n_rot * 2 * LN * 4,
                  ksk_b = (size_t)n_rot * (T - 1) * 2 * LN * 4;
@@ -401,6 +418,8 @@ extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, 
     for (uint32_t q : c->q)   // the bias q 2^30 must cover sums up to 2^59
         if (q <= (1u << 29)) return set_error(HYENA_EINVAL, std::string(who) + ": primes must exceed 2^29");
     if (O == 0) return HYENA_OK;
+    if ((size_t)O * 2 * c->L > (0x7fffffffull >> (c->logN - 8)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": too many outputs");
     const size_t PLNb = (size_t)2 * c->L * c->N * 4;
     if (soverlap(d_out, O * PLNb, d_in, R * PLNb) || soverlap(d_out, O * PLNb, d_w, (size_t)O * R * 4))
         return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps an input");
