@@ -309,9 +309,13 @@ def conv_rotations(n: int, frame_w: int):
 def simd_conv_cn2(primes, ct, w, k: int, kh: int, frame_w: int, rot_keys, swap_keys, log2_base: int) -> np.ndarray:
     """The paper's convolution with c_n = 2 input channels per ciphertext
     ("Enabling Output Channel Packing", Eq. (hadamard2), and the [k, -k]
-    plaintext of "Optimal Parameter Selection"), for a 3x3 kernel w [Co][2][3][3]:
-    1. HRot of the input by the nine kernel offsets (hoisted);
-    2. CMult + HAdd: A_o = sum_r k (f0 + f1)_r rot_r, B_o = sum_r (f0 - f1)_r rot_r;
+    plaintext of "Optimal Parameter Selection"), for a 3x3 kernel
+    w [Co][2 G][3][3] over G input ciphertexts ct [G][2][L][N] (ciphertext g
+    holds channel 2g in its first slot row, 2g + 1 in its second; a single
+    ciphertext [2][L][N] is G = 1):
+    1. HRot of every input by the nine kernel offsets (hoisted);
+    2. CMult + HAdd: A_o = sum_{g,r} k (f0 + f1)_{g,r} rot_{g,r},
+       B_o = sum_{g,r} (f0 - f1)_{g,r} rot_{g,r}, f0 = w[o][2g], f1 = w[o][2g+1];
     3. one PMult of B_o by the [k, -k] plaintext kh (X^{n/4} + X^{3n/4}), added to A_o:
        row 0 then holds 2k sum f0 x0, row 1 2k sum f1 x1 (the 1/2 of Eq.
        (hadamard2) is left out: every output carries the same factor 2, like k);
@@ -320,16 +324,19 @@ def simd_conv_cn2(primes, ct, w, k: int, kh: int, frame_w: int, rot_keys, swap_k
     rot_keys: {g: key} for the nine exponents of conv_rotations; swap_keys: the
     key for 2n - 1. Returns [Co][2][L][N]."""
     ct = np.asarray(ct, dtype=np.uint32)
-    n = ct.shape[-1]
+    if ct.ndim == 3:
+        ct = ct[None]
+    G, n = ct.shape[0], ct.shape[-1]
     gs = conv_rotations(n, frame_w)
-    rots = np.stack([hrot(primes, ct, g, rot_keys[g], log2_base) for g in gs])
+    rots = np.stack([hrot(primes, ct[g], r, rot_keys[r], log2_base) for g in range(G) for r in gs])
     w = np.asarray(w, dtype=np.int64)
     Co = w.shape[0]
-    out = np.empty((Co,) + ct.shape, dtype=np.uint32)
+    out = np.empty((Co,) + ct.shape[1:], dtype=np.uint32)
     wpm = np.zeros(n, dtype=np.int64)
     wpm[n // 4] = wpm[3 * n // 4] = kh
     for o in range(Co):
-        f0, f1 = w[o, 0].reshape(9), w[o, 1].reshape(9)
+        f0 = w[o, 0::2].reshape(G * 9)              # index g*9 + r, matching rots
+        f1 = w[o, 1::2].reshape(G * 9)
         A, B = cmult_accumulate(rots, np.stack([k * (f0 + f1), f0 - f1]), primes)
         Z = np.empty_like(A)
         for part in range(2):

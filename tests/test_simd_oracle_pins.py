@@ -220,21 +220,24 @@ def test_cmult_accumulate_is_linear_and_matches_decryption():
     assert np.array_equal(dec, (W @ m) % p)
 
 
-def test_simd_conv_cn2_decrypts_to_2k_times_the_convolution():
-    """The paper's SIMD convolution (c_n = 2) through encryption: decrypting and
-    decoding output o gives 2k conv(x)_o mod p in both rows, at every position
-    of the image (brute-force convolution)."""
+@pytest.mark.parametrize("G", [1, 2])
+def test_simd_conv_cn2_decrypts_to_2k_times_the_convolution(G):
+    """The paper's SIMD convolution (c_n = 2) through encryption, over one and
+    two input ciphertexts (2 and 4 input channels): decrypting and decoding
+    output o gives 2k conv(x)_o mod p in both rows, at every position of the
+    image (brute-force convolution)."""
     n, L, p, b = 1024, 3, 12289, 8
     fh, fw = 16, 32
     primes = orc.ntt_primes(n, L, 30)
     s = orc.keygen(n, 31)
     h = simd.h_pn(n, p)
     k, kh = simd.best_k(h, p, 61)
-    rng = np.random.default_rng(12)
+    rng = np.random.default_rng(12 + G)
     H, W, Co = fh - 2, fw - 2, 2
-    x = rng.integers(-8, 8, size=(2, H, W))
-    w = rng.integers(-8, 8, size=(Co, 2, 3, 3))
-    ct = simd.encrypt_p(primes, p, s, simd.encode(simd.frame_slots(x, fh, fw), p, n)[None], 70)[0]
+    x = rng.integers(-8, 8, size=(2 * G, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2 * G, 3, 3))
+    msgs = np.stack([simd.encode(simd.frame_slots(x[2 * g:2 * g + 2], fh, fw), p, n) for g in range(G)])
+    ct = simd.encrypt_p(primes, p, s, msgs, 70)
     gs = simd.conv_rotations(n, fw)
     rk = {g: simd.galois_keygen(primes, s, g, b, 900 + i) for i, g in enumerate(gs)}
     sk_ = simd.galois_keygen(primes, s, 2 * n - 1, b, 999)
