@@ -783,48 +783,14 @@ def simd_conv_layer(hy, torch, best, k, kh):
     hy.hyena_ksk_prepare(ctx, keys)
     hy.hyena_ksk_prepare(ctx, skey)
     rng = np.random.default_rng(9)
-    w = rng.integers(-8, 8, size=(Co, Ci, 9))
-    f0, f1 = w[:, 0::2, :].reshape(Co, -1), w[:, 1::2, :].reshape(Co, -1)   # [Co][32 ciphertexts x 9 rotations]
-    W_A = torch.from_numpy((k * (f0 + f1)).astype(np.int32)).to(dev)
-    W_B = torch.from_numpy((f0 - f1).astype(np.int32)).to(dev)
-    pair = torch.from_numpy(np.concatenate([np.eye(Co), np.eye(Co)], axis=1).astype(np.int32)).to(dev)
-    rots = torch.empty(n_in * 9 * 2 * LN, **i32)
-    work = torch.empty(max(n_in, Co) * (L * D + 1) * LN, **i32)
-    AP = torch.empty(2 * Co * 2 * LN, **i32)     # [A | PMult(B)]
-    Bb = torch.empty(Co * 2 * LN, **i32)
-    Zb = torch.empty(2 * Co * 2 * LN, **i32)     # [Z | swapped Z]
+    wa, wb = hy.hyena_simd_conv_weights(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8), k)
+    d_wa, d_wb = torch.from_numpy(wa).to(dev), torch.from_numpy(wb).to(dev)
+    work = torch.empty(hy.hyena_simd_conv_workspace(ctx, n_in, Co, b), **i32)
     out = torch.empty(Co * 2 * LN, **i32)
-    half = Co * 2 * LN
-    ev = []
-
-    def layer(mark=False):
-        def m():
-            if mark:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record()
-                ev.append(e)
-        m()
-        hy.hyena_hrot_hoisted(ctx, ct, gs, b, keys, work, rots)
-        m()
-        hy.hyena_cmult_accumulate(ctx, rots, W_A, AP[:half])
-        hy.hyena_cmult_accumulate(ctx, rots, W_B, Bb)
-        m()
-        hy.hyena_pmult_sparse(ctx, Bb, [N // 4, 3 * N // 4], [kh, kh], AP[half:])
-        hy.hyena_cmult_accumulate(ctx, AP, pair, Zb[:half])
-        m()
-        hy.hyena_hrot_hoisted(ctx, Zb[:half], [2 * N - 1], b, skey, work, Zb[half:])
-        hy.hyena_cmult_accumulate(ctx, Zb, pair, out)
-        m()
-
-    ms = best(layer)
-    ev.clear()
-    layer(mark=True)
-    torch.cuda.synchronize()
-    st = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    ms = best(lambda: hy.hyena_simd_conv_cn2(ctx, ct, fw, d_wa, d_wb, kh, b, keys, skey, work, out))
     res = {"workload": "30x30, 64 -> 64 channels, 3x3, n=2048, 3 primes < 2^30, base 2^8, c_n = 2",
            "ms": ms, "input_ciphertexts": n_in, "rotations": n_in * 9 + Co, "output_ciphertexts": Co,
-           "stages_ms": {"hrot_inputs": st[0], "cmult_accumulate": st[1], "pmult_and_add": st[2],
-                         "row_swap_hrot_and_add": st[3]}}
+           "call": "hyena_simd_conv_cn2"}
     # the coefficient-encoded path of the same layer at the same n and q
     d = hy.hyena_conv_plan(ctx, 30, 30, Ci, Co, 3, c_n=1, flags=hy.HYENA_FUSE_WHT)
     wt = torch.from_numpy(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8)).to(dev)

@@ -424,6 +424,37 @@ int hyena_cmult_accumulate(const hyena_ctx *ctx, const uint32_t *d_in, uint32_t 
                            const int32_t *d_w, uint32_t O, uint32_t *d_out, hyena_stream_t stream);
 
 /*
+ * The paper's convolution with c_n = 2 in the SIMD setting (3x3 kernel):
+ * input ciphertext g of n_in holds input channel 2g in its first slot row and
+ * 2g + 1 in its second, each as a zero-bordered frame of width frame_w (so a
+ * kernel offset (di, dj) is a rotation by (di - 1) frame_w + (dj - 1) slots).
+ *   1. hoisted HRot of every input by the nine offsets;
+ *   2. CMult + HAdd: A_o = sum wa[o][g*9 + r] rot_{g,r}, B_o likewise with wb;
+ *   3. Z_o = A_o + PMult(B_o, kh (X^(N/4) + X^(3N/4))), the [k, -k] plaintext;
+ *   4. out_o = Z_o + HRot(Z_o, X -> X^(2N-1)), the row swap.
+ * With wa = k (f0 + f1) and wb = f0 - f1 (hyena_simd_conv_weights), both
+ * rows of out_o hold 2k conv(x)_o mod p ("Enabling Output Channel Packing",
+ * Eq. (hadamard2), with the [k, -k] plaintext of "Optimal Parameter
+ * Selection"; the 1/2 of the equation is left out, every output carrying 2).
+ *
+ * hyena_simd_conv_weights (host): f int8 [Co][Ci][3][3], Ci even, k <= 255;
+ * wa, wb host int32 [Co][Ci/2 * 9]. hyena_simd_conv_workspace: uint32 words
+ * of d_work hyena_simd_conv_cn2 needs (0 for a bad log2_base).
+ * hyena_simd_conv_cn2: d_ct device [n_in][2][L][N] (n_in <= 455), d_wa/d_wb
+ * device int32 [Co][n_in*9], d_rot_ksk prepared keys [9][L*D][2][L][N] for the
+ * nine offsets in (di, dj) order, d_swap_ksk prepared key for 2N - 1, d_work
+ * 16-byte aligned, d_out device [Co][2][L][N] not overlapping the rest.
+ * Errors: EINVAL, EHIP.
+ */
+int hyena_simd_conv_weights(uint32_t Ci, uint32_t Co, const int8_t *f, uint32_t k, int32_t *wa,
+                            int32_t *wb);
+size_t hyena_simd_conv_workspace(const hyena_ctx *ctx, uint32_t n_in, uint32_t Co, uint32_t log2_base);
+int hyena_simd_conv_cn2(const hyena_ctx *ctx, const uint32_t *d_ct, uint32_t n_in, uint32_t frame_w,
+                        const int32_t *d_wa, const int32_t *d_wb, uint32_t Co, uint32_t kh,
+                        uint32_t log2_base, const uint32_t *d_rot_ksk, const uint32_t *d_swap_ksk,
+                        uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -91,6 +91,8 @@ _SIGS = {
     "hyena_ksk_prepare": [_P, _P, _sz, _P],
     "hyena_hrot_hoisted": [_P, _P, _sz, _u32, _P, _u32, _P, _P, _P, _P],
     "hyena_cmult_accumulate": [_P, _P, _u32, _P, _u32, _P, _P],
+    "hyena_simd_conv_weights": [_u32, _u32, _P, _u32, _P, _P],
+    "hyena_simd_conv_cn2": [_P, _P, _u32, _u32, _P, _P, _u32, _u32, _u32, _P, _P, _P, _sz, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -445,6 +447,38 @@ def hyena_cmult_accumulate(ctx: Ctx, d_in, d_w, d_out, stream=None) -> None:
     _need(d_out, O * 2 * ctx.L * ctx.N, "d_out")
     _check(lib().hyena_cmult_accumulate(ctx.handle, _dev_ptr(d_in, "int32"), R, _dev_ptr(d_w, "int32"), O,
                                         _dev_ptr(d_out, "int32"), _stream(stream)))
+
+
+def hyena_simd_conv_weights(f: np.ndarray, k: int):
+    """Walsh CMult scalars (wa, wb) int32 [Co][Ci/2 * 9] of the c_n = 2 SIMD
+    convolution from integer weights f [Co][Ci][3][3]."""
+    f = np.ascontiguousarray(f, dtype=np.int8)
+    Co, Ci = f.shape[0], f.shape[1]
+    wa = np.zeros((Co, Ci // 2 * 9), dtype=np.int32)
+    wb = np.zeros_like(wa)
+    _check(lib().hyena_simd_conv_weights(Ci, Co, _np_ptr(f, np.int8), k, _np_ptr(wa, np.int32), _np_ptr(wb, np.int32)))
+    return wa, wb
+
+
+def hyena_simd_conv_workspace(ctx: Ctx, n_in: int, Co: int, log2_base: int) -> int:
+    L = lib()
+    L.hyena_simd_conv_workspace.argtypes = [_P, _u32, _u32, _u32]
+    L.hyena_simd_conv_workspace.restype = _sz
+    return int(L.hyena_simd_conv_workspace(ctx.handle, n_in, Co, log2_base))
+
+
+def hyena_simd_conv_cn2(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, log2_base: int, d_rot_ksk, d_swap_ksk,
+                        d_work, d_out, stream=None) -> None:
+    """The paper's c_n = 2 SIMD convolution (3x3): d_out[o] holds 2k conv(x)_o in both rows."""
+    n_in = _polys(ctx, d_ct, 2 * ctx.L)
+    Co = d_wa.shape[0]
+    if tuple(d_wa.shape) != (Co, n_in * 9) or tuple(d_wb.shape) != (Co, n_in * 9):
+        raise ValueError("d_wa and d_wb must be [Co][n_in * 9]")
+    _need(d_out, Co * 2 * ctx.L * ctx.N, "d_out")
+    _check(lib().hyena_simd_conv_cn2(ctx.handle, _dev_ptr(d_ct, "int32"), n_in, frame_w, _dev_ptr(d_wa, "int32"),
+                                     _dev_ptr(d_wb, "int32"), Co, kh, log2_base, _dev_ptr(d_rot_ksk, "int32"),
+                                     _dev_ptr(d_swap_ksk, "int32"), _dev_ptr(d_work, "int32"), d_work.numel(),
+                                     _dev_ptr(d_out, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -227,6 +227,17 @@ __global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *in, cons
     }
 }
 
+// HAdd: out = a + b mod q_i for ciphertext arrays [..][L][N] of `polys` limb-polynomials
+__global__ void __launch_bounds__(STH) hadd_kernel(const uint32_t *a, const uint32_t *b, uint32_t *out,
+                                                   uint32_t polys, uint32_t logN, uint32_t L, LimbTable lt) {
+    const uint32_t chunks = polys << (logN - 8);   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t q = lt.c[(c >> (logN - 8)) % L].q;
+        const size_t i = ((size_t)c << 8) + threadIdx.x;
+        out[i] = scsub(a[i] + b[i], q);
+    }
+}
+
 unsigned sgrid(size_t chunks) { return (unsigned)std::min<size_t>(chunks, 8192); }
 
 bool soverlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -425,5 +436,87 @@ extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, 
         return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps an input");
     hipLaunchKernelGGL(cmult_acc_kernel, dim3(sgrid(((size_t)O * 2 * c->L) << (c->logN - 8))), dim3(STH), 0,
                        (hipStream_t)stream, d_in, d_w, d_out, R, O, c->logN, c->L, c->lt);
+    return slaunched(who);
+}
+
+extern "C" int hyena_simd_conv_weights(uint32_t Ci, uint32_t Co, const int8_t *f, uint32_t k, int32_t *wa,
+                                       int32_t *wb) {
+    if (!f || !wa || !wb) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights: NULL argument");
+    if (Ci == 0 || Ci % 2 || Co == 0) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights: Ci must be even and positive, Co positive");
+    if (k > 255) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights: k above 255 (the scalars must stay within 2^16)");
+    const uint32_t G = Ci / 2;
+    for (uint32_t o = 0; o < Co; o++)
+        for (uint32_t g = 0; g < G; g++)
+            for (uint32_t r = 0; r < 9; r++) {
+                const int32_t f0 = f[((size_t)o * Ci + 2 * g) * 9 + r], f1 = f[((size_t)o * Ci + 2 * g + 1) * 9 + r];
+                wa[((size_t)o * G + g) * 9 + r] = (int32_t)k * (f0 + f1);
+                wb[((size_t)o * G + g) * 9 + r] = f0 - f1;
+            }
+    return HYENA_OK;
+}
+
+extern "C" size_t hyena_simd_conv_workspace(const hyena_ctx *c, uint32_t n_in, uint32_t Co, uint32_t log2_base) {
+    if (!c || log2_base < 1 || log2_base > 29) return 0;
+    const size_t LN = (size_t)c->L * c->N, D = (31 + log2_base - 1) / log2_base;
+    const size_t hw = (size_t)std::max(n_in, Co) * (c->L * D + 1) * LN;
+    return (size_t)n_in * 9 * 2 * LN + hw + 3 * (size_t)Co * 2 * LN;
+}
+
+extern "C" int hyena_simd_conv_cn2(const hyena_ctx *c, const uint32_t *d_ct, uint32_t n_in, uint32_t frame_w,
+                                   const int32_t *d_wa, const int32_t *d_wb, uint32_t Co, uint32_t kh,
+                                   uint32_t log2_base, const uint32_t *d_rot_ksk, const uint32_t *d_swap_ksk,
+                                   uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream) {
+    static const char *who = "hyena_simd_conv_cn2";
+    if (!c || !d_ct || !d_wa || !d_wb || !d_rot_ksk || !d_swap_ksk || !d_work || !d_out)
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (n_in == 0 || Co == 0) return set_error(HYENA_EINVAL, std::string(who) + ": no inputs or outputs");
+    if (n_in * 9 > 4096) return set_error(HYENA_EINVAL, std::string(who) + ": more than 455 input ciphertexts");
+    if (frame_w == 0 || frame_w >= c->N / 2) return set_error(HYENA_EINVAL, std::string(who) + ": frame width must be in [1, N/2)");
+    const size_t need = hyena_simd_conv_workspace(c, n_in, Co, log2_base);
+    if (need == 0) return set_error(HYENA_EINVAL, std::string(who) + ": log2_base must be in [1, 29]");
+    if (work_words < need) return set_error(HYENA_EINVAL, std::string(who) + ": workspace too small");
+    if ((size_t)Co * 2 * c->L > (0x7fffffffull >> (c->logN - 8)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": too many outputs");
+    const size_t LN = (size_t)c->L * c->N, CT = 2 * LN;
+    if (soverlap(d_out, Co * CT * 4, d_work, work_words * 4) || soverlap(d_out, Co * CT * 4, d_ct, n_in * CT * 4))
+        return set_error(HYENA_EINVAL, std::string(who) + ": d_out overlaps an input or the workspace");
+    // the nine rotations: slot s + (di - 1) frame_w + (dj - 1) moves to slot s, X -> X^(3^off)
+    uint32_t gs[9];
+    const uint32_t half = c->N / 2, mask = 2 * c->N - 1;
+    for (uint32_t di = 0; di < 3; di++)
+        for (uint32_t dj = 0; dj < 3; dj++) {
+            const int64_t off = ((int64_t)di - 1) * frame_w + ((int64_t)dj - 1);
+            const uint32_t e = (uint32_t)(((off % half) + half) % half);
+            uint32_t g = 1, b = 3;
+            for (uint32_t x = e; x; x >>= 1) {
+                if (x & 1) g = (g * b) & mask;
+                b = (b * b) & mask;
+            }
+            gs[di * 3 + dj] = g;
+        }
+    uint32_t *rots = d_work;                                   // [n_in][9][2][L][N]
+    uint32_t *hwork = rots + (size_t)n_in * 9 * CT;            // HRot workspace
+    const size_t D = (31 + log2_base - 1) / log2_base;
+    uint32_t *A = hwork + (size_t)std::max(n_in, Co) * (c->L * D + 1) * LN;
+    uint32_t *B = A + Co * CT, *PB = B + Co * CT;
+    const hipStream_t s = (hipStream_t)stream;
+    const uint32_t polys = Co * 2 * c->L;
+    // 1. hoisted HRot of every input by the nine offsets
+    if (int rc = hyena_hrot_hoisted(c, d_ct, n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
+    // 2. CMult + HAdd of the Walsh components over every rotation
+    if (int rc = hyena_cmult_accumulate(c, rots, n_in * 9, d_wa, Co, A, stream)) return rc;
+    if (int rc = hyena_cmult_accumulate(c, rots, n_in * 9, d_wb, Co, B, stream)) return rc;
+    // 3. PMult of B by the [k, -k] plaintext, added to A (Z into B's buffer)
+    const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
+    if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)Co, 2, exps, coefs, PB, stream)) return rc;   // [2 Co][L][N]
+    hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, PB, B, polys,
+                       c->logN, c->L, c->lt);
+    if (int rc = slaunched(who)) return rc;
+    // 4. row-swap HRot (into PB's buffer) and HAdd
+    const uint32_t swap = 2 * c->N - 1;
+    if (int rc = hyena_hrot_hoisted(c, B, Co, 1, &swap, log2_base, d_swap_ksk, hwork, PB, stream)) return rc;
+    hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, B, PB, d_out, polys,
+                       c->logN, c->L, c->lt);
     return slaunched(who);
 }

@@ -292,3 +292,47 @@ def test_simd_conv_cn2_on_gpu_matches_oracle(dev):
         for row in range(2):
             frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
+
+
+def test_simd_conv_cn2_entry_point(dev):
+    """hyena_simd_conv_cn2 over two input ciphertexts (4 channels -> 3 outputs)
+    at the paper's parameters: equal to the oracle's convolution bit for bit,
+    decrypting to 2k conv(x); a too-small workspace is refused."""
+    import torch
+    n, L, p, b = 2048, 3, 307201, 8
+    fh, fw, G, Co = 32, 32, 2, 3
+    say("hyena_simd_conv_cn2 n=2048, 2 inputs")
+    ctx = ctx_for(n, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(n, 19)
+    h, k, kh = hy.hyena_simd_params(n, p, 61)
+    rng = np.random.default_rng(33)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(2 * G, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2 * G, 3, 3))
+    msgs = np.stack([simd.encode(simd.frame_slots(x[2 * g:2 * g + 2], fh, fw), p, n) for g in range(G)])
+    ct = simd.encrypt_p(primes, p, s, msgs, 6)
+    gs = simd.conv_rotations(n, fw)
+    keys = np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 600 + i) for i, g in enumerate(gs)])
+    skey = hy.hyena_galois_keygen(ctx, s, 2 * n - 1, b, 699)
+    want = simd.simd_conv_cn2(primes, ct, w, k, kh, fw, {g: keys[i] for i, g in enumerate(gs)}, skey, b)
+    dk, dsk = to_dev(keys), to_dev(skey)
+    hy.hyena_ksk_prepare(ctx, dk)
+    hy.hyena_ksk_prepare(ctx, dsk)
+    wa, wb = hy.hyena_simd_conv_weights(w.astype(np.int8), k)
+    d_wa, d_wb = torch.from_numpy(wa).cuda(), torch.from_numpy(wb).cuda()
+    words = hy.hyena_simd_conv_workspace(ctx, G, Co, b)
+    work = torch.empty(words, dtype=torch.int32, device="cuda")
+    out = torch.empty(Co * 2 * L * n, dtype=torch.int32, device="cuda")
+    d_ct = to_dev(ct)
+    hy.hyena_simd_conv_cn2(ctx, d_ct, fw, d_wa, d_wb, kh, b, dk, dsk, work, out)
+    got = from_dev(out).reshape(Co, 2, L, n)
+    assert np.array_equal(got, want)
+    y = orc.direct_conv(x, w, 3)
+    for o in range(Co):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, got[o][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
+    with pytest.raises(hy.HyenaError):
+        hy.hyena_simd_conv_cn2(ctx, d_ct, fw, d_wa, d_wb, kh, b, dk, dsk, work[:words - 4], out)

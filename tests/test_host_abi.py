@@ -218,3 +218,18 @@ def test_galois_keygen_matches_oracle():
     for g, b in [(4, 16), (3, 0), (3, 30)]:
         with pytest.raises(hy.HyenaError):
             hy.hyena_galois_keygen(ctx, s, g, b, 1)
+
+
+def test_simd_conv_weights():
+    rng = np.random.default_rng(1)
+    f = rng.integers(-8, 8, size=(3, 4, 3, 3)).astype(np.int8)
+    wa, wb = hy.hyena_simd_conv_weights(f, 11)
+    for o in range(3):
+        for g in range(2):
+            f0, f1 = f[o, 2 * g].reshape(9).astype(np.int32), f[o, 2 * g + 1].reshape(9).astype(np.int32)
+            assert np.array_equal(wa[o, g * 9:(g + 1) * 9], 11 * (f0 + f1))
+            assert np.array_equal(wb[o, g * 9:(g + 1) * 9], f0 - f1)
+    with pytest.raises(hy.HyenaError):                    # odd channel count
+        hy.hyena_simd_conv_weights(f[:, :3], 11)
+    with pytest.raises(hy.HyenaError):                    # scalars would exceed 2^16
+        hy.hyena_simd_conv_weights(f, 256)
