@@ -201,6 +201,54 @@ __global__ void __launch_bounds__(STH) keyswitch_kernel(const uint32_t *work, co
     }
 }
 
+// The same key switching with TD = L D known at compile time: a thread keeps
+// the 2 TD key words of its (rotation, limb, slot) in registers and serves
+// KS_M ciphertexts with them, so keys are read once per KS_M ciphertexts.
+constexpr uint32_t KS_M = 8;
+
+template <uint32_t TD>
+__global__ void __launch_bounds__(STH) keyswitch_keys_kernel(const uint32_t *work, const uint32_t *ksk, uint32_t *out,
+                                                             uint32_t n_ct, uint32_t logN, uint32_t L, LimbTable lt,
+                                                             RotArgs ra) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1, cpl = 1u << (logN - 8);
+    const size_t LN = (size_t)L << logN;
+    const uint32_t groups = (n_ct + KS_M - 1) / KS_M;
+    const uint32_t chunks = groups * ra.n_rot * L * cpl;   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t sch = c % cpl, rest = c / cpl;
+        const uint32_t k = rest % L, rr = rest / L;
+        const uint32_t r = rr % ra.n_rot, mg = rr / ra.n_rot;
+        const uint32_t s = (sch << 8) + threadIdx.x;
+        const uint32_t e = ((2 * brev(s, logN) + 1) * ra.g[r]) & mask;
+        const uint32_t sr = brev(e >> 1, logN);
+        const LimbConst &lc = lt.c[k];
+        const uint32_t q = lc.q, qn = lc.qinv_neg;
+        const uint32_t *kr = ksk + (size_t)r * TD * 2 * LN + (size_t)k * N + s;
+        uint32_t k0[TD], k1[TD];
+#pragma unroll
+        for (uint32_t t = 0; t < TD; t++) {
+            k0[t] = kr[(size_t)(2 * t) * LN];
+            k1[t] = kr[(size_t)(2 * t + 1) * LN];
+        }
+        const uint32_t m_end = min(n_ct, (mg + 1) * KS_M);
+        for (uint32_t m = mg * KS_M; m < m_end; m++) {
+            const uint32_t *wm = work + (size_t)m * (TD + 1) * LN + (size_t)k * N + sr;
+            uint32_t d[TD + 1];
+#pragma unroll
+            for (uint32_t t = 0; t <= TD; t++) d[t] = wm[(size_t)t * LN];
+            uint32_t acc0 = d[TD], acc1 = 0;
+#pragma unroll
+            for (uint32_t t = 0; t < TD; t++) {
+                acc0 = scsub(acc0 + smont(d[t], k0[t], q, qn), q);
+                acc1 = scsub(acc1 + smont(d[t], k1[t], q, qn), q);
+            }
+            uint32_t *o = out + ((size_t)m * ra.n_rot + r) * 2 * LN + (size_t)k * N + s;
+            o[0] = acc0;
+            o[LN] = acc1;
+        }
+    }
+}
+
 // out[o] = sum_r W[o][r] in[r] mod q_i for ciphertexts [R][2][L][N]: products
 // of residues by small signed integers summed exactly in a signed 64-bit word
 // (|W| <= 2^16, R <= 4096: |sum| < 2^59 <= q 2^30), one reduction per output
@@ -414,8 +462,20 @@ extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size
                        n_ct, c->logN, c->L, ra);
     if (int rc = slaunched(who)) return rc;
     if (int rc = launch_ntt(c, d_work, n_ct * T, false, s)) return rc;
-    hipLaunchKernelGGL(keyswitch_kernel, dim3(sgrid(((n_ct * n_rot) * c->L) << (c->logN - 8))), dim3(STH), 0, s,
-                       d_work, d_ksk, d_out, n_ct, c->logN, c->L, c->lt, ra);
+    const uint32_t TD = c->L * ra.D;
+    const size_t kchunks = (((n_ct + KS_M - 1) / KS_M) * n_rot * c->L) << (c->logN - 8);
+#define HY_KS(td)                                                                                               \
+    case td:                                                                                                    \
+        hipLaunchKernelGGL(keyswitch_keys_kernel<td>, dim3(sgrid(kchunks)), dim3(STH), 0, s, d_work, d_ksk, d_out, \
+                           (uint32_t)n_ct, c->logN, c->L, c->lt, ra);                                           \
+        break;
+    switch (TD) {
+        HY_KS(1) HY_KS(2) HY_KS(3) HY_KS(4) HY_KS(6) HY_KS(8) HY_KS(9) HY_KS(12)
+        default:
+            hipLaunchKernelGGL(keyswitch_kernel, dim3(sgrid(((n_ct * n_rot) * c->L) << (c->logN - 8))), dim3(STH), 0,
+                               s, d_work, d_ksk, d_out, n_ct, c->logN, c->L, c->lt, ra);
+    }
+#undef HY_KS
     if (int rc = slaunched(who)) return rc;
     return launch_ntt(c, d_out, n_ct * n_rot * 2, true, s);
 }
