@@ -336,3 +336,38 @@ def test_simd_conv_cn2_entry_point(dev):
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
     with pytest.raises(hy.HyenaError):
         hy.hyena_simd_conv_cn2(ctx, d_ct, fw, d_wa, d_wb, kh, b, dk, dsk, work[:words - 4], out)
+
+
+def test_simd_conv_cn1_from_library_calls(dev):
+    """c_n = 1 at the paper's parameters: hoisted HRot of 4 single-channel
+    ciphertexts by the nine offsets, then one CMult-accumulate (the paper's
+    CMult and HAdd with lazy reduction) per output channel; decrypts to
+    conv(x) in the first row."""
+    import torch
+    n, L, p, b = 2048, 3, 307201, 8
+    fh, fw, Ci, Co = 32, 32, 4, 3
+    say("simd conv c_n=1 n=2048")
+    ctx = ctx_for(n, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(n, 23)
+    rng = np.random.default_rng(44)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(Ci, H, W))
+    w = rng.integers(-8, 8, size=(Co, Ci, 3, 3))
+    rows = [simd.frame_slots(np.stack([x[c], np.zeros_like(x[c])]), fh, fw) for c in range(Ci)]
+    ct = simd.encrypt_p(primes, p, s, np.stack([simd.encode(r, p, n) for r in rows]), 4)
+    gs = simd.conv_rotations(n, fw)
+    keys = to_dev(np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 80 + i) for i, g in enumerate(gs)]))
+    hy.hyena_ksk_prepare(ctx, keys)
+    LN, D = L * n, hy.n_digits(b)
+    rots = torch.empty(Ci * 9 * 2 * LN, dtype=torch.int32, device="cuda")
+    work = torch.empty(Ci * (L * D + 1) * LN, dtype=torch.int32, device="cuda")
+    hy.hyena_hrot_hoisted(ctx, to_dev(ct), gs, b, keys, work, rots)
+    out = torch.empty(Co * 2 * LN, dtype=torch.int32, device="cuda")
+    hy.hyena_cmult_accumulate(ctx, rots, torch.from_numpy(w.reshape(Co, Ci * 9).astype(np.int32)).cuda(), out)
+    got = from_dev(out).reshape(Co, 2, L, n)
+    y = orc.direct_conv(x, w, 3)
+    for o in range(Co):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, got[o][None])[0], p, n).astype(np.int64)
+        frame = slots[:n // 2].reshape(fh, fw)
+        assert np.array_equal(frame[1:1 + H, 1:1 + W], y[o] % p), o

@@ -248,3 +248,28 @@ def test_simd_conv_cn2_decrypts_to_2k_times_the_convolution(G):
         for row in range(2):
             frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
+
+
+def test_simd_conv_cn1_is_rotations_and_lazy_cmult():
+    """c_n = 1 (one channel per ciphertext, in its first slot row): the
+    convolution is sum_{c,r} f[o][c][r] HRot(ct_c, offset r), CMult + HAdd
+    only; decryption gives conv(x)_o in the first row."""
+    n, L, p, b = 1024, 3, 12289, 8
+    fh, fw, Ci, Co = 16, 32, 2, 2
+    primes = orc.ntt_primes(n, L, 30)
+    s = orc.keygen(n, 41)
+    rng = np.random.default_rng(5)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(Ci, H, W))
+    w = rng.integers(-8, 8, size=(Co, Ci, 3, 3))
+    rows = [simd.frame_slots(np.stack([x[c], np.zeros_like(x[c])]), fh, fw) for c in range(Ci)]
+    ct = simd.encrypt_p(primes, p, s, np.stack([simd.encode(r, p, n) for r in rows]), 3)
+    gs = simd.conv_rotations(n, fw)
+    keys = {g: simd.galois_keygen(primes, s, g, b, 60 + i) for i, g in enumerate(gs)}
+    rots = np.stack([simd.hrot(primes, ct[c], g, keys[g], b) for c in range(Ci) for g in gs])
+    out = simd.cmult_accumulate(rots, w.reshape(Co, Ci * 9), primes)
+    y = orc.direct_conv(x, w, 3)
+    for o in range(Co):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, out[o][None])[0], p, n).astype(np.int64)
+        frame = slots[:n // 2].reshape(fh, fw)
+        assert np.array_equal(frame[1:1 + H, 1:1 + W], y[o] % p), o
