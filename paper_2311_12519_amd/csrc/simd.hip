@@ -483,7 +483,8 @@ extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size
 extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, uint32_t R, const int32_t *d_w,
                                       uint32_t O, uint32_t *d_out, hyena_stream_t stream) {
     static const char *who = "hyena_cmult_accumulate";
-    if (!c || (R && O && (!d_in || !d_w || !d_out))) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (!c || (O && !d_out) || (R && O && (!d_in || !d_w)))   // with R = 0 the outputs are still written (zeros)
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
     if (int rc = device_ctx(c, who)) return rc;
     if (R > 4096) return set_error(HYENA_EINVAL, std::string(who) + ": more than 4096 inputs");
     for (uint32_t q : c->q)   // the bias q 2^30 must cover sums up to 2^59

@@ -233,3 +233,12 @@ def test_simd_conv_weights():
         hy.hyena_simd_conv_weights(f[:, :3], 11)
     with pytest.raises(hy.HyenaError):                    # scalars would exceed 2^16
         hy.hyena_simd_conv_weights(f, 256)
+
+
+def test_cmult_accumulate_refuses_null_output_even_without_inputs():
+    """R = 0 still writes O (zero) outputs, so a NULL output is refused before
+    anything else (a host-only context would refuse next)."""
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    null = ctypes.c_void_p(0)
+    assert hy.lib().hyena_cmult_accumulate(ctx.handle, null, 0, null, 3, null, null) == hy.HYENA_EINVAL
+    assert "NULL" in hy.lib().hyena_last_error().decode()
