@@ -345,3 +345,42 @@ def simd_conv_cn2(primes, ct, w, k: int, kh: int, frame_w: int, rot_keys, swap_k
         Zs = hrot(primes, Z, 2 * n - 1, swap_keys, log2_base)
         out[o] = cmult_accumulate(np.stack([Z, Zs]), np.array([[1, 1]]), primes)[0]
     return out
+
+
+def simd_conv_cn2_packed(primes, ct, w, k: int, kh: int, frame_w: int, rot_keys, swap_keys,
+                         log2_base: int) -> np.ndarray:
+    """The convolution with c_n = 2 channels per ciphertext on both sides
+    (output channel packing, "Enabling Output Channel Packing": each PMult by a
+    two-valued plaintext [a | b] in its Walsh form (k (a + b)) CMult +
+    PMult((a - b) CMult, [k, -k])), for a 3x3 kernel w [Co][2 G][3][3], Co even:
+    1. HRot of every input by X^{2n-1} (the row swap): sct_g holds channel
+       2g + 1 in its first row and 2g in its second;
+    2. hoisted HRot of every ct_g and sct_g by the nine kernel offsets;
+    3. for output pair (o, o + 1), with a the first row's and b the second
+       row's weights (ct_g: a = w[o][2g], b = w[o+1][2g+1]; sct_g:
+       a = w[o][2g+1], b = w[o+1][2g]):
+       A = sum k (a + b) rot, B = sum (a - b) rot, out = A + PMult(B, [k, -k]);
+       the first row of out holds 2k conv(x)_o, the second 2k conv(x)_{o+1}.
+    Returns [Co/2][2][L][N]."""
+    ct = np.asarray(ct, dtype=np.uint32)
+    if ct.ndim == 3:
+        ct = ct[None]
+    G, n = ct.shape[0], ct.shape[-1]
+    sct = np.stack([hrot(primes, ct[g], 2 * n - 1, swap_keys, log2_base) for g in range(G)])
+    gs = conv_rotations(n, frame_w)
+    srcs = np.concatenate([ct, sct])                  # h = 0: ct_g, h = 1: sct_g
+    rots = np.stack([hrot(primes, srcs[j], r, rot_keys[r], log2_base) for j in range(2 * G) for r in gs])
+    w = np.asarray(w, dtype=np.int64)
+    Co = w.shape[0]
+    out = np.empty((Co // 2,) + ct.shape[1:], dtype=np.uint32)
+    wpm = np.zeros(n, dtype=np.int64)
+    wpm[n // 4] = wpm[3 * n // 4] = kh
+    for o2 in range(Co // 2):
+        o = 2 * o2
+        a = np.concatenate([w[o, 0::2].reshape(G * 9), w[o, 1::2].reshape(G * 9)])
+        b = np.concatenate([w[o + 1, 1::2].reshape(G * 9), w[o + 1, 0::2].reshape(G * 9)])
+        A, B = cmult_accumulate(rots, np.stack([k * (a + b), a - b]), primes)
+        for part in range(2):
+            for i, q in enumerate(primes):
+                out[o2, part, i] = (A[part, i].astype(np.uint64) + pmult(B[part, i], wpm, q)) % np.uint64(q)
+    return out

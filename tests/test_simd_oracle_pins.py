@@ -273,3 +273,33 @@ def test_simd_conv_cn1_is_rotations_and_lazy_cmult():
         slots = simd.decode(simd.decrypt_p(primes, p, s, out[o][None])[0], p, n).astype(np.int64)
         frame = slots[:n // 2].reshape(fh, fw)
         assert np.array_equal(frame[1:1 + H, 1:1 + W], y[o] % p), o
+
+
+@pytest.mark.parametrize("G", [1, 2])
+def test_simd_conv_cn2_packed_outputs_two_channels_per_ciphertext(G):
+    """Output channel packing: output ciphertext o2 decrypts to 2k conv(x)_{2 o2}
+    in its first slot row and 2k conv(x)_{2 o2 + 1} in its second, at every
+    image position; half as many output ciphertexts as output channels."""
+    n, L, p, b = 1024, 3, 12289, 8
+    fh, fw, Co = 16, 32, 4
+    primes = orc.ntt_primes(n, L, 30)
+    s = orc.keygen(n, 51)
+    h = simd.h_pn(n, p)
+    k, kh = simd.best_k(h, p, 61)
+    rng = np.random.default_rng(60 + G)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(2 * G, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2 * G, 3, 3))
+    msgs = np.stack([simd.encode(simd.frame_slots(x[2 * g:2 * g + 2], fh, fw), p, n) for g in range(G)])
+    ct = simd.encrypt_p(primes, p, s, msgs, 71)
+    gs = simd.conv_rotations(n, fw)
+    rk = {g: simd.galois_keygen(primes, s, g, b, 910 + i) for i, g in enumerate(gs)}
+    swk = simd.galois_keygen(primes, s, 2 * n - 1, b, 998)
+    out = simd.simd_conv_cn2_packed(primes, ct, w, k, kh, fw, rk, swk, b)
+    assert out.shape[0] == Co // 2
+    y = orc.direct_conv(x, w, 3)
+    for o2 in range(Co // 2):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, out[o2][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[2 * o2 + row]) % p), (o2, row)
