@@ -791,6 +791,17 @@ def simd_conv_layer(hy, torch, best, k, kh):
     res = {"workload": "30x30, 64 -> 64 channels, 3x3, n=2048, 3 primes < 2^30, base 2^8, c_n = 2",
            "ms": ms, "input_ciphertexts": n_in, "rotations": n_in * 9 + Co, "output_ciphertexts": Co,
            "call": "hyena_simd_conv_cn2"}
+    # the same layer with output channel packing: two output channels per output ciphertext
+    pa, pb = hy.hyena_simd_conv_weights_packed(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8), k)
+    d_pa, d_pb = torch.from_numpy(pa).to(dev), torch.from_numpy(pb).to(dev)
+    pwork = torch.empty(hy.hyena_simd_conv_packed_workspace(ctx, n_in, Co, b), **i32)
+    pout = torch.empty(Co // 2 * 2 * LN, **i32)
+    del work
+    res["output_packed"] = {"ms": best(lambda: hy.hyena_simd_conv_packed(ctx, ct, fw, d_pa, d_pb, kh, b, keys, skey,
+                                                                          pwork, pout)),
+                            "rotations": n_in * 10, "output_ciphertexts": Co // 2,
+                            "output_bytes": Co // 2 * 2 * LN * 4, "call": "hyena_simd_conv_packed"}
+    del pwork
     # the coefficient-encoded path of the same layer at the same n and q
     d = hy.hyena_conv_plan(ctx, 30, 30, Ci, Co, 3, c_n=1, flags=hy.HYENA_FUSE_WHT)
     wt = torch.from_numpy(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8)).to(dev)
@@ -808,7 +819,8 @@ def simd_conv_layer(hy, torch, best, k, kh):
     res["coefficient_path"] = {"ms": best(coeff), "input_ciphertexts": d.n_in, "output_ciphertexts": d.n_out,
                                "channels_per_ciphertext": d.ci}
     hy.hyena_destroy(ctx)
-    log(f"simd conv layer {ms:.3f} ms (coefficient path {res['coefficient_path']['ms']:.3f} ms)")
+    log(f"simd conv layer {ms:.3f} ms, output-packed {res['output_packed']['ms']:.3f} ms "
+        f"(coefficient path {res['coefficient_path']['ms']:.3f} ms)")
     return res
 
 

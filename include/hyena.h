@@ -455,6 +455,33 @@ int hyena_simd_conv_cn2(const hyena_ctx *ctx, const uint32_t *d_ct, uint32_t n_i
                         uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream);
 
 /*
+ * The same convolution with output channel packing ("Enabling Output Channel
+ * Packing": two output channels per output ciphertext, the communication of
+ * conventional packed convolution). Every PMult by a two-valued plaintext
+ * [a | b] is taken in its Walsh form, k (a + b) CMult + PMult((a - b) CMult,
+ * [k, -k]):
+ *   1. HRot of every input by X^(2N-1) (row swap);
+ *   2. hoisted HRot of the inputs and their swaps by the nine offsets;
+ *   3. A = sum wa rot, B = sum wb rot, out = A + PMult(B, [k, -k]).
+ * With hyena_simd_conv_weights_packed (a the first row's weights, b the
+ * second's: a = f[o][2g], b = f[o+1][2g+1] on input g, a = f[o][2g+1],
+ * b = f[o+1][2g] on its swap), output ciphertext o2 holds 2k conv(x)_{2 o2}
+ * in its first slot row and 2k conv(x)_{2 o2 + 1} in its second.
+ * wa, wb: int32 [Co/2][2 n_in * 9] (index (h n_in + g) 9 + r, h = 1 for the
+ * swapped input); Co even; n_in <= 227; d_out [Co/2][2][L][N]. Workspace from
+ * hyena_simd_conv_packed_workspace; d_ct, d_work and d_out must not overlap.
+ * Errors: EINVAL, EHIP.
+ */
+int hyena_simd_conv_weights_packed(uint32_t Ci, uint32_t Co, const int8_t *f, uint32_t k,
+                                   int32_t *wa, int32_t *wb);
+size_t hyena_simd_conv_packed_workspace(const hyena_ctx *ctx, uint32_t n_in, uint32_t Co,
+                                        uint32_t log2_base);
+int hyena_simd_conv_packed(const hyena_ctx *ctx, const uint32_t *d_ct, uint32_t n_in, uint32_t frame_w,
+                           const int32_t *d_wa, const int32_t *d_wb, uint32_t Co, uint32_t kh,
+                           uint32_t log2_base, const uint32_t *d_rot_ksk, const uint32_t *d_swap_ksk,
+                           uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -93,6 +93,8 @@ _SIGS = {
     "hyena_cmult_accumulate": [_P, _P, _u32, _P, _u32, _P, _P],
     "hyena_simd_conv_weights": [_u32, _u32, _P, _u32, _P, _P],
     "hyena_simd_conv_cn2": [_P, _P, _u32, _u32, _P, _P, _u32, _u32, _u32, _P, _P, _P, _sz, _P, _P],
+    "hyena_simd_conv_weights_packed": [_u32, _u32, _P, _u32, _P, _P],
+    "hyena_simd_conv_packed": [_P, _P, _u32, _u32, _P, _P, _u32, _u32, _u32, _P, _P, _P, _sz, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -479,6 +481,40 @@ def hyena_simd_conv_cn2(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, log2_
                                      _dev_ptr(d_wb, "int32"), Co, kh, log2_base, _dev_ptr(d_rot_ksk, "int32"),
                                      _dev_ptr(d_swap_ksk, "int32"), _dev_ptr(d_work, "int32"), d_work.numel(),
                                      _dev_ptr(d_out, "int32"), _stream(stream)))
+
+
+def hyena_simd_conv_weights_packed(f: np.ndarray, k: int):
+    """Walsh CMult scalars (wa, wb) int32 [Co/2][Ci * 9] of the output-packed
+    c_n = 2 SIMD convolution from integer weights f [Co][Ci][3][3]."""
+    f = np.ascontiguousarray(f, dtype=np.int8)
+    Co, Ci = f.shape[0], f.shape[1]
+    wa = np.zeros((max(Co // 2, 1), Ci * 9), dtype=np.int32)
+    wb = np.zeros_like(wa)
+    _check(lib().hyena_simd_conv_weights_packed(Ci, Co, _np_ptr(f, np.int8), k, _np_ptr(wa, np.int32),
+                                                _np_ptr(wb, np.int32)))
+    return wa, wb
+
+
+def hyena_simd_conv_packed_workspace(ctx: Ctx, n_in: int, Co: int, log2_base: int) -> int:
+    L = lib()
+    L.hyena_simd_conv_packed_workspace.argtypes = [_P, _u32, _u32, _u32]
+    L.hyena_simd_conv_packed_workspace.restype = _sz
+    return int(L.hyena_simd_conv_packed_workspace(ctx.handle, n_in, Co, log2_base))
+
+
+def hyena_simd_conv_packed(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, log2_base: int, d_rot_ksk,
+                           d_swap_ksk, d_work, d_out, stream=None) -> None:
+    """Output-packed c_n = 2 SIMD convolution: d_out[o2] holds 2k conv(x)_{2 o2}
+    and 2k conv(x)_{2 o2 + 1} in its two slot rows."""
+    n_in = _polys(ctx, d_ct, 2 * ctx.L)
+    P2 = d_wa.shape[0]
+    if tuple(d_wa.shape) != (P2, 2 * n_in * 9) or tuple(d_wb.shape) != (P2, 2 * n_in * 9):
+        raise ValueError("d_wa and d_wb must be [Co/2][2 n_in * 9]")
+    _need(d_out, P2 * 2 * ctx.L * ctx.N, "d_out")
+    _check(lib().hyena_simd_conv_packed(ctx.handle, _dev_ptr(d_ct, "int32"), n_in, frame_w, _dev_ptr(d_wa, "int32"),
+                                        _dev_ptr(d_wb, "int32"), 2 * P2, kh, log2_base, _dev_ptr(d_rot_ksk, "int32"),
+                                        _dev_ptr(d_swap_ksk, "int32"), _dev_ptr(d_work, "int32"), d_work.numel(),
+                                        _dev_ptr(d_out, "int32"), _stream(stream)))
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -581,3 +581,92 @@ extern "C" int hyena_simd_conv_cn2(const hyena_ctx *c, const uint32_t *d_ct, uin
                        c->logN, c->L, c->lt);
     return slaunched(who);
 }
+
+extern "C" int hyena_simd_conv_weights_packed(uint32_t Ci, uint32_t Co, const int8_t *f, uint32_t k, int32_t *wa,
+                                              int32_t *wb) {
+    if (!f || !wa || !wb) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights_packed: NULL argument");
+    if (Ci == 0 || Ci % 2 || Co == 0 || Co % 2)
+        return set_error(HYENA_EINVAL, "hyena_simd_conv_weights_packed: Ci and Co must be even and positive");
+    if (k > 255) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights_packed: k above 255 (the scalars must stay within 2^16)");
+    const uint32_t G = Ci / 2, R = 2 * G * 9;
+    auto tap = [&](uint32_t o, uint32_t c, uint32_t r) { return (int32_t)f[((size_t)o * Ci + c) * 9 + r]; };
+    for (uint32_t o2 = 0; o2 < Co / 2; o2++)
+        for (uint32_t h = 0; h < 2; h++)          // h = 0: the input, h = 1: its row swap
+            for (uint32_t g = 0; g < G; g++)
+                for (uint32_t r = 0; r < 9; r++) {
+                    const uint32_t o = 2 * o2;
+                    const int32_t a = h ? tap(o, 2 * g + 1, r) : tap(o, 2 * g, r);
+                    const int32_t b = h ? tap(o + 1, 2 * g, r) : tap(o + 1, 2 * g + 1, r);
+                    const size_t i = (size_t)o2 * R + ((size_t)h * G + g) * 9 + r;
+                    wa[i] = (int32_t)k * (a + b);
+                    wb[i] = a - b;
+                }
+    return HYENA_OK;
+}
+
+extern "C" size_t hyena_simd_conv_packed_workspace(const hyena_ctx *c, uint32_t n_in, uint32_t Co,
+                                                   uint32_t log2_base) {
+    if (!c || log2_base < 1 || log2_base > 29) return 0;
+    const size_t LN = (size_t)c->L * c->N, CT = 2 * LN, D = (31 + log2_base - 1) / log2_base;
+    return 2 * (size_t)n_in * CT + 2 * (size_t)n_in * 9 * CT + 2 * (size_t)n_in * (c->L * D + 1) * LN +
+           3 * (size_t)(Co / 2) * CT;
+}
+
+extern "C" int hyena_simd_conv_packed(const hyena_ctx *c, const uint32_t *d_ct, uint32_t n_in, uint32_t frame_w,
+                                      const int32_t *d_wa, const int32_t *d_wb, uint32_t Co, uint32_t kh,
+                                      uint32_t log2_base, const uint32_t *d_rot_ksk, const uint32_t *d_swap_ksk,
+                                      uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream) {
+    static const char *who = "hyena_simd_conv_packed";
+    if (!c || !d_ct || !d_wa || !d_wb || !d_rot_ksk || !d_swap_ksk || !d_work || !d_out)
+        return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = device_ctx(c, who)) return rc;
+    if (n_in == 0 || Co == 0 || Co % 2) return set_error(HYENA_EINVAL, std::string(who) + ": need inputs and an even Co");
+    if (2 * n_in * 9 > 4096) return set_error(HYENA_EINVAL, std::string(who) + ": more than 227 input ciphertexts");
+    if (frame_w == 0 || frame_w >= c->N / 2) return set_error(HYENA_EINVAL, std::string(who) + ": frame width must be in [1, N/2)");
+    const size_t need = hyena_simd_conv_packed_workspace(c, n_in, Co, log2_base);
+    if (need == 0) return set_error(HYENA_EINVAL, std::string(who) + ": log2_base must be in [1, 29]");
+    if (work_words < need) return set_error(HYENA_EINVAL, std::string(who) + ": workspace too small");
+    const uint32_t P2 = Co / 2;
+    if ((size_t)P2 * 2 * c->L > (0x7fffffffull >> (c->logN - 8)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": too many outputs");
+    const size_t LN = (size_t)c->L * c->N, CT = 2 * LN;
+    if (soverlap(d_out, P2 * CT * 4, d_work, work_words * 4) || soverlap(d_out, P2 * CT * 4, d_ct, n_in * CT * 4) ||
+        soverlap(d_work, work_words * 4, d_ct, n_in * CT * 4))
+        return set_error(HYENA_EINVAL, std::string(who) + ": d_out, d_work and d_ct must not overlap");
+    uint32_t gs[9];
+    const uint32_t half = c->N / 2, mask = 2 * c->N - 1;
+    for (uint32_t di = 0; di < 3; di++)
+        for (uint32_t dj = 0; dj < 3; dj++) {
+            const int64_t off = ((int64_t)di - 1) * frame_w + ((int64_t)dj - 1);
+            const uint32_t e = (uint32_t)(((off % half) + half) % half);
+            uint32_t g = 1, b = 3;
+            for (uint32_t x = e; x; x >>= 1) {
+                if (x & 1) g = (g * b) & mask;
+                b = (b * b) & mask;
+            }
+            gs[di * 3 + dj] = g;
+        }
+    const size_t D = (31 + log2_base - 1) / log2_base;
+    uint32_t *X = d_work;                                      // [2 n_in] ciphertexts: inputs, then their row swaps
+    uint32_t *rots = X + 2 * (size_t)n_in * CT;                // [2 n_in][9]
+    uint32_t *hwork = rots + 2 * (size_t)n_in * 9 * CT;
+    uint32_t *A = hwork + 2 * (size_t)n_in * (c->L * D + 1) * LN;
+    uint32_t *B = A + P2 * CT, *PB = B + P2 * CT;
+    const hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(X, d_ct, (size_t)n_in * CT * 4, hipMemcpyDeviceToDevice, s));
+    // 1. the row swap of every input
+    const uint32_t swap = 2 * c->N - 1;
+    if (int rc = hyena_hrot_hoisted(c, d_ct, n_in, 1, &swap, log2_base, d_swap_ksk, hwork, X + (size_t)n_in * CT, stream))
+        return rc;
+    // 2. hoisted HRot of the inputs and their swaps by the nine offsets
+    if (int rc = hyena_hrot_hoisted(c, X, 2 * (size_t)n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
+    // 3. CMult + HAdd of the Walsh components, PMult of B by [k, -k], A + PMult(B)
+    if (int rc = hyena_cmult_accumulate(c, rots, 2 * n_in * 9, d_wa, P2, A, stream)) return rc;
+    if (int rc = hyena_cmult_accumulate(c, rots, 2 * n_in * 9, d_wb, P2, B, stream)) return rc;
+    const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
+    if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)P2, 2, exps, coefs, PB, stream)) return rc;   // [2 P2][L][N]
+    const uint32_t polys = P2 * 2 * c->L;
+    hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, PB, d_out, polys,
+                       c->logN, c->L, c->lt);
+    return slaunched(who);
+}

@@ -371,3 +371,43 @@ def test_simd_conv_cn1_from_library_calls(dev):
         slots = simd.decode(simd.decrypt_p(primes, p, s, got[o][None])[0], p, n).astype(np.int64)
         frame = slots[:n // 2].reshape(fh, fw)
         assert np.array_equal(frame[1:1 + H, 1:1 + W], y[o] % p), o
+
+
+def test_simd_conv_packed_entry_point(dev):
+    """hyena_simd_conv_packed (output channel packing) over two input
+    ciphertexts, 4 -> 4 channels: two output ciphertexts equal to the oracle's
+    bit for bit, each decrypting to two output channels."""
+    import torch
+    n, L, p, b = 2048, 3, 307201, 8
+    fh, fw, G, Co = 32, 32, 2, 4
+    say("hyena_simd_conv_packed n=2048, 2 inputs, 4 outputs")
+    ctx = ctx_for(n, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(n, 29)
+    h, k, kh = hy.hyena_simd_params(n, p, 61)
+    rng = np.random.default_rng(55)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(2 * G, H, W))
+    w = rng.integers(-8, 8, size=(Co, 2 * G, 3, 3))
+    msgs = np.stack([simd.encode(simd.frame_slots(x[2 * g:2 * g + 2], fh, fw), p, n) for g in range(G)])
+    ct = simd.encrypt_p(primes, p, s, msgs, 8)
+    gs = simd.conv_rotations(n, fw)
+    keys = np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 700 + i) for i, g in enumerate(gs)])
+    skey = hy.hyena_galois_keygen(ctx, s, 2 * n - 1, b, 799)
+    want = simd.simd_conv_cn2_packed(primes, ct, w, k, kh, fw, {g: keys[i] for i, g in enumerate(gs)}, skey, b)
+    dk, dsk = to_dev(keys), to_dev(skey)
+    hy.hyena_ksk_prepare(ctx, dk)
+    hy.hyena_ksk_prepare(ctx, dsk)
+    wa, wb = hy.hyena_simd_conv_weights_packed(w.astype(np.int8), k)
+    work = torch.empty(hy.hyena_simd_conv_packed_workspace(ctx, G, Co, b), dtype=torch.int32, device="cuda")
+    out = torch.empty(Co // 2 * 2 * L * n, dtype=torch.int32, device="cuda")
+    hy.hyena_simd_conv_packed(ctx, to_dev(ct), fw, torch.from_numpy(wa).cuda(), torch.from_numpy(wb).cuda(), kh, b,
+                              dk, dsk, work, out)
+    got = from_dev(out).reshape(Co // 2, 2, L, n)
+    assert np.array_equal(got, want)
+    y = orc.direct_conv(x, w, 3)
+    for o2 in range(Co // 2):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, got[o2][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[2 * o2 + row]) % p), (o2, row)

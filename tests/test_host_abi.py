@@ -242,3 +242,20 @@ def test_cmult_accumulate_refuses_null_output_even_without_inputs():
     null = ctypes.c_void_p(0)
     assert hy.lib().hyena_cmult_accumulate(ctx.handle, null, 0, null, 3, null, null) == hy.HYENA_EINVAL
     assert "NULL" in hy.lib().hyena_last_error().decode()
+
+
+def test_simd_conv_weights_packed():
+    rng = np.random.default_rng(2)
+    f = rng.integers(-8, 8, size=(4, 4, 3, 3)).astype(np.int8)
+    wa, wb = hy.hyena_simd_conv_weights_packed(f, 11)
+    G = 2
+    for o2 in range(2):
+        o = 2 * o2
+        for h in range(2):
+            for g in range(G):
+                a = f[o, 2 * g + h].reshape(9).astype(np.int32)
+                b = f[o + 1, 2 * g + 1 - h].reshape(9).astype(np.int32)
+                sl = slice((h * G + g) * 9, (h * G + g + 1) * 9)
+                assert np.array_equal(wa[o2, sl], 11 * (a + b)) and np.array_equal(wb[o2, sl], a - b)
+    with pytest.raises(hy.HyenaError):                    # odd output count
+        hy.hyena_simd_conv_weights_packed(f[:3], 11)
