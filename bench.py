@@ -818,8 +818,25 @@ def simd_conv_layer(hy, torch, best, k, kh):
 
     res["coefficient_path"] = {"ms": best(coeff), "input_ciphertexts": d.n_in, "output_ciphertexts": d.n_out,
                                "channels_per_ciphertext": d.ci}
+    # the decomposition base from the worst-case noise budget, with the [k, -k]
+    # plaintext and with the [1, -1] one, and the layer at the chosen base
+    h = hy.hyena_simd_params(N, 307201, 61)[0]
+    bk, mk = hy.hyena_simd_conv_choose_base(ctx, 307201, kh, wa, wb)
+    wa1, wb1 = hy.hyena_simd_conv_weights(rng.integers(-8, 8, size=(Co, Ci, 3, 3)).astype(np.int8), 1)
+    b1, m1 = hy.hyena_simd_conv_choose_base(ctx, 307201, h, wa1, wb1)
+    keys_c = torch.from_numpy(np.stack([hy.hyena_galois_keygen(ctx, sk, gg, bk, 20 + i)
+                                        for i, gg in enumerate(gs)]).view(np.int32)).to(dev)
+    skey_c = torch.from_numpy(hy.hyena_galois_keygen(ctx, sk, 2 * N - 1, bk, 98).view(np.int32)).to(dev)
+    hy.hyena_ksk_prepare(ctx, keys_c)
+    hy.hyena_ksk_prepare(ctx, skey_c)
+    work_c = torch.empty(hy.hyena_simd_conv_workspace(ctx, n_in, Co, bk), **i32)
+    res["noise_chosen_base"] = {
+        "log2_base_k_plaintext": bk, "margin_bits": mk, "digits_per_limb": hy.n_digits(bk),
+        "log2_base_pm1_plaintext": b1, "digits_per_limb_pm1": hy.n_digits(b1),
+        "ms": best(lambda: hy.hyena_simd_conv_cn2(ctx, ct, fw, d_wa, d_wb, kh, bk, keys_c, skey_c, work_c, out))}
     hy.hyena_destroy(ctx)
-    log(f"simd conv layer {ms:.3f} ms, output-packed {res['output_packed']['ms']:.3f} ms "
+    log(f"simd conv layer {ms:.3f} ms at base 2^{b}, {res['noise_chosen_base']['ms']:.3f} ms at the chosen 2^{bk}, "
+        f"output-packed {res['output_packed']['ms']:.3f} ms "
         f"(coefficient path {res['coefficient_path']['ms']:.3f} ms)")
     return res
 

@@ -482,6 +482,23 @@ int hyena_simd_conv_packed(const hyena_ctx *ctx, const uint32_t *d_ct, uint32_t 
                            uint32_t *d_work, size_t work_words, uint32_t *d_out, hyena_stream_t stream);
 
 /*
+ * Decomposition base from the noise budget ("Optimal Parameter Selection":
+ * the noise the [k, -k] plaintext saves allows a larger base for HRot, hence
+ * fewer digits and less computation). Returns in *log2_base the largest
+ * b <= 29 whose worst-case output noise of hyena_simd_conv_cn2 (packed = 0) or
+ * hyena_simd_conv_packed (packed = 1) with weights wa, wb (host int32 [O][R],
+ * as passed to those calls) and PMult coefficient kh stays below
+ * q / (2p) - p, and in *margin_bits (may be NULL) log2 of that limit over the
+ * bound. The bound: fresh and key errors at most 32; L D N (2^b - 1) 32 per
+ * key switching; q mod p per automorphism, per unit of sum |w| of a CMult and
+ * HAdd, per HAdd and 2 kh per PMult; noise times sum |w| and times 2 kh.
+ * Errors: EINVAL, ENOISE (no base fits).
+ */
+int hyena_simd_conv_choose_base(const hyena_ctx *ctx, uint32_t p, uint32_t kh, const int32_t *wa,
+                                const int32_t *wb, uint32_t O, uint32_t R, int packed,
+                                uint32_t *log2_base, double *margin_bits);
+
+/*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
  * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by

@@ -95,6 +95,7 @@ _SIGS = {
     "hyena_simd_conv_cn2": [_P, _P, _u32, _u32, _P, _P, _u32, _u32, _u32, _P, _P, _P, _sz, _P, _P],
     "hyena_simd_conv_weights_packed": [_u32, _u32, _P, _u32, _P, _P],
     "hyena_simd_conv_packed": [_P, _P, _u32, _u32, _P, _P, _u32, _u32, _u32, _P, _P, _P, _sz, _P, _P],
+    "hyena_simd_conv_choose_base": [_P, _u32, _u32, _P, _P, _u32, _u32, ctypes.c_int, _P, _P],
     "hyena_wht_pack": [_P, _u32, _P, _P, _sz, _P],
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
@@ -515,6 +516,18 @@ def hyena_simd_conv_packed(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, lo
                                         _dev_ptr(d_wb, "int32"), 2 * P2, kh, log2_base, _dev_ptr(d_rot_ksk, "int32"),
                                         _dev_ptr(d_swap_ksk, "int32"), _dev_ptr(d_work, "int32"), d_work.numel(),
                                         _dev_ptr(d_out, "int32"), _stream(stream)))
+
+
+def hyena_simd_conv_choose_base(ctx: Ctx, p: int, kh: int, wa: np.ndarray, wb: np.ndarray, packed: bool = False):
+    """(log2 of the largest decomposition base the worst-case noise allows, margin in bits)."""
+    wa = np.ascontiguousarray(wa, dtype=np.int32)
+    wb = np.ascontiguousarray(wb, dtype=np.int32)
+    if wa.shape != wb.shape or wa.ndim != 2:
+        raise ValueError("wa and wb must be [O][R] of the same shape")
+    b, m = ctypes.c_uint32(), ctypes.c_double()
+    _check(lib().hyena_simd_conv_choose_base(ctx.handle, p, kh, _np_ptr(wa, np.int32), _np_ptr(wb, np.int32),
+                                             wa.shape[0], wa.shape[1], int(packed), ctypes.byref(b), ctypes.byref(m)))
+    return b.value, m.value
 
 
 def hyena_wht_pack(ctx: Ctx, c_n: int, d_in, d_out, G: int, stream=None) -> None:

@@ -8,6 +8,8 @@
 // the value at zeta^(-3^s mod 2n), zeta the least primitive 2n-th root of
 // unity mod p (the context's psi). X -> X^3 rotates both rows by one slot,
 // X -> X^(2n-1) swaps them.
+#include <cmath>
+
 #include "internal.h"
 
 namespace {
@@ -669,4 +671,54 @@ extern "C" int hyena_simd_conv_packed(const hyena_ctx *c, const uint32_t *d_ct, 
     hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, PB, d_out, polys,
                        c->logN, c->L, c->lt);
     return slaunched(who);
+}
+
+// Worst-case noise (infinity norm of v - Delta m over the coefficients) of the
+// c_n = 2 convolution's output for base 2^b, as a double; fresh noise and key
+// errors at most B = 32, q mod p < p:
+//   key switching KS = L D N (2^b - 1) B per HRot; an automorphism negates
+//   coefficients, which adds q mod p once; a CMult-and-HAdd by scalars w adds
+//   (sum |w|) times the input noise plus (q mod p) per unit of sum |w| (the
+//   carries of the plaintext sum past p); PMult by kh (X^(N/4) + X^(3N/4))
+//   multiplies noise by 2 kh and adds 2 kh (q mod p); HAdd adds q mod p.
+static double simd_conv_noise(const hyena_ctx *c, double p, double kh, double sa, double sb, uint32_t b, bool packed) {
+    const double B = 32.0, D = (31 + b - 1) / b;
+    const double KS = (double)c->L * D * c->N * (std::ldexp(1.0, (int)b) - 1.0) * B;
+    const double in = packed ? B + KS + p : B;               // packed: half the inputs went through the row swap
+    const double rot = in + KS + p;
+    const double A = sa * rot + p * sa, Bn = sb * rot + p * sb;
+    const double PB = 2 * kh * Bn + 2 * kh * p;
+    const double Z = A + PB + p;
+    return packed ? Z : Z + (Z + KS + p) + p;                 // unpacked: Z + HRot(Z, row swap)
+}
+
+extern "C" int hyena_simd_conv_choose_base(const hyena_ctx *c, uint32_t p, uint32_t kh, const int32_t *wa,
+                                           const int32_t *wb, uint32_t O, uint32_t R, int packed,
+                                           uint32_t *log2_base, double *margin_bits) {
+    static const char *who = "hyena_simd_conv_choose_base";
+    if (!c || !wa || !wb || !log2_base || !O || !R) return set_error(HYENA_EINVAL, std::string(who) + ": NULL or empty argument");
+    if (p < 3) return set_error(HYENA_EINVAL, std::string(who) + ": p must be an odd prime");
+    double sa = 0, sb = 0;   // the largest sum |w| over the outputs
+    for (uint32_t o = 0; o < O; o++) {
+        double a = 0, b = 0;
+        for (uint32_t r = 0; r < R; r++) {
+            a += std::fabs((double)wa[(size_t)o * R + r]);
+            b += std::fabs((double)wb[(size_t)o * R + r]);
+        }
+        sa = std::max(sa, a);
+        sb = std::max(sb, b);
+    }
+    double logq = 0;
+    for (uint32_t q : c->q) logq += std::log2((double)q);
+    // decryption is exact while |noise| < q / (2p) - p (the rounding also absorbs (q mod p) m / q < p)
+    const double limit = std::exp2(logq - std::log2(2.0 * p)) - p;
+    for (uint32_t b = 29; b >= 1; b--) {
+        const double bound = simd_conv_noise(c, p, kh, sa, sb, b, packed != 0);
+        if (bound < limit) {
+            *log2_base = b;
+            if (margin_bits) *margin_bits = std::log2(limit) - std::log2(bound);
+            return HYENA_OK;
+        }
+    }
+    return set_error(HYENA_ENOISE, std::string(who) + ": no base keeps the worst-case noise below q / 2p");
 }

@@ -303,3 +303,58 @@ def test_simd_conv_cn2_packed_outputs_two_channels_per_ciphertext(G):
         for row in range(2):
             frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[2 * o2 + row]) % p), (o2, row)
+
+
+@pytest.mark.parametrize("packed", [False, True])
+def test_choose_base_bounds_the_measured_noise(packed):
+    """hyena_simd_conv_choose_base (host): the base it returns keeps the
+    worst-case bound below q/(2p) - p, the oracle's convolution at that base
+    decrypts exactly and its measured output noise |v - Delta m| is within the
+    bound; the [k, -k] plaintext never allows a smaller base than [1, -1]."""
+    import math as _m
+    import paper_2311_12519_amd as hy
+    n, L, p = 1024, 3, 12289
+    fh, fw, Co = 16, 32, 2
+    primes = orc.ntt_primes(n, L, 30)
+    ctx = hy.hyena_create(n, L, primes=primes, flags=hy.HYENA_HOST_ONLY | hy.HYENA_ALLOW_INSECURE)
+    h = simd.h_pn(n, p)
+    k, kh = simd.best_k(h, p, 61)
+    rng = np.random.default_rng(70 + packed)
+    x = rng.integers(-8, 8, size=(2, fh - 2, fw - 2))
+    w = rng.integers(-8, 8, size=(Co, 2, 3, 3))
+    W = hy.hyena_simd_conv_weights_packed if packed else hy.hyena_simd_conv_weights
+    wa, wb = W(w.astype(np.int8), k)
+    b, margin = hy.hyena_simd_conv_choose_base(ctx, p, kh, wa, wb, packed)
+    wa1, wb1 = W(w.astype(np.int8), 1)
+    b1, _ = hy.hyena_simd_conv_choose_base(ctx, p, h, wa1, wb1, packed)
+    assert b >= b1
+    q = _m.prod(primes)
+    bound = (q // (2 * p) - p) / 2 ** margin
+    s = orc.keygen(n, 91)
+    ct = simd.encrypt_p(primes, p, s, simd.encode(simd.frame_slots(x, fh, fw), p, n)[None], 92)
+    gs = simd.conv_rotations(n, fw)
+    rk = {g: simd.galois_keygen(primes, s, g, b, 93 + i) for i, g in enumerate(gs)}
+    swk = simd.galois_keygen(primes, s, 2 * n - 1, b, 99)
+    conv = simd.simd_conv_cn2_packed if packed else simd.simd_conv_cn2
+    out = conv(primes, ct, w, k, kh, fw, rk, swk, b)
+    delta = q // p
+    for o in range(out.shape[0]):
+        m = simd.decrypt_p(primes, p, s, out[o][None])[0]
+        v = orc.decrypt_phase(primes, s, out[o])
+        noise = max(abs(((vi - delta * int(mi)) + q // 2) % q - q // 2) for vi, mi in zip(v, m))
+        assert noise <= bound, (o, _m.log2(noise), _m.log2(bound))
+
+
+def test_choose_base_k_trick_gains_four_bits_on_a_64_channel_layer():
+    """On a 30x30 64 -> 64 layer (n = 2048, three primes below 2^30, the
+    paper's p = 307201) the [k, -k] plaintext (kh = 5125) allows a base 2^4
+    larger than the [1, -1] plaintext (h = 84248): the noise saving of the
+    "Optimal Parameter Selection" section turned into a larger base."""
+    import paper_2311_12519_amd as hy
+    ctx = hy.hyena_create(2048, 3, flags=hy.HYENA_PRIMES_30BIT | hy.HYENA_ALLOW_INSECURE | hy.HYENA_HOST_ONLY)
+    h, k, kh = hy.hyena_simd_params(2048, 307201, 61)
+    f = np.random.default_rng(9).integers(-8, 8, size=(64, 64, 3, 3)).astype(np.int8)
+    for packed, W in ((False, hy.hyena_simd_conv_weights), (True, hy.hyena_simd_conv_weights_packed)):
+        b, _ = hy.hyena_simd_conv_choose_base(ctx, 307201, kh, *W(f, k), packed)
+        b1, _ = hy.hyena_simd_conv_choose_base(ctx, 307201, h, *W(f, 1), packed)
+        assert b - b1 == 4, (packed, b, b1)
