@@ -277,6 +277,38 @@ __global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *in, cons
     }
 }
 
+// Two weight sets over the same inputs (the A and B Walsh components of the
+// SIMD convolution): every input word is read once for both sums.
+__device__ __forceinline__ uint32_t lazy_result(int64_t acc, const LimbConst &lc) {
+    const uint64_t t = (uint64_t)(acc + ((int64_t)lc.q << 30));          // in [0, q 2^31)
+    const uint32_t m = (uint32_t)t * lc.qinv_neg;
+    const uint32_t y = scsub((uint32_t)(((uint64_t)m * lc.q + t) >> 32), lc.q);   // t 2^-32 mod q
+    return smont(y, lc.r64, lc.q, lc.qinv_neg);                                    // t mod q
+}
+
+__global__ void __launch_bounds__(STH) cmult_acc2_kernel(const uint32_t *in, const int32_t *WA, const int32_t *WB,
+                                                         uint32_t *outA, uint32_t *outB, uint32_t R, uint32_t O,
+                                                         uint32_t logN, uint32_t L, LimbTable lt) {
+    const size_t PLN = (size_t)2 * L << logN;
+    const uint32_t chunks = (uint32_t)(((size_t)O * 2 * L) << (logN - 8));   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t op = c >> (logN - 8);
+        const uint32_t o = op / (2 * L), limb = op % L;
+        const size_t idx = ((size_t)(op % (2 * L)) << logN) + ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const int32_t *wa = WA + (size_t)o * R, *wb = WB + (size_t)o * R;
+        int64_t a = 0, b = 0;
+#pragma unroll 8
+        for (uint32_t r = 0; r < R; r++) {
+            const int64_t x = (int64_t)in[(size_t)r * PLN + idx];
+            a += (int64_t)wa[r] * x;
+            b += (int64_t)wb[r] * x;
+        }
+        const LimbConst &lc = lt.c[limb];
+        outA[(size_t)o * PLN + idx] = lazy_result(a, lc);
+        outB[(size_t)o * PLN + idx] = lazy_result(b, lc);
+    }
+}
+
 // HAdd: out = a + b mod q_i for ciphertext arrays [..][L][N] of `polys` limb-polynomials
 __global__ void __launch_bounds__(STH) hadd_kernel(const uint32_t *a, const uint32_t *b, uint32_t *out,
                                                    uint32_t polys, uint32_t logN, uint32_t L, LimbTable lt) {
@@ -502,6 +534,20 @@ extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, 
     return slaunched(who);
 }
 
+// A = sum wa in, B = sum wb in over R ciphertexts (the checks of hyena_cmult_accumulate)
+static int cmult_accumulate2(const hyena_ctx *c, const uint32_t *d_in, uint32_t R, const int32_t *d_wa,
+                             const int32_t *d_wb, uint32_t O, uint32_t *A, uint32_t *B, hipStream_t s) {
+    static const char *who = "hyena_simd_conv";
+    if (R > 4096) return set_error(HYENA_EINVAL, std::string(who) + ": more than 4096 rotations");
+    for (uint32_t q : c->q)
+        if (q <= (1u << 29)) return set_error(HYENA_EINVAL, std::string(who) + ": primes must exceed 2^29");
+    if ((size_t)O * 2 * c->L > (0x7fffffffull >> (c->logN - 8)))
+        return set_error(HYENA_EINVAL, std::string(who) + ": too many outputs");
+    hipLaunchKernelGGL(cmult_acc2_kernel, dim3(sgrid(((size_t)O * 2 * c->L) << (c->logN - 8))), dim3(STH), 0, s, d_in,
+                       d_wa, d_wb, A, B, R, O, c->logN, c->L, c->lt);
+    return slaunched(who);
+}
+
 extern "C" int hyena_simd_conv_weights(uint32_t Ci, uint32_t Co, const int8_t *f, uint32_t k, int32_t *wa,
                                        int32_t *wb) {
     if (!f || !wa || !wb) return set_error(HYENA_EINVAL, "hyena_simd_conv_weights: NULL argument");
@@ -568,8 +614,7 @@ extern "C" int hyena_simd_conv_cn2(const hyena_ctx *c, const uint32_t *d_ct, uin
     // 1. hoisted HRot of every input by the nine offsets
     if (int rc = hyena_hrot_hoisted(c, d_ct, n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
     // 2. CMult + HAdd of the Walsh components over every rotation
-    if (int rc = hyena_cmult_accumulate(c, rots, n_in * 9, d_wa, Co, A, stream)) return rc;
-    if (int rc = hyena_cmult_accumulate(c, rots, n_in * 9, d_wb, Co, B, stream)) return rc;
+    if (int rc = cmult_accumulate2(c, rots, n_in * 9, d_wa, d_wb, Co, A, B, s)) return rc;
     // 3. PMult of B by the [k, -k] plaintext, added to A (Z into B's buffer)
     const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
     if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)Co, 2, exps, coefs, PB, stream)) return rc;   // [2 Co][L][N]
@@ -663,8 +708,7 @@ extern "C" int hyena_simd_conv_packed(const hyena_ctx *c, const uint32_t *d_ct, 
     // 2. hoisted HRot of the inputs and their swaps by the nine offsets
     if (int rc = hyena_hrot_hoisted(c, X, 2 * (size_t)n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
     // 3. CMult + HAdd of the Walsh components, PMult of B by [k, -k], A + PMult(B)
-    if (int rc = hyena_cmult_accumulate(c, rots, 2 * n_in * 9, d_wa, P2, A, stream)) return rc;
-    if (int rc = hyena_cmult_accumulate(c, rots, 2 * n_in * 9, d_wb, P2, B, stream)) return rc;
+    if (int rc = cmult_accumulate2(c, rots, 2 * n_in * 9, d_wa, d_wb, P2, A, B, s)) return rc;
     const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
     if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)P2, 2, exps, coefs, PB, stream)) return rc;   // [2 P2][L][N]
     const uint32_t polys = P2 * 2 * c->L;
