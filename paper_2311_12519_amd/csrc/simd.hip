@@ -309,6 +309,29 @@ __global__ void __launch_bounds__(STH) cmult_acc2_kernel(const uint32_t *in, con
     }
 }
 
+// The [k, -k] plaintext kh (X^(N/4) + X^(3N/4)) at the NTT's evaluation point
+// psi^e (e = 2 brv(s) + 1 odd) is kh (w^e + w^(3e)) with w = psi^(N/4) of order
+// 8, so it takes four values per limb, chosen by e mod 8: in the NTT domain
+// PMult by it is a product by one of four constants.
+struct PmConst {
+    uint32_t c[HYENA_MAX_LIMBS][4];   // kh (w^e + w^3e) 2^32 mod q_i for e = 1, 3, 5, 7
+};
+
+// Z = A + B . NTT(w_pm) (NTT domain), ciphertext arrays [..][L][N]
+__global__ void __launch_bounds__(STH) pm_madd_ntt_kernel(const uint32_t *A, const uint32_t *B, uint32_t *Z,
+                                                          uint32_t polys, uint32_t logN, uint32_t L, LimbTable lt,
+                                                          PmConst pc) {
+    const uint32_t chunks = polys << (logN - 8);   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t limb = (c >> (logN - 8)) % L;
+        const LimbConst &lc = lt.c[limb];
+        const uint32_t s = ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
+        const uint32_t e = 2 * brev(s, logN) + 1;
+        const size_t i = ((size_t)c << 8) + threadIdx.x;
+        Z[i] = scsub(A[i] + smont(B[i], pc.c[limb][(e >> 1) & 3], lc.q, lc.qinv_neg), lc.q);
+    }
+}
+
 // HAdd: out = a + b mod q_i for ciphertext arrays [..][L][N] of `polys` limb-polynomials
 __global__ void __launch_bounds__(STH) hadd_kernel(const uint32_t *a, const uint32_t *b, uint32_t *out,
                                                    uint32_t polys, uint32_t logN, uint32_t L, LimbTable lt) {
@@ -463,9 +486,10 @@ extern "C" int hyena_ksk_prepare(const hyena_ctx *c, uint32_t *d_ksk, size_t n_p
     return slaunched(who);
 }
 
-extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint32_t n_rot,
-                                  const uint32_t *gs, uint32_t log2_base, const uint32_t *d_ksk, uint32_t *d_work,
-                                  uint32_t *d_out, hyena_stream_t stream) {
+// intt_out = false leaves the rotated ciphertexts in the NTT domain
+static int hrot_impl(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint32_t n_rot, const uint32_t *gs,
+                     uint32_t log2_base, const uint32_t *d_ksk, uint32_t *d_work, uint32_t *d_out,
+                     hyena_stream_t stream, bool intt_out) {
     static const char *who = "hyena_hrot_hoisted";
     if (!c || (n_ct && n_rot && (!d_ct || !gs || !d_ksk || !d_work || !d_out)))
         return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
@@ -511,7 +535,27 @@ extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size
     }
 #undef HY_KS
     if (int rc = slaunched(who)) return rc;
-    return launch_ntt(c, d_out, n_ct * n_rot * 2, true, s);
+    return intt_out ? launch_ntt(c, d_out, n_ct * n_rot * 2, true, s) : HYENA_OK;
+}
+
+extern "C" int hyena_hrot_hoisted(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint32_t n_rot,
+                                  const uint32_t *gs, uint32_t log2_base, const uint32_t *d_ksk, uint32_t *d_work,
+                                  uint32_t *d_out, hyena_stream_t stream) {
+    return hrot_impl(c, d_ct, n_ct, n_rot, gs, log2_base, d_ksk, d_work, d_out, stream, true);
+}
+
+// constants of the [k, -k] plaintext in the NTT domain
+static PmConst pm_constants(const hyena_ctx *c, uint32_t kh) {
+    PmConst pc{};
+    for (uint32_t i = 0; i < c->L; i++) {
+        const uint32_t q = c->q[i], w = h_powmod(c->psi[i], c->N / 4, q);
+        for (uint32_t j = 0; j < 4; j++) {
+            const uint32_t e = 2 * j + 1;
+            const uint64_t v = ((uint64_t)h_powmod(w, e, q) + h_powmod(w, 3 * e, q)) % q;
+            pc.c[i][j] = to_montgomery(h_mulmod((uint32_t)v, kh % q, q), q);
+        }
+    }
+    return pc;
 }
 
 extern "C" int hyena_cmult_accumulate(const hyena_ctx *c, const uint32_t *d_in, uint32_t R, const int32_t *d_w,
@@ -611,16 +655,15 @@ extern "C" int hyena_simd_conv_cn2(const hyena_ctx *c, const uint32_t *d_ct, uin
     uint32_t *B = A + Co * CT, *PB = B + Co * CT;
     const hipStream_t s = (hipStream_t)stream;
     const uint32_t polys = Co * 2 * c->L;
-    // 1. hoisted HRot of every input by the nine offsets
-    if (int rc = hyena_hrot_hoisted(c, d_ct, n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
-    // 2. CMult + HAdd of the Walsh components over every rotation
+    // 1. hoisted HRot of every input by the nine offsets, left in the NTT domain
+    if (int rc = hrot_impl(c, d_ct, n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream, false)) return rc;
+    // 2. CMult + HAdd of the Walsh components over every rotation (linear: either domain)
     if (int rc = cmult_accumulate2(c, rots, n_in * 9, d_wa, d_wb, Co, A, B, s)) return rc;
-    // 3. PMult of B by the [k, -k] plaintext, added to A (Z into B's buffer)
-    const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
-    if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)Co, 2, exps, coefs, PB, stream)) return rc;   // [2 Co][L][N]
-    hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, PB, B, polys,
-                       c->logN, c->L, c->lt);
+    // 3. Z = A + PMult(B, [k, -k]): a product by one of four constants per slot; then Z's inverse NTT
+    hipLaunchKernelGGL(pm_madd_ntt_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, B, B,
+                       polys, c->logN, c->L, c->lt, pm_constants(c, kh));
     if (int rc = slaunched(who)) return rc;
+    if (int rc = launch_ntt(c, B, 2 * (size_t)Co, true, s)) return rc;
     // 4. row-swap HRot (into PB's buffer) and HAdd
     const uint32_t swap = 2 * c->N - 1;
     if (int rc = hyena_hrot_hoisted(c, B, Co, 1, &swap, log2_base, d_swap_ksk, hwork, PB, stream)) return rc;
@@ -656,7 +699,7 @@ extern "C" size_t hyena_simd_conv_packed_workspace(const hyena_ctx *c, uint32_t 
     if (!c || log2_base < 1 || log2_base > 29) return 0;
     const size_t LN = (size_t)c->L * c->N, CT = 2 * LN, D = (31 + log2_base - 1) / log2_base;
     return 2 * (size_t)n_in * CT + 2 * (size_t)n_in * 9 * CT + 2 * (size_t)n_in * (c->L * D + 1) * LN +
-           3 * (size_t)(Co / 2) * CT;
+           2 * (size_t)(Co / 2) * CT;
 }
 
 extern "C" int hyena_simd_conv_packed(const hyena_ctx *c, const uint32_t *d_ct, uint32_t n_in, uint32_t frame_w,
@@ -698,23 +741,22 @@ extern "C" int hyena_simd_conv_packed(const hyena_ctx *c, const uint32_t *d_ct, 
     uint32_t *rots = X + 2 * (size_t)n_in * CT;                // [2 n_in][9]
     uint32_t *hwork = rots + 2 * (size_t)n_in * 9 * CT;
     uint32_t *A = hwork + 2 * (size_t)n_in * (c->L * D + 1) * LN;
-    uint32_t *B = A + P2 * CT, *PB = B + P2 * CT;
+    uint32_t *B = A + P2 * CT;
     const hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(X, d_ct, (size_t)n_in * CT * 4, hipMemcpyDeviceToDevice, s));
     // 1. the row swap of every input
     const uint32_t swap = 2 * c->N - 1;
     if (int rc = hyena_hrot_hoisted(c, d_ct, n_in, 1, &swap, log2_base, d_swap_ksk, hwork, X + (size_t)n_in * CT, stream))
         return rc;
-    // 2. hoisted HRot of the inputs and their swaps by the nine offsets
-    if (int rc = hyena_hrot_hoisted(c, X, 2 * (size_t)n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream)) return rc;
-    // 3. CMult + HAdd of the Walsh components, PMult of B by [k, -k], A + PMult(B)
+    // 2. hoisted HRot of the inputs and their swaps by the nine offsets, left in the NTT domain
+    if (int rc = hrot_impl(c, X, 2 * (size_t)n_in, 9, gs, log2_base, d_rot_ksk, hwork, rots, stream, false)) return rc;
+    // 3. CMult + HAdd of the Walsh components; out = A + PMult(B, [k, -k]) pointwise; its inverse NTT
     if (int rc = cmult_accumulate2(c, rots, 2 * n_in * 9, d_wa, d_wb, P2, A, B, s)) return rc;
-    const uint32_t exps[2] = {c->N / 4, 3 * c->N / 4}, coefs[2] = {kh, kh};
-    if (int rc = hyena_pmult_sparse(c, B, 2 * (size_t)P2, 2, exps, coefs, PB, stream)) return rc;   // [2 P2][L][N]
     const uint32_t polys = P2 * 2 * c->L;
-    hipLaunchKernelGGL(hadd_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, PB, d_out, polys,
-                       c->logN, c->L, c->lt);
-    return slaunched(who);
+    hipLaunchKernelGGL(pm_madd_ntt_kernel, dim3(sgrid((size_t)polys << (c->logN - 8))), dim3(STH), 0, s, A, B, d_out,
+                       polys, c->logN, c->L, c->lt, pm_constants(c, kh));
+    if (int rc = slaunched(who)) return rc;
+    return launch_ntt(c, d_out, 2 * (size_t)P2, true, s);
 }
 
 // Worst-case noise (infinity norm of v - Delta m over the coefficients) of the
