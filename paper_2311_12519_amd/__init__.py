@@ -120,6 +120,10 @@ def lib() -> ctypes.CDLL:
             f.restype = None if name == "hyena_destroy" else ctypes.c_int
         L.hyena_last_error.restype = ctypes.c_char_p
         L.hyena_last_error.argtypes = []
+        for name in ("hyena_simd_conv_workspace", "hyena_simd_conv_packed_workspace"):   # size_t results
+            f = getattr(L, name)
+            f.argtypes = [_P, _u32, _u32, _u32]
+            f.restype = _sz
         _register_extra(L)
         _lib = L
     return _lib
@@ -464,10 +468,8 @@ def hyena_simd_conv_weights(f: np.ndarray, k: int):
 
 
 def hyena_simd_conv_workspace(ctx: Ctx, n_in: int, Co: int, log2_base: int) -> int:
-    L = lib()
-    L.hyena_simd_conv_workspace.argtypes = [_P, _u32, _u32, _u32]
-    L.hyena_simd_conv_workspace.restype = _sz
-    return int(L.hyena_simd_conv_workspace(ctx.handle, n_in, Co, log2_base))
+    """uint32 words of workspace hyena_simd_conv_cn2 needs (0 for a bad base)."""
+    return int(lib().hyena_simd_conv_workspace(ctx.handle, n_in, Co, log2_base))
 
 
 def hyena_simd_conv_cn2(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, log2_base: int, d_rot_ksk, d_swap_ksk,
@@ -497,10 +499,8 @@ def hyena_simd_conv_weights_packed(f: np.ndarray, k: int):
 
 
 def hyena_simd_conv_packed_workspace(ctx: Ctx, n_in: int, Co: int, log2_base: int) -> int:
-    L = lib()
-    L.hyena_simd_conv_packed_workspace.argtypes = [_P, _u32, _u32, _u32]
-    L.hyena_simd_conv_packed_workspace.restype = _sz
-    return int(L.hyena_simd_conv_packed_workspace(ctx.handle, n_in, Co, log2_base))
+    """uint32 words of workspace hyena_simd_conv_packed needs (0 for a bad base)."""
+    return int(lib().hyena_simd_conv_packed_workspace(ctx.handle, n_in, Co, log2_base))
 
 
 def hyena_simd_conv_packed(ctx: Ctx, d_ct, frame_w: int, d_wa, d_wb, kh: int, log2_base: int, d_rot_ksk,
