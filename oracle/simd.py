@@ -23,6 +23,12 @@ What it computes, in the paper's terms:
   one plaintext polynomial per kernel element.
 * Galois automorphisms a(X) -> a(X^g) in R_q (the map behind HRot, "Homomorphic
   Operations in BFV") and PMult by a plaintext in R_q (a negacyclic product).
+* HRot with a decomposition base 2^b and hoisting (key generation and key
+  switching, RNS-BV digits of each limb's residues).
+* BFV with a prime plaintext modulus p, and CMult + HAdd by integer scalars.
+* The convolution with c_n = 2 channels per ciphertext ("Enabling Output
+  Channel Packing", Eq. (hadamard2), with the [k, -k] plaintext), with and
+  without output channel packing, over any number of input ciphertexts.
 
 Readings where the paper is silent: slot s < n/2 holds the value at
 zeta^(3^s mod 2n) and slot n/2 + s the value at zeta^(-3^s mod 2n) (the
@@ -30,7 +36,9 @@ generator-3 two-row layout of the batch encoder used with the paper's
 parameters; with the least primitive root it gives the paper's
 h_{2048,307201} = 84248); plaintext coefficients enter PMult as integers in
 [0, p), the representation the paper's "minimise k h mod p" criterion
-measures.
+measures; the 1/2 of Eq. (hadamard2) is left out (every output carries the
+factor 2, as it carries k); one input channel per slot row, in a
+zero-bordered frame of power-of-two width, kernel offsets as row rotations.
 """
 from __future__ import annotations
 
