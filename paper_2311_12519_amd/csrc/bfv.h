@@ -29,3 +29,9 @@ void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B);   // decry
 // otherwise they must not overlap. dst and mul 16-byte aligned (ntt.hip).
 int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
                        const uint32_t *mul, hipStream_t s);
+
+// Inverse NTT of P polynomials a [P][L][N] in place, adding as it stores
+// limb i of polynomial p at add_src + p add_stride + i N (mod q_i; canonical
+// inputs); add_src must not overlap a; a 16-byte aligned (ntt.hip).
+int launch_ntt_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+                       hipStream_t s);

@@ -137,8 +137,8 @@ __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const
     }
 }
 
-// msg <- round(t [c0 + work]_q / q) mod t, centered; the host decryption's integer steps
-__global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *ct, const uint32_t *work, int32_t *msg,
+// msg <- round(t v / q) mod t, centered, v = work = [c0 + c1 s]_q; the host decryption's integer steps
+__global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *work, int32_t *msg,
                                                              size_t n, uint32_t logN, uint32_t L, uint32_t log2_t,
                                                              LimbTable lt, ClientConst cc) {
     const uint32_t cpl = 1u << (logN - 8);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *ct,
         for (uint32_t i = 0; i < L; i++) {
             const uint32_t q = lt.c[i].q;
             const size_t r = ((size_t)i << logN) + j;
-            const uint64_t v = caddmod(work[m * LN + r], ct[m * 2 * LN + r], q);
+            const uint64_t v = work[m * LN + r];                 // c0 + c1 s mod q_i
             ipart += v * cc.A[i];
             uint64_t rem, unused;
             ipart += cdivmod(v * cc.B[i], q, cc.rcp[i], rem);        // v B_i < 2^62
@@ -266,9 +266,10 @@ extern "C" int hyena_decrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     // c1 s = INTT(NTT(c1) . NTT(s)): the forward transform reads c1 of every ciphertext in place
     // and writes the product into the workspace
     if (int rc = launch_ntt_fwd_mul(c, d_ct + LN, 2 * LN, n, d_work, d_s_hat, s)) return rc;
-    if (int rc = launch_ntt(c, d_work, n, true, s)) return rc;
+    // v = c0 + c1 s: the inverse transform adds c0 as it stores
+    if (int rc = launch_ntt_inv_add(c, d_work, n, d_ct, 2 * LN, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
-    hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_work, d_msg, n, c->logN,
+    hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_work, d_msg, n, c->logN,
                        L, c->log2_t, c->lt, cc);
     return launched(who);
 }

@@ -404,6 +404,42 @@ hipError_t launch_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_st
     return hipGetLastError();
 }
 
+// Inverse transform that adds another array as it stores: block p (limb-
+// polynomial p of a [P][L][N] array a) stores INTT(a_p) + add mod q, with add
+// limb p mod L of polynomial p / L at add_src + (p / L) add_stride (decryption
+// adds c0 to c1 s this way). add_src must not overlap a.
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
+ntt_inv_add_kernel(uint32_t *a_all, const uint32_t *__restrict__ add_src, size_t add_stride,
+                   const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN, T = 1 << LOGT, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
+    __shared__ uint32_t lds[N + N / 32];
+    const uint32_t p = blockIdx.x, limb = p % L, poly = p / L, tid = threadIdx.x;
+    uint32_t *a = a_all + (size_t)p * N;
+    const uint32_t *ad = add_src + (size_t)poly * add_stride + (size_t)limb * N;
+    const uint32_t *tw = tw_all + (size_t)limb * N;
+    const LimbConst lc = lt.c[limb];
+    uint32_t x[E];
+    load_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
+    inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, lc, lds, tid);
+    inv_pass<LOGN, LOGT, E_LOG, 0, E0, true, LAZY>(x, tw, lc, tid);
+#pragma unroll
+    for (int r = 0; r < E; r++) a[tid + r * T] = csub(x[r] + ad[tid + r * T], lc.q);
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+                          hipStream_t s) {
+    const dim3 grid((unsigned)(P * c->L)), block(1u << LOGT);
+    if (c->lazy_ntt)
+        hipLaunchKernelGGL((ntt_inv_add_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, a, add_src,
+                           add_stride, c->d_iw, c->lt, c->L);
+    else
+        hipLaunchKernelGGL((ntt_inv_add_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, a, add_src,
+                           add_stride, c->d_iw, c->lt, c->L);
+    return hipGetLastError();
+}
+
 // Persistent inverse transform: a grid of a few blocks per CU (a multiple of
 // L, so a block keeps one limb); block b transforms limb-polynomials b,
 // b + grid, ... and loads the next one's first-pass residues into registers
@@ -674,6 +710,25 @@ int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_strid
         default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
     }
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
+    return HYENA_OK;
+}
+
+int launch_ntt_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+                       hipStream_t s) {
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_intt: context was created host-only");
+    if (P == 0) return HYENA_OK;
+    if (P * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_intt: too many polynomials");
+    if ((uintptr_t)a & 15u) return set_error(HYENA_EINVAL, "hyena_intt: polynomial array is not 16-byte aligned");
+    hipError_t e;
+    switch (c->logN) {   // the default schedule of each N (one block per limb-polynomial)
+        case 10: e = launch_inv_add<10, 6, 4, 3, 3, 0>(c, a, P, add_src, add_stride, s); break;
+        case 11: e = launch_inv_add<11, 7, 4, 4, 3, 0>(c, a, P, add_src, add_stride, s); break;
+        case 12: e = launch_inv_add<12, 8, 4, 4, 4, 0>(c, a, P, add_src, add_stride, s); break;
+        case 13: e = launch_inv_add<13, 8, 5, 4, 4, 0>(c, a, P, add_src, add_stride, s); break;
+        case 14: e = launch_inv_add<14, 10, 4, 4, 4, 2>(c, a, P, add_src, add_stride, s); break;
+        default: return set_error(HYENA_EUNSUPPORTED, "hyena_intt: unsupported N");
+    }
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_intt: ") + hipGetErrorString(e));
     return HYENA_OK;
 }
 
