@@ -411,3 +411,46 @@ def test_simd_conv_packed_entry_point(dev):
         for row in range(2):
             frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[2 * o2 + row]) % p), (o2, row)
+
+
+def test_simd_conv_packed_full_layer_at_the_noise_chosen_base(dev):
+    """The benchmark's layer at full size (30x30, 64 -> 64 channels, n = 2048,
+    three primes below 2^30) with output channel packing, at the base
+    hyena_simd_conv_choose_base returns: sampled output ciphertexts decrypt to
+    2k conv(x) for both of their output channels at every image position (a
+    property that holds at any size; bit equality with the oracle's
+    composition is checked on the smaller cases above)."""
+    import torch
+    n, L, p = 2048, 3, 307201
+    fh, fw, Ci, Co = 32, 32, 64, 64
+    say("hyena_simd_conv_packed, 64 -> 64 at the chosen base")
+    ctx = ctx_for(n, L, 30)
+    primes = ctx.primes
+    s = orc.keygen(n, 61)
+    h, k, kh = hy.hyena_simd_params(n, p, 61)
+    rng = np.random.default_rng(62)
+    H, W = fh - 2, fw - 2
+    x = rng.integers(-8, 8, size=(Ci, H, W))
+    w = rng.integers(-8, 8, size=(Co, Ci, 3, 3))
+    wa, wb = hy.hyena_simd_conv_weights_packed(w.astype(np.int8), k)
+    b, margin = hy.hyena_simd_conv_choose_base(ctx, p, kh, wa, wb, packed=True)
+    say(f"  chosen base 2^{b} (margin {margin:.2f} bits)")
+    G = Ci // 2
+    msgs = np.stack([simd.encode(simd.frame_slots(x[2 * g:2 * g + 2], fh, fw), p, n) for g in range(G)])
+    ct = simd.encrypt_p(primes, p, s, msgs, 63)
+    gs = simd.conv_rotations(n, fw)
+    keys = to_dev(np.stack([hy.hyena_galois_keygen(ctx, s, g, b, 640 + i) for i, g in enumerate(gs)]))
+    skey = to_dev(hy.hyena_galois_keygen(ctx, s, 2 * n - 1, b, 649))
+    hy.hyena_ksk_prepare(ctx, keys)
+    hy.hyena_ksk_prepare(ctx, skey)
+    work = torch.empty(hy.hyena_simd_conv_packed_workspace(ctx, G, Co, b), dtype=torch.int32, device="cuda")
+    out = torch.empty(Co // 2 * 2 * L * n, dtype=torch.int32, device="cuda")
+    hy.hyena_simd_conv_packed(ctx, to_dev(ct), fw, torch.from_numpy(wa).cuda(), torch.from_numpy(wb).cuda(), kh, b,
+                              keys, skey, work, out)
+    got = from_dev(out).reshape(Co // 2, 2, L, n)
+    y = orc.direct_conv(x, w, 3)
+    for o2 in (0, 7, 19, 31):
+        slots = simd.decode(simd.decrypt_p(primes, p, s, got[o2][None])[0], p, n).astype(np.int64)
+        for row in range(2):
+            frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
+            assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[2 * o2 + row]) % p), (o2, row)
