@@ -35,3 +35,9 @@ int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_strid
 // inputs); add_src must not overlap a; a 16-byte aligned (ntt.hip).
 int launch_ntt_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
                        hipStream_t s);
+
+// Encryption's uniform polynomials drawn inside the forward NTT: for message m
+// and limb i, a = floor(q_i sm64(seed, 2 ((m L + i) N + j)) / 2^64); writes
+// c1 = -a into ct [n][2][L][N] and NTT(a) . mul into dst [n][L][N] (ntt.hip).
+int launch_ntt_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+                          uint64_t seed, hipStream_t s);

@@ -84,25 +84,6 @@ __global__ void __launch_bounds__(CTH) to_montgomery_kernel(uint32_t *s, uint32_
     }
 }
 
-// work[m] <- a and c1 <- [-a] for n ciphertexts [n][2][L][N]
-__global__ void __launch_bounds__(CTH) sample_a_kernel(uint32_t *ct, uint32_t *work, size_t n, uint32_t logN,
-                                                       uint32_t L, uint64_t seed, LimbTable lt) {
-    const uint32_t cpl = 1u << (logN - 8);   // chunks per limb-polynomial
-    const size_t LN = (size_t)L << logN, chunks = n * L * cpl;
-    for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
-        const size_t poly = c >> (logN - 8);           // m L + i
-        const size_t m = poly / L;
-        const uint32_t i = (uint32_t)(poly - m * L);
-        const uint32_t j = ((uint32_t)(c & (cpl - 1)) << 8) + threadIdx.x;
-        const size_t idx = (c << 8) + threadIdx.x;     // (m L + i) N + j
-        const uint32_t q = lt.c[i].q;
-        const uint32_t a = (uint32_t)__umul64hi(hy_sm64(seed, 2 * (uint64_t)idx), (uint64_t)q);
-        const size_t r = ((size_t)i << logN) + j;
-        work[m * LN + r] = a;
-        ct[m * 2 * LN + LN + r] = a ? q - a : 0;
-    }
-}
-
 // c0 <- [Delta_i lift(msg) + work + lift(e)]_{q_i} (work = a s); e drawn once per (m, j) for all limbs
 __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const uint32_t *work, const int32_t *msg,
                                                              size_t n, uint32_t logN, uint32_t L, uint64_t seed,
@@ -232,12 +213,9 @@ extern "C" int hyena_encrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     bfv_error_thresholds(th.t);
     for (int k = 0; k + 1 < 2 * kErrBound; k++)   // the kernel's binary search relies on it
         if (th.t[k] > th.t[k + 1]) return set_error(HYENA_EINVAL, std::string(who) + ": sampler table not monotone");
-    const size_t chunks = (n * L) << (c->logN - 8);
-    hipLaunchKernelGGL(sample_a_kernel, dim3(grid_for(chunks)), dim3(CTH), 0, s, d_ct, d_work, n, c->logN, L, seed,
-                       c->lt);
-    if (int rc = launched(who)) return rc;
-    // a s = INTT(NTT(a) . NTT(s)) in the workspace, the product fused into the forward transform's store
-    if (int rc = launch_ntt_fwd_mul(c, d_work, LN, n, d_work, d_s_hat, s)) return rc;
+    // a drawn inside the forward transform, which writes c1 = -a and NTT(a) . NTT(s) into the workspace;
+    // a s = INTT of that
+    if (int rc = launch_ntt_fwd_sample(c, d_ct, n, d_work, d_s_hat, seed, s)) return rc;
     if (int rc = launch_ntt(c, d_work, n, true, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
     hipLaunchKernelGGL(encrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_work, d_msg, n,

@@ -391,6 +391,46 @@ ntt_fwd_mul_kernel(const uint32_t *src, size_t src_stride, uint32_t *dst, const 
     store_runs_mul<LOGT, LOGN - LOGT, (E3 > 0 ? E3 : E2)>(x, dst + (size_t)p * N, mul + (size_t)limb * N, q, qn, tid);
 }
 
+// Forward transform of the encryption's uniform polynomials, drawn in the
+// load: block p (limb p mod L of message p / L) takes
+// a_j = floor(q sm64(seed, 2 (p N + j)) / 2^64), writes c1 = -a of that
+// ciphertext ([n][2][L][N]) and stores NTT(a) . mul into dst [n][L][N].
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
+__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
+ntt_fwd_sample_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ mul, uint64_t seed,
+                      const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << (LOGN - LOGT);
+    __shared__ uint32_t lds[N + N / 32];
+    const uint32_t p = blockIdx.x, limb = p % L, m = p / L, tid = threadIdx.x;
+    const size_t LN = (size_t)L * N;
+    uint32_t *c1 = ct + (size_t)m * 2 * LN + LN + (size_t)limb * N;
+    const uint32_t *tw = tw_all + (size_t)limb * N;
+    const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg;
+    uint32_t x[E];
+#pragma unroll
+    for (int r = 0; r < E; r++) {
+        const uint32_t j = tid + r * T;
+        const uint32_t a = (uint32_t)__umul64hi(hy_sm64(seed, 2 * ((uint64_t)p * N + j)), (uint64_t)q);
+        x[r] = a;
+        c1[j] = a ? q - a : 0;
+    }
+    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
+    store_runs_mul<LOGT, LOGN - LOGT, (E3 > 0 ? E3 : E2)>(x, dst + (size_t)p * N, mul + (size_t)limb * N, q, qn, tid);
+}
+
+template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
+hipError_t launch_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+                             uint64_t seed, hipStream_t s) {
+    const dim3 grid((unsigned)(n * c->L)), block(1u << LOGT);
+    if (c->lazy_ntt)
+        hipLaunchKernelGGL((ntt_fwd_sample_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, ct, dst, mul,
+                           seed, c->d_fw, c->lt, c->L);
+    else
+        hipLaunchKernelGGL((ntt_fwd_sample_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, ct, dst, mul,
+                           seed, c->d_fw, c->lt, c->L);
+    return hipGetLastError();
+}
+
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
 hipError_t launch_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
                           const uint32_t *mul, hipStream_t s) {
@@ -707,6 +747,26 @@ int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_strid
         case 12: e = launch_fwd_mul<12, 8, 4, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
         case 13: e = launch_fwd_mul<13, 8, 5, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
         case 14: e = launch_fwd_mul<14, 10, 4, 4, 4, 2>(c, src, src_stride, P, dst, mul, s); break;
+        default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
+    }
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
+    return HYENA_OK;
+}
+
+int launch_ntt_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+                          uint64_t seed, hipStream_t s) {
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
+    if (n == 0) return HYENA_OK;
+    if (n * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
+    if (((uintptr_t)dst | (uintptr_t)mul) & 15u)
+        return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
+    hipError_t e;
+    switch (c->logN) {
+        case 10: e = launch_fwd_sample<10, 6, 4, 3, 3, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 11: e = launch_fwd_sample<11, 7, 4, 4, 3, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 12: e = launch_fwd_sample<12, 8, 4, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 13: e = launch_fwd_sample<13, 8, 5, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 14: e = launch_fwd_sample<14, 10, 4, 4, 4, 2>(c, ct, n, dst, mul, seed, s); break;
         default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
     }
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
