@@ -108,6 +108,8 @@ def parse():
                     help="skip the supplementary client-side run (device encryption and decryption)")
     ap.add_argument("--no-simd", action="store_true",
                     help="skip the supplementary run of the SIMD-setting kernels (HRot, batch encoding, PMult)")
+    ap.add_argument("--no-synth", action="store_true",
+                    help="skip the supplementary run of the evaluation-domain weight synthesis")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -398,6 +400,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         enc.append(e0.elapsed_time(e1))
+    synth = None if args.no_synth else weight_synthesis(ctx, layers, hy, torch)
     out = {
         "metric": "HE-conv coeff-MACs/s + layers/s at N=8192, batched/tuned vs plain; bit-exact",
         "value": head["coeff_macs_per_s"],
@@ -421,6 +424,8 @@ def main():
         "ms_per_step_with_encode": head["ms_per_step"] + min(enc),
         "schedules": res,
     }
+    if synth is not None:
+        out["weight_synthesis"] = synth
     if "plain" in res:
         for m in ("batched", "tuned"):
             if m in res:
@@ -491,6 +496,47 @@ def main():
     else:
         log("no oracle run: outputs not checked (--no-cpu-baseline)")
     print(json.dumps(out))
+
+
+def weight_synthesis(ctx, layers, hy, torch):
+    """Every layer's NTT-domain weights made two ways: hyena_encode_weights
+    (taps scattered into kernel polynomials, then the NTT) and
+    hyena_synth_weights (each word evaluated from the integer taps, ci*k*k
+    multiply-adds, no transform). The two must agree on every word."""
+    log("supplementary run: evaluation-domain weight synthesis against scatter + NTT ...")
+    big = max(o.d_wn.numel() for o in layers)
+    scratch = torch.empty(big, dtype=torch.int32, device="cuda")
+
+    def timed(fn):
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    rows = []
+    for o in layers:
+        d, n = o.desc_b, o.d_wn.numel()
+        dst = scratch[:n]
+        t_enc = timed(lambda: hy.hyena_encode_weights(ctx, d, o.d_w, o.d_wn))
+        t_syn = timed(lambda: hy.hyena_synth_weights(ctx, d, o.d_w, dst))
+        if not torch.equal(dst, o.d_wn):
+            raise SystemExit(f"synthesised and encoded weights differ on VGG layer {o.lay.name}")
+        rows.append({"layer": o.lay.name, "taps_per_word": d.ci * d.k * d.k, "words": n,
+                     "encode_ms": t_enc, "synth_ms": t_syn})
+    del scratch
+    tot_e = sum(r["encode_ms"] for r in rows)
+    tot_s = sum(r["synth_ms"] for r in rows)
+    c1 = [r for r in rows if r["taps_per_word"] <= 9]
+    log(f"weights: scatter + NTT {tot_e:.2f} ms, synthesis {tot_s:.2f} ms for all layers (equal words); "
+        f"layers with <= 9 taps per word: {sum(r['encode_ms'] for r in c1):.3f} against "
+        f"{sum(r['synth_ms'] for r in c1):.3f} ms")
+    return {"encode_ms": tot_e, "synth_ms": tot_s, "bit_exact": True, "layers": rows}
 
 
 def wht_bandwidth(ctx, layers, hy, torch):

@@ -237,6 +237,23 @@ int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                          const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
 
 /*
+ * The same d_wntt as hyena_encode_weights, bit for bit, synthesised directly
+ * from the integer taps (the paper stores kernels as small integers and
+ * derives their polynomial form on demand, "Enabling Output Channel Packing";
+ * the evaluation points are those of the negacyclic NTT that the "Homomorphic
+ * Operations in BFV" section multiplies with): word k of limb i is
+ *   c_n^{-1} 2^32 * sum_taps gw * psi_i^((2 brv(k) + 1) e_tap)  mod q_i
+ * over the ci*k*k taps of the input group, with no coefficient array and no
+ * transform. Each word costs ci*k*k multiply-adds, so it is the cheaper form
+ * for layers with few taps per input group (ci = 1). Every word of d_wntt is
+ * written (no prior zeroing needed); 4-byte alignment suffices.
+ * Errors: EINVAL (NULL, unplanned descriptor, host-only context),
+ * EUNSUPPORTED (depthwise layers, N not a multiple of 256), EHIP.
+ */
+int hyena_synth_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
+                        const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
+
+/*
  * In-place forward negacyclic NTT of P polynomials, d_poly: device uint32
  * [P][L][N] (limb i uses q_i):
  *   A[k] = sum_j a[j] psi_i^((2 brv(k) + 1) j) mod q_i

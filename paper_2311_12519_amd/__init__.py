@@ -75,6 +75,7 @@ _SIGS = {
     "hyena_pack_input": [_P, _u32, _P, _P],
     "hyena_unpack_output": [_P, _u32, _P, _P],
     "hyena_encode_weights": [_P, _P, _P, _P, _P],
+    "hyena_synth_weights": [_P, _P, _P, _P, _P],
     "hyena_ntt": [_P, _P, _sz, _P],
     "hyena_intt": [_P, _P, _sz, _P],
     "hyena_conv": [_P, _P, _P, _P, _P, _P],
@@ -277,6 +278,11 @@ def hyena_unpack_output(desc: ConvDesc, N: int, msg: np.ndarray) -> np.ndarray:
 def hyena_encode_weights(ctx: Ctx, desc: ConvDesc, d_w, d_wntt, stream=None) -> None:
     _check(lib().hyena_encode_weights(ctx.handle, ctypes.byref(desc), _dev_ptr(d_w, "int8"),
                                       _dev_ptr(d_wntt, "int32"), _stream(stream)))
+
+
+def hyena_synth_weights(ctx: Ctx, desc: ConvDesc, d_w, d_wntt, stream=None) -> None:
+    _check(lib().hyena_synth_weights(ctx.handle, ctypes.byref(desc), _dev_ptr(d_w, "int8"),
+                                     _dev_ptr(d_wntt, "int32"), _stream(stream)))
 
 
 def hyena_ntt(ctx: Ctx, d_poly, stream=None) -> None:

@@ -1,0 +1,172 @@
+// Evaluation-domain weight synthesis for gfx950.
+//
+// The cloud keeps each layer's kernels as small integers (the "Enabling Output
+// Channel Packing" section) and needs them as evaluations at the NTT points.
+// The kernel polynomial of output o and input group g is a sparse sum of
+// monomials gw X^e (one per tap: e = O - c'*Bt - di*Wp - dj, gw the
+// Walsh-combined integer weight), so its value at the point of NTT slot k,
+// r = psi^(2 brv(k) + 1), is sum gw r^e: ci*k*k multiply-adds per word, with
+// no coefficient array and no transform. hyena_encode_weights reaches the
+// same words by scattering the taps and running the forward NTT.
+//
+// A block owns 256 slots of one limb for kSynthPolys consecutive polynomials
+// (o, g). Each thread forms r^O, r^-Bt, r^-Wp and r^-1 by square-and-multiply
+// and walks the tap powers with one Montgomery product per tap; the block
+// stages the Walsh-combined weights of up to kSynthTaps taps of all its
+// polynomials in LDS (read back as broadcasts); every tap adds power times
+// weight into one signed 64-bit accumulator per polynomial. |gw| <= 64 * 128
+// and fewer than 2^17 taps of powers below 2^31 keep it below 2^61 <= q 2^32,
+// so adding q 2^32 makes it a non-negative 64-bit value that one fold and one
+// Montgomery reduction take.
+#include <string>
+
+#include "internal.h"
+
+namespace {
+
+constexpr uint32_t kSynthPolys = 32, kSynthTaps = 256;
+
+struct SynthArgs {
+    const int8_t *w;
+    uint32_t *out;
+    uint32_t N, L, logN, Co, Ci, k, ci, Bt, Wp, O, w_groups, c_n, kchunks;
+    uint32_t psi_m[HYENA_MAX_LIMBS];   // psi_i 2^32 mod q_i
+    uint32_t wscale[HYENA_MAX_LIMBS];  // c_n^{-1} 2^64 mod q_i
+    LimbTable lt;
+};
+
+// Montgomery reduction: y 2^-32 mod q for y < q 2^32
+__device__ __forceinline__ uint32_t redc(uint64_t y, const LimbConst &lc) {
+    const uint32_t m = (uint32_t)y * lc.qinv_neg;
+    const uint32_t t = (uint32_t)(((uint64_t)m * lc.q + y) >> 32);
+    return min(t, t - lc.q);
+}
+
+__device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, const LimbConst &lc) {
+    return redc((uint64_t)a * b, lc);  // a, b < q: a b < q 2^32
+}
+
+// b^e for b in Montgomery form; the result is in Montgomery form
+__device__ uint32_t mont_pow(uint32_t b, uint32_t e, const LimbConst &lc) {
+    uint32_t r = lc.r32;  // 1 in Montgomery form
+    for (; e; e >>= 1) {
+        if (e & 1) r = mont_mul(r, b, lc);
+        b = mont_mul(b, b, lc);
+    }
+    return r;
+}
+
+__global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
+    __shared__ __align__(16) int32_t gs[kSynthTaps][kSynthPolys];
+    const uint32_t chunk = blockIdx.x % a.kchunks, pblk = blockIdx.x / a.kchunks, limb = blockIdx.y;
+    const uint32_t slot = chunk * 256 + threadIdx.x;
+    const LimbConst lc = a.lt.c[limb];
+    const uint32_t two_n = 2 * a.N;
+    // exponent of r = psi^(2 brv(slot) + 1); psi has order 2N
+    const uint64_t re = 2 * (uint64_t)(__brev(slot) >> (32 - a.logN)) + 1;
+    auto rpow = [&](uint32_t e) { return mont_pow(a.psi_m[limb], (uint32_t)(re * e % two_n), lc); };
+    const uint32_t step_c = rpow(two_n - a.Bt % two_n), step_r = rpow(two_n - a.Wp % two_n),
+                   step_j = rpow(two_n - 1);
+    const uint32_t polys = a.Co * a.w_groups, p0 = pblk * kSynthPolys, kk = a.k * a.k;
+    const uint32_t cpb = kSynthTaps / kk > 0 ? kSynthTaps / kk : 1;
+    int64_t acc[kSynthPolys];
+#pragma unroll
+    for (uint32_t pb = 0; pb < kSynthPolys; pb++) acc[pb] = 0;
+    uint32_t pc = rpow(a.O % two_n);
+    for (uint32_t cp0 = 0; cp0 < a.ci; cp0 += cpb) {
+        const uint32_t nc = min(cpb, a.ci - cp0), nt = nc * kk;
+        __syncthreads();  // the previous chunk's weights are no longer read
+        // consecutive threads take consecutive taps of one polynomial: the
+        // int8 weights of (cw, di, dj) are contiguous for a fixed output
+        for (uint32_t idx = threadIdx.x; idx < nt * kSynthPolys; idx += 256) {
+            const uint32_t t = idx % nt, pb = idx / nt, p = p0 + pb;
+            int32_t gsum = 0;
+            if (p < polys) {
+                const uint32_t o = p / a.w_groups, g = p % a.w_groups, cw = g * a.ci + cp0 + t / kk;
+                if (cw < a.Ci) {
+                    const uint32_t G = o / a.c_n, j = o % a.c_n, tap = t % kk;
+                    for (uint32_t b = 0; b < a.c_n; b++) {
+                        const int v = a.w[((size_t)(G * a.c_n + b) * a.Ci + cw) * kk + tap];
+                        gsum += (__popc(j & b) & 1) ? -v : v;
+                    }
+                }
+            }
+            gs[t][pb] = gsum;
+        }
+        __syncthreads();
+        uint32_t t = 0;
+        for (uint32_t c = 0; c < nc; c++, pc = mont_mul(pc, step_c, lc)) {
+            uint32_t pr = pc;
+            for (uint32_t di = 0; di < a.k; di++, pr = mont_mul(pr, step_r, lc)) {
+                uint32_t pw = pr;
+                for (uint32_t dj = 0; dj < a.k; dj++, pw = mont_mul(pw, step_j, lc), t++) {
+                    const int4 *row = reinterpret_cast<const int4 *>(gs[t]);
+#pragma unroll
+                    for (uint32_t v4 = 0; v4 < kSynthPolys / 4; v4++) {
+                        const int4 v = row[v4];
+                        acc[4 * v4 + 0] += (int64_t)v.x * pw;
+                        acc[4 * v4 + 1] += (int64_t)v.y * pw;
+                        acc[4 * v4 + 2] += (int64_t)v.z * pw;
+                        acc[4 * v4 + 3] += (int64_t)v.w * pw;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t pb = 0; pb < kSynthPolys; pb++) {
+        const uint32_t p = p0 + pb;
+        if (p >= polys) break;
+        // acc = 2^32 sum (the powers are in Montgomery form); the reduction
+        // leaves sum, the product by c_n^{-1} 2^64 then c_n^{-1} 2^32 sum
+        const uint64_t y = (uint64_t)acc[pb] + ((uint64_t)lc.q << 32);
+        // fold the high word (hi 2^32 = hi r32 mod q), then reduce:
+        // hi r32 + lo <= (2^32 - 1) q < q 2^32
+        const uint32_t v = redc((uint64_t)(uint32_t)(y >> 32) * lc.r32 + (uint32_t)y, lc);
+        a.out[((size_t)p * a.L + limb) * a.N + slot] = mont_mul(v, a.wscale[limb], lc);
+    }
+}
+
+}  // namespace
+
+extern "C" int hyena_synth_weights(const hyena_ctx *c, const hyena_conv_desc *d, const int8_t *d_w,
+                                   uint32_t *d_wntt, hyena_stream_t s) {
+    if (!c || !d || !d_w || !d_wntt) return set_error(HYENA_EINVAL, "hyena_synth_weights: NULL argument");
+    if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_synth_weights: descriptor not planned");
+    if (d->depthwise) return set_error(HYENA_EUNSUPPORTED, "hyena_synth_weights: depthwise layers use hyena_encode_weights");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_synth_weights: context was created host-only");
+    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_synth_weights: N must be a multiple of 256");
+    const uint32_t cn = d->c_n ? d->c_n : 1;
+    if (d->k * d->k > kSynthTaps || cn > 64 || d->Co % cn || !d->ci || (size_t)d->ci * d->w_groups < d->Ci ||
+        (uint64_t)d->ci * d->k * d->k >= (1u << 17))
+        return set_error(HYENA_EINVAL, "hyena_synth_weights: descriptor fields inconsistent with a plan");
+    const size_t polys = (size_t)d->Co * d->w_groups;
+    if (polys == 0) return HYENA_OK;
+    const size_t blocks = (polys + kSynthPolys - 1) / kSynthPolys * (c->N / 256);
+    if (blocks > 0x7fffffffu / 256) return set_error(HYENA_EINVAL, "hyena_synth_weights: layer too large for one launch");
+    SynthArgs a{};
+    a.w = d_w;
+    a.out = d_wntt;
+    a.N = c->N;
+    a.L = c->L;
+    a.logN = c->logN;
+    a.Co = d->Co;
+    a.Ci = d->Ci;
+    a.k = d->k;
+    a.ci = d->ci;
+    a.Bt = d->Bt;
+    a.Wp = d->Wp;
+    a.O = d->O;
+    a.w_groups = d->w_groups;
+    a.c_n = cn;
+    a.kchunks = c->N / 256;
+    a.lt = c->lt;
+    for (uint32_t i = 0; i < c->L; i++) {
+        a.psi_m[i] = to_montgomery(c->psi[i], c->q[i]);
+        a.wscale[i] = to_montgomery(to_montgomery(h_powmod(a.c_n, c->q[i] - 2, c->q[i]), c->q[i]), c->q[i]);
+    }
+    hipLaunchKernelGGL(synth_weights_kernel, dim3((unsigned)blocks, c->L), dim3(256), 0, (hipStream_t)s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_synth_weights: ") + hipGetErrorString(e));
+    return HYENA_OK;
+}

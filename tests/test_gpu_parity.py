@@ -129,6 +129,42 @@ def test_encode_weights_matches_oracle(dev, c_n, dw):
                 assert np.array_equal(got[o, 0 if dw else slot, i], want.astype(np.uint32)), (o, g, i)
 
 
+@pytest.mark.parametrize("N,L,bits,H,Ci,Co,k,c_n", [
+    (4096, 2, 30, 16, 16, 16, 3, 1),     # ci = 12: two input groups, the second ragged
+    (4096, 2, 30, 16, 16, 16, 3, 4),     # Walsh-combined taps
+    (8192, 3, 31, 64, 3, 20, 3, 1),      # ci = 1 (9 taps per word), 60 polynomials
+    (8192, 3, 31, 14, 64, 32, 1, 2),     # 1x1 kernel
+    (16384, 2, 31, 7, 100, 8, 3, 8),     # many taps per word
+])
+def test_synth_weights_equals_encode_weights(dev, N, L, bits, H, Ci, Co, k, c_n):
+    """hyena_synth_weights (evaluation-domain synthesis, no NTT) against
+    hyena_encode_weights on every word, and against the oracle's kernel
+    polynomials on the first and last output channel."""
+    import torch
+    say(f"synth N={N} L={L} H={H} Ci={Ci} Co={Co} k={k} c_n={c_n}")
+    ctx = ctx_for(N, L, bits)
+    lay = wl.Layer("t", H, H, Ci, Co, k)
+    d = hy.hyena_conv_plan(ctx, H, H, Ci, Co, k, c_n=c_n)
+    w = wl.weights(5 + c_n, lay)
+    dw_t = torch.from_numpy(w).cuda()
+    n = hy.wntt_words(ctx, d)
+    enc = torch.empty(n, dtype=torch.int32, device="cuda")
+    syn = torch.full((n,), -1, dtype=torch.int32, device="cuda")   # every word must be written
+    hy.hyena_encode_weights(ctx, d, dw_t, enc)
+    hy.hyena_synth_weights(ctx, d, dw_t, syn)
+    a, b = from_dev(enc), from_dev(syn)
+    assert np.array_equal(a, b), int(np.count_nonzero(a != b))
+    pl = orc.plan(N, H, H, Ci, Co, k)
+    got = b.reshape(Co, d.w_groups, L, N)
+    for o in (0, Co - 1):
+        G, j = divmod(o, c_n)
+        for g in range(pl.n_groups):
+            Kw = orc.walsh_kernel_residues(pl, w, c_n, ctx.primes, G, j, g)
+            for i, q in enumerate(ctx.primes):
+                want = (orc.ntt(Kw[i], q, ctx.psi[i]).astype(np.uint64) << np.uint64(32)) % np.uint64(q)
+                assert np.array_equal(got[o, g, i], want.astype(np.uint32)), (o, g, i)
+
+
 # ---------------------------------------------------------------- Walsh-Hadamard
 
 @pytest.mark.parametrize("c_n", [2, 4, 8, 64])

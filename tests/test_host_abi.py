@@ -169,6 +169,21 @@ def test_client_device_calls_refused_on_host_only_context():
     assert "host-only" in L.hyena_last_error().decode()
 
 
+def test_synth_weights_refusals():
+    """hyena_synth_weights checks its arguments before any launch: NULL arrays,
+    depthwise layers (EUNSUPPORTED) and host-only contexts are refused."""
+    ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
+    L = hy.lib()
+    fake = ctypes.c_void_p(0x10000)      # never dereferenced: every call below fails its checks first
+    null = ctypes.c_void_p(0)
+    d = hy.hyena_conv_plan(ctx, 16, 16, 16, 16, 3)
+    dd = hy.hyena_conv_plan(ctx, 16, 16, 16, 16, 3, depthwise=True)
+    assert L.hyena_synth_weights(ctx.handle, ctypes.byref(d), null, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_synth_weights(ctx.handle, ctypes.byref(dd), fake, fake, null) == hy.HYENA_EUNSUPPORTED
+    assert L.hyena_synth_weights(ctx.handle, ctypes.byref(d), fake, fake, null) == hy.HYENA_EINVAL
+    assert "host-only" in L.hyena_last_error().decode()
+
+
 def test_simd_params_match_the_papers_example_and_the_oracle():
     """hyena_simd_params (closed form h = (w + w^3)^-1, w = zeta^(n/4)) against
     the paper's worked example and the oracle's brute-force encoding."""
