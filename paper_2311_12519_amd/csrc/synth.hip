@@ -14,9 +14,13 @@
 // and walks the tap powers with one Montgomery product per tap; the block
 // stages the Walsh-combined weights of up to kSynthTaps taps of all its
 // polynomials in LDS (read back as broadcasts); every tap adds power times
-// weight into one signed 64-bit accumulator per polynomial. |gw| <= 64 * 128
-// and fewer than 2^17 taps of powers below 2^31 keep it below 2^61 <= q 2^32,
-// so adding q 2^32 makes it a non-negative 64-bit value that one fold and one
+// weight into one 64-bit accumulator per polynomial. The weights are stored
+// offset by 2^13 (|gw| <= 64 * 128, so gw + 2^13 is in [0, 2^14]), which makes
+// each product one unsigned 32 x 32 -> 64 multiply-add; the offset's share,
+// 2^13 times the sum of the powers (one accumulator for all polynomials), is
+// taken off at the end. Fewer than 2^17 taps of powers below 2^31 keep the
+// unsigned sums below 2^62 and the signed result below 2^61 <= q 2^32, so
+// adding q 2^32 makes it a non-negative 64-bit value that one fold and one
 // Montgomery reduction take.
 #include <string>
 
@@ -57,7 +61,7 @@ __device__ uint32_t mont_pow(uint32_t b, uint32_t e, const LimbConst &lc) {
 }
 
 __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
-    __shared__ __align__(16) int32_t gs[kSynthTaps][kSynthPolys];
+    __shared__ __align__(16) uint32_t gs[kSynthTaps][kSynthPolys];  // gw + 2^13
     const uint32_t chunk = blockIdx.x % a.kchunks, pblk = blockIdx.x / a.kchunks, limb = blockIdx.y;
     const uint32_t slot = chunk * 256 + threadIdx.x;
     const LimbConst lc = a.lt.c[limb];
@@ -69,7 +73,7 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
                    step_j = rpow(two_n - 1);
     const uint32_t polys = a.Co * a.w_groups, p0 = pblk * kSynthPolys, kk = a.k * a.k;
     const uint32_t cpb = kSynthTaps / kk > 0 ? kSynthTaps / kk : 1;
-    int64_t acc[kSynthPolys];
+    uint64_t acc[kSynthPolys], psum = 0;
 #pragma unroll
     for (uint32_t pb = 0; pb < kSynthPolys; pb++) acc[pb] = 0;
     uint32_t pc = rpow(a.O % two_n);
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
                     }
                 }
             }
-            gs[t][pb] = gsum;
+            gs[t][pb] = (uint32_t)(gsum + (1 << 13));
         }
         __syncthreads();
         uint32_t t = 0;
@@ -100,14 +104,15 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
             for (uint32_t di = 0; di < a.k; di++, pr = mont_mul(pr, step_r, lc)) {
                 uint32_t pw = pr;
                 for (uint32_t dj = 0; dj < a.k; dj++, pw = mont_mul(pw, step_j, lc), t++) {
-                    const int4 *row = reinterpret_cast<const int4 *>(gs[t]);
+                    const uint4 *row = reinterpret_cast<const uint4 *>(gs[t]);
+                    psum += pw;
 #pragma unroll
                     for (uint32_t v4 = 0; v4 < kSynthPolys / 4; v4++) {
-                        const int4 v = row[v4];
-                        acc[4 * v4 + 0] += (int64_t)v.x * pw;
-                        acc[4 * v4 + 1] += (int64_t)v.y * pw;
-                        acc[4 * v4 + 2] += (int64_t)v.z * pw;
-                        acc[4 * v4 + 3] += (int64_t)v.w * pw;
+                        const uint4 v = row[v4];
+                        acc[4 * v4 + 0] += (uint64_t)v.x * pw;
+                        acc[4 * v4 + 1] += (uint64_t)v.y * pw;
+                        acc[4 * v4 + 2] += (uint64_t)v.z * pw;
+                        acc[4 * v4 + 3] += (uint64_t)v.w * pw;
                     }
                 }
             }
@@ -117,9 +122,11 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
     for (uint32_t pb = 0; pb < kSynthPolys; pb++) {
         const uint32_t p = p0 + pb;
         if (p >= polys) break;
-        // acc = 2^32 sum (the powers are in Montgomery form); the reduction
-        // leaves sum, the product by c_n^{-1} 2^64 then c_n^{-1} 2^32 sum
-        const uint64_t y = (uint64_t)acc[pb] + ((uint64_t)lc.q << 32);
+        // y = sum gw pw + q 2^32, in [0, 2^64) (the unsigned wrap-around of
+        // the subtraction cancels because the true value is in range); the
+        // powers carry 2^32 (Montgomery form), so the reduction leaves
+        // sum gw r^e, and the product by c_n^{-1} 2^64 makes it c_n^{-1} 2^32 sum
+        const uint64_t y = acc[pb] - (psum << 13) + ((uint64_t)lc.q << 32);
         // fold the high word (hi 2^32 = hi r32 mod q), then reduce:
         // hi r32 + lo <= (2^32 - 1) q < q 2^32
         const uint32_t v = redc((uint64_t)(uint32_t)(y >> 32) * lc.r32 + (uint32_t)y, lc);
