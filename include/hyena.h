@@ -245,8 +245,9 @@ int hyena_encode_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
  *   c_n^{-1} 2^32 * sum_taps gw * psi_i^((2 brv(k) + 1) e_tap)  mod q_i
  * over the ci*k*k taps of the input group, with no coefficient array and no
  * transform. Each word costs ci*k*k multiply-adds, so it is the cheaper form
- * for layers with few taps per input group (ci = 1). Every word of d_wntt is
- * written (no prior zeroing needed); 4-byte alignment suffices.
+ * for layers with few taps per input group (up to about 18: ci <= 2 at k = 3).
+ * Every word of d_wntt is written (no prior zeroing needed); 4-byte
+ * alignment suffices.
  * Errors: EINVAL (NULL, unplanned descriptor, host-only context),
  * EUNSUPPORTED (depthwise layers, N not a multiple of 256), EHIP.
  */
