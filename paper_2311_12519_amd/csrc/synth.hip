@@ -10,8 +10,10 @@
 // same words by scattering the taps and running the forward NTT.
 //
 // A block owns 256 slots of one limb for kSynthPolys consecutive polynomials
-// (o, g). Each thread forms r^O, r^-Bt, r^-Wp and r^-1 by square-and-multiply
-// and walks the tap powers with one Montgomery product per tap; the block
+// (o, g). Each thread looks up r^O, r^-Bt, r^-Wp and r^-1 in the context's
+// table of psi powers (r^E = psi^((2 brv(k) + 1) E mod 2N), and
+// psi^(m + N) = -psi^m) and walks the tap powers with one Montgomery product
+// per tap; the block
 // stages the Walsh-combined weights of up to kSynthTaps taps of all its
 // polynomials in LDS (read back as broadcasts); every tap adds power times
 // weight into one 64-bit accumulator per polynomial. The weights are stored
@@ -33,8 +35,8 @@ constexpr uint32_t kSynthPolys = 32, kSynthTaps = 256;
 struct SynthArgs {
     const int8_t *w;
     uint32_t *out;
+    const uint32_t *fw;                // [L][N]: fw[i][j] = psi_i^brv(j) 2^32 mod q_i
     uint32_t N, L, logN, Co, Ci, k, ci, Bt, Wp, O, w_groups, c_n, kchunks;
-    uint32_t psi_m[HYENA_MAX_LIMBS];   // psi_i 2^32 mod q_i
     uint32_t wscale[HYENA_MAX_LIMBS];  // c_n^{-1} 2^64 mod q_i
     LimbTable lt;
 };
@@ -50,14 +52,11 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t b, const LimbC
     return redc((uint64_t)a * b, lc);  // a, b < q: a b < q 2^32
 }
 
-// b^e for b in Montgomery form; the result is in Montgomery form
-__device__ uint32_t mont_pow(uint32_t b, uint32_t e, const LimbConst &lc) {
-    uint32_t r = lc.r32;  // 1 in Montgomery form
-    for (; e; e >>= 1) {
-        if (e & 1) r = mont_mul(r, b, lc);
-        b = mont_mul(b, b, lc);
-    }
-    return r;
+// psi^e 2^32 mod q for e < 2N, from the bit-reversed table of psi^j, j < N
+__device__ __forceinline__ uint32_t psi_pow(const uint32_t *fw, uint32_t e, uint32_t N, uint32_t logN,
+                                            const LimbConst &lc) {
+    const uint32_t v = fw[__brev(e & (N - 1)) >> (32 - logN)];
+    return (e & N) ? lc.q - v : v;  // v != 0: psi^j is a unit
 }
 
 __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
@@ -65,18 +64,18 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
     const uint32_t chunk = blockIdx.x % a.kchunks, pblk = blockIdx.x / a.kchunks, limb = blockIdx.y;
     const uint32_t slot = chunk * 256 + threadIdx.x;
     const LimbConst lc = a.lt.c[limb];
-    const uint32_t two_n = 2 * a.N;
-    // exponent of r = psi^(2 brv(slot) + 1); psi has order 2N
-    const uint64_t re = 2 * (uint64_t)(__brev(slot) >> (32 - a.logN)) + 1;
-    auto rpow = [&](uint32_t e) { return mont_pow(a.psi_m[limb], (uint32_t)(re * e % two_n), lc); };
-    const uint32_t step_c = rpow(two_n - a.Bt % two_n), step_r = rpow(two_n - a.Wp % two_n),
-                   step_j = rpow(two_n - 1);
+    const uint32_t mask = 2 * a.N - 1;  // psi has order 2N, a power of two
+    // exponent of r = psi^(2 brv(slot) + 1); exponents are taken mod 2N
+    const uint32_t re = 2 * (__brev(slot) >> (32 - a.logN)) + 1;
+    const uint32_t *fw = a.fw + (size_t)limb * a.N;
+    auto rpow = [&](uint32_t e) { return psi_pow(fw, (re * e) & mask, a.N, a.logN, lc); };
+    const uint32_t step_c = rpow(0u - a.Bt), step_r = rpow(0u - a.Wp), step_j = rpow(0u - 1u);
     const uint32_t polys = a.Co * a.w_groups, p0 = pblk * kSynthPolys, kk = a.k * a.k;
     const uint32_t cpb = kSynthTaps / kk > 0 ? kSynthTaps / kk : 1;
     uint64_t acc[kSynthPolys], psum = 0;
 #pragma unroll
     for (uint32_t pb = 0; pb < kSynthPolys; pb++) acc[pb] = 0;
-    uint32_t pc = rpow(a.O % two_n);
+    uint32_t pc = rpow(a.O);
     for (uint32_t cp0 = 0; cp0 < a.ci; cp0 += cpb) {
         const uint32_t nc = min(cpb, a.ci - cp0), nt = nc * kk;
         __syncthreads();  // the previous chunk's weights are no longer read
@@ -154,6 +153,7 @@ extern "C" int hyena_synth_weights(const hyena_ctx *c, const hyena_conv_desc *d,
     SynthArgs a{};
     a.w = d_w;
     a.out = d_wntt;
+    a.fw = c->d_fw;
     a.N = c->N;
     a.L = c->L;
     a.logN = c->logN;
@@ -169,7 +169,6 @@ extern "C" int hyena_synth_weights(const hyena_ctx *c, const hyena_conv_desc *d,
     a.kchunks = c->N / 256;
     a.lt = c->lt;
     for (uint32_t i = 0; i < c->L; i++) {
-        a.psi_m[i] = to_montgomery(c->psi[i], c->q[i]);
         a.wscale[i] = to_montgomery(to_montgomery(h_powmod(a.c_n, c->q[i] - 2, c->q[i]), c->q[i]), c->q[i]);
     }
     hipLaunchKernelGGL(synth_weights_kernel, dim3((unsigned)blocks, c->L), dim3(256), 0, (hipStream_t)s, a);
