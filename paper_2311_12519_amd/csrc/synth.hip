@@ -75,7 +75,9 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
     uint64_t acc[kSynthPolys], psum = 0;
 #pragma unroll
     for (uint32_t pb = 0; pb < kSynthPolys; pb++) acc[pb] = 0;
-    uint32_t pc = rpow(a.O);
+    // the walk starts from c_n^{-1} 2^64 r^O (Montgomery form of
+    // c_n^{-1} 2^32 r^O), so every tap power carries the output scale
+    uint32_t pc = mont_mul(rpow(a.O), a.wscale[limb], lc);
     for (uint32_t cp0 = 0; cp0 < a.ci; cp0 += cpb) {
         const uint32_t nc = min(cpb, a.ci - cp0), nt = nc * kk;
         __syncthreads();  // the previous chunk's weights are no longer read
@@ -123,13 +125,13 @@ __global__ void __launch_bounds__(256) synth_weights_kernel(SynthArgs a) {
         if (p >= polys) break;
         // y = sum gw pw + q 2^32, in [0, 2^64) (the unsigned wrap-around of
         // the subtraction cancels because the true value is in range); the
-        // powers carry 2^32 (Montgomery form), so the reduction leaves
-        // sum gw r^e, and the product by c_n^{-1} 2^64 makes it c_n^{-1} 2^32 sum
+        // powers are c_n^{-1} 2^64 r^e, so the reduction leaves
+        // c_n^{-1} 2^32 sum gw r^e
         const uint64_t y = acc[pb] - (psum << 13) + ((uint64_t)lc.q << 32);
         // fold the high word (hi 2^32 = hi r32 mod q), then reduce:
         // hi r32 + lo <= (2^32 - 1) q < q 2^32
-        const uint32_t v = redc((uint64_t)(uint32_t)(y >> 32) * lc.r32 + (uint32_t)y, lc);
-        a.out[((size_t)p * a.L + limb) * a.N + slot] = mont_mul(v, a.wscale[limb], lc);
+        a.out[((size_t)p * a.L + limb) * a.N + slot] =
+            redc((uint64_t)(uint32_t)(y >> 32) * lc.r32 + (uint32_t)y, lc);
     }
 }
 
