@@ -123,7 +123,13 @@ int hyena_encrypt(const hyena_ctx *ctx, const int8_t *sk, const int32_t *msg,
 /*
  * Decryption m = [round(t * [c0 + c1 s]_q / q)]_t, centered in (-t/2, t/2].
  * ct: host uint32 [n][2][L][N] coefficient domain; msg: host int32 [n][N].
- * Exact whenever the noise is below Delta/2 by a margin of L * 2^-30 q/t.
+ * Computed in RNS form (Halevi, Polyakov & Shoup 2019) with the fractions of
+ * the L terms summed in 32.32 fixed point, truncated: the result is the exact
+ * rounding except where the fractional part of t v / q (v = [c0 + c1 s]_q)
+ * lies in [1/2, 1/2 + L 2^-32), where it may be one less. So it is exact
+ * whenever the noise is below Delta/2 by a margin of L * 2^-32 q/t.
+ * hyena_decrypt_device computes the same values. Errors: EINVAL (NULL, a
+ * residue not below its prime).
  */
 int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
                   size_t n, int32_t *msg);
@@ -212,7 +218,12 @@ int hyena_conv_plan(const hyena_ctx *ctx, hyena_conv_desc *desc);
 int hyena_pack_input(const hyena_conv_desc *desc, uint32_t N, const int8_t *x, int32_t *msg);
 
 /* msg: host int32 [tiles][Co][N], decrypted outputs in hyena_conv order ->
- * y: host int32 [Co][H][W], the stride-1 output (subsample for stride 2). */
+ * y: host int32 [Co][Ho][Wo], the layer's output. The server always computes
+ * the stride-1 convolution; for stride 1, Ho = H and Wo = W; for stride 2
+ * (MobileNetV1's downsampling layers, the "End-to-end Evaluation" section)
+ * Ho = ceil(H/2), Wo = ceil(W/2) and y[o][i][j] is the stride-1 output at row
+ * 2i, column 2j, which equals the stride-2 convolution with padding (k-1)/2.
+ * Errors: EINVAL (NULL, unplanned descriptor). */
 int hyena_unpack_output(const hyena_conv_desc *desc, uint32_t N, const int32_t *msg, int32_t *y);
 
 /* ------------------------------------------------------------------------
@@ -255,8 +266,11 @@ int hyena_synth_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                         const int8_t *d_w, uint32_t *d_wntt, hyena_stream_t stream);
 
 /*
- * In-place forward negacyclic NTT of P polynomials, d_poly: device uint32
- * [P][L][N] (limb i uses q_i):
+ * In-place forward negacyclic NTT of P polynomials ("Homomorphic Operations
+ * in BFV": PMult multiplies in Z_q[X]/(X^N+1), which this transform turns
+ * into pointwise products; "Optimal Parameter Selection", step 1: q = 1 mod
+ * 2N is what makes it exist), d_poly: device uint32 [P][L][N] (limb i uses
+ * q_i):
  *   A[k] = sum_j a[j] psi_i^((2 brv(k) + 1) j) mod q_i
  * (evaluation at the odd powers of psi_i, bit-reversed order; the transform
  * that turns the negacyclic product into a pointwise one, q = 1 mod 2N).
@@ -265,7 +279,13 @@ int hyena_synth_weights(const hyena_ctx *ctx, const hyena_conv_desc *desc,
  */
 int hyena_ntt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
 
-/* In-place inverse of hyena_ntt, including the factor N^{-1}. */
+/*
+ * In-place inverse of hyena_ntt, including the factor N^{-1}: the outputs of
+ * the NTT-domain products go back to the coefficient domain, where the
+ * client decrypts them ("Homomorphic Operations in BFV": the negacyclic ring
+ * Z_q[X]/(X^N+1) in which PMult and CMult multiply). d_poly: device uint32
+ * [P][L][N], residues in [0, q_i), 16-byte aligned. Errors: EINVAL, EHIP.
+ */
 int hyena_intt(const hyena_ctx *ctx, uint32_t *d_poly, size_t P, hyena_stream_t stream);
 
 /*
@@ -519,10 +539,15 @@ int hyena_simd_conv_choose_base(const hyena_ctx *ctx, uint32_t p, uint32_t kh, c
 /*
  * Walsh-Hadamard recombination across groups of c_n polynomials (the "Enabling Output Channel Packing" section):
  *   out[G][b] = sum_j H[b][j] in[G][j]  mod q_i, b, j < c_n,
- * each in[G][j] a block of `poly_words` uint32 residues whose limb is given by
- * the position: blocks are [2][L][N] ciphertexts (poly_words = 2*L*N).
+ * H the Sylvester-ordered Walsh-Hadamard matrix (H_1 = [1],
+ * H_2m = [[H_m, H_m], [H_m, -H_m]]), each in[G][j] one ciphertext of 2*L*N
+ * uint32 residues in [2][L][N] order (the limb of a residue, and so its
+ * prime, follows from its position). Applied to the Walsh components of
+ * hyena_conv (computed with weights scaled by c_n^{-1}) it gives the
+ * per-output-channel products exactly.
  * d_in, d_out: device uint32 [G][c_n][2][L][N], 16-byte aligned; d_out may
- * alias d_in. Errors: EINVAL, EHIP.
+ * alias d_in. c_n: a power of two, 1 to 64. G = 0 does nothing.
+ * Errors: EINVAL (NULL, alignment, c_n, host-only context), EHIP.
  */
 int hyena_wht_pack(const hyena_ctx *ctx, uint32_t c_n, const uint32_t *d_in,
                    uint32_t *d_out, size_t G, hyena_stream_t stream);

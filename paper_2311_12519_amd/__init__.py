@@ -266,7 +266,8 @@ def hyena_pack_input(desc: ConvDesc, N: int, x: np.ndarray) -> np.ndarray:
 
 def hyena_unpack_output(desc: ConvDesc, N: int, msg: np.ndarray) -> np.ndarray:
     msg = np.ascontiguousarray(msg, dtype=np.int32)
-    y = np.zeros((desc.Co, desc.H, desc.W), dtype=np.int32)
+    s = max(1, desc.stride)
+    y = np.zeros((desc.Co, -(-desc.H // s), -(-desc.W // s)), dtype=np.int32)
     _check(lib().hyena_unpack_output(ctypes.byref(desc), N, _np_ptr(msg, np.int32), _np_ptr(y, np.int32)))
     return y
 

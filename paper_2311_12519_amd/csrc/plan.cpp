@@ -110,14 +110,24 @@ extern "C" int hyena_pack_input(const hyena_conv_desc *d, uint32_t N, const int8
 extern "C" int hyena_unpack_output(const hyena_conv_desc *d, uint32_t N, const int32_t *msg, int32_t *y) {
     if (!d || !msg || !y) return set_error(HYENA_EINVAL, "hyena_unpack_output: NULL argument");
     if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_unpack_output: descriptor not planned");
+    // a stride-s layer keeps rows and columns 0, s, 2s, ... of the stride-1
+    // output that the server computes
+    const uint32_t s = d->stride > 1 ? d->stride : 1;
+    const uint32_t Ho = (d->H + s - 1) / s, Wo = (d->W + s - 1) / s;
     for (uint32_t tau = 0; tau < d->tiles; tau++)
         for (uint32_t o = 0; o < d->Co; o++) {
             const int32_t *m = msg + ((size_t)tau * d->Co + o) * N;
             for (uint32_t r = 0; r < d->R; r++) {
                 const uint32_t row = tau * d->R + r;
                 if (row >= d->H) break;
-                std::memcpy(y + ((size_t)o * d->H + row) * d->W, m + d->O + (size_t)r * d->Wp,
-                            sizeof(int32_t) * d->W);
+                if (row % s) continue;
+                const int32_t *src = m + d->O + (size_t)r * d->Wp;
+                int32_t *dst = y + ((size_t)o * Ho + row / s) * Wo;
+                if (s == 1) {
+                    std::memcpy(dst, src, sizeof(int32_t) * d->W);
+                } else {
+                    for (uint32_t j = 0; j < Wo; j++) dst[j] = src[(size_t)j * s];
+                }
             }
         }
     return HYENA_OK;

@@ -141,6 +141,9 @@ extern "C" int hyena_synth_weights(const hyena_ctx *c, const hyena_conv_desc *d,
                                    uint32_t *d_wntt, hyena_stream_t s) {
     if (!c || !d || !d_w || !d_wntt) return set_error(HYENA_EINVAL, "hyena_synth_weights: NULL argument");
     if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_synth_weights: descriptor not planned");
+    // the signs popc(j & b) of the Walsh combination form the Sylvester
+    // matrix only for a power of two
+    if (d->c_n & (d->c_n - 1)) return set_error(HYENA_EINVAL, "hyena_synth_weights: c_n must be a power of two");
     if (d->depthwise) return set_error(HYENA_EUNSUPPORTED, "hyena_synth_weights: depthwise layers use hyena_encode_weights");
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_synth_weights: context was created host-only");
     if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_synth_weights: N must be a multiple of 256");

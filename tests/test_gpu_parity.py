@@ -165,6 +165,45 @@ def test_synth_weights_equals_encode_weights(dev, N, L, bits, H, Ci, Co, k, c_n)
                 assert np.array_equal(got[o, g, i], want.astype(np.uint32)), (o, g, i)
 
 
+@pytest.mark.parametrize("pattern", ["all_min", "alternating", "all_max"])
+def test_synth_weights_full_int8_range_at_cn64(dev, pattern):
+    """The synthesis kernel's overflow argument at its edge: full-range int8
+    weights at c_n = 64 make Walsh weights of magnitude up to 64 * 128 = 2^13
+    (all -128: the first Walsh row is -8192; -128/127 alternating along the
+    output channels: rows of +-8160), over 576 taps per word (ci = 64 at
+    N = 16384). Every word must equal the scatter + NTT encoding, and the
+    first and last output channels the oracle's NTT of the Walsh kernel."""
+    import torch
+    say(f"synth full int8 range c_n=64 {pattern}")
+    N, L, H, Ci, Co, c_n = 16384, 2, 14, 64, 64, 64
+    ctx = ctx_for(N, L, 31)
+    d = hy.hyena_conv_plan(ctx, H, H, Ci, Co, 3, c_n=c_n)
+    assert d.ci == 64 and d.w_groups == 1
+    if pattern == "all_min":
+        w = np.full((Co, Ci, 3, 3), -128, dtype=np.int8)
+    elif pattern == "all_max":
+        w = np.full((Co, Ci, 3, 3), 127, dtype=np.int8)
+    else:
+        w = np.where((np.arange(Co) % 2 == 0)[:, None, None, None], -128, 127) * np.ones((1, Ci, 3, 3))
+        w = w.astype(np.int8)
+    dw_t = torch.from_numpy(w).cuda()
+    n = hy.wntt_words(ctx, d)
+    enc = torch.empty(n, dtype=torch.int32, device="cuda")
+    syn = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, dw_t, enc)
+    hy.hyena_synth_weights(ctx, d, dw_t, syn)
+    a, b = from_dev(enc), from_dev(syn)
+    assert np.array_equal(a, b), int(np.count_nonzero(a != b))
+    pl = orc.plan(N, H, H, Ci, Co, 3)
+    got = b.reshape(Co, d.w_groups, L, N)
+    for o in (0, 1, Co - 1):
+        G, j = divmod(o, c_n)
+        Kw = orc.walsh_kernel_residues(pl, w, c_n, ctx.primes, G, j, 0)
+        for i, q in enumerate(ctx.primes):
+            want = (orc.ntt(Kw[i], q, ctx.psi[i]).astype(np.uint64) << np.uint64(32)) % np.uint64(q)
+            assert np.array_equal(got[o, 0, i], want.astype(np.uint32)), (o, i)
+
+
 # ---------------------------------------------------------------- Walsh-Hadamard
 
 @pytest.mark.parametrize("c_n", [2, 4, 8, 64])
@@ -193,8 +232,8 @@ def run_layer(ctx, lay, c_n, seed, batch=1, fuse=True, ci_req=0, check_decrypt=T
     import torch
     N, L = ctx.N, ctx.L
     flags = hy.HYENA_FUSE_WHT if fuse else 0
-    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, depthwise=lay.depthwise, c_n=c_n,
-                           flags=flags, batch=batch, ci_req=ci_req)
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, stride=lay.stride, depthwise=lay.depthwise,
+                           c_n=c_n, flags=flags, batch=batch, ci_req=ci_req)
     pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, lay.depthwise, ci_req or None)
     w = wl.weights(seed, lay)
     s = orc.keygen(N, wl.crypto_seed(seed))
@@ -223,7 +262,8 @@ def run_layer(ctx, lay, c_n, seed, batch=1, fuse=True, ci_req=0, check_decrypt=T
         if check_decrypt:
             dec = hy.hyena_decrypt(ctx, s, got[b].reshape(-1, 2, L, N)).reshape(pl.tiles, lay.Co, N)
             y = hy.hyena_unpack_output(d, N, dec)
-            assert np.array_equal(y, orc.direct_conv(xs[b], w, lay.k, lay.depthwise))
+            want_y = orc.subsample(orc.direct_conv(xs[b], w, lay.k, lay.depthwise), lay.stride)
+            assert np.array_equal(y, want_y)
 
 
 CONFIGS = [
@@ -252,6 +292,10 @@ VARIANTS = [
     ("ci_lowered", (4096, 2, 30), wl.Layer("t", 16, 16, 16, 8, 3), 1, 1, True, 5),
     ("cn32_unfusable", (8192, 3, 31), wl.Layer("t", 14, 14, 32, 32, 3), 32, 1, True, 0),
     ("primes30_batch8", (8192, 3, 30), wl.Layer("t", 28, 28, 64, 32, 3), 1, 8, True, 0),
+    # MobileNetV1's stride-2 layer kinds (conv0 3 -> 32 at 56x56, a depthwise
+    # 3x3 at 28x28): stride-1 server work, every second row and column unpacked
+    ("stride2_conv0", (8192, 3, 31), wl.Layer("t", 56, 56, 3, 32, 3, stride=2), 1, 2, True, 0),
+    ("stride2_depthwise", (8192, 3, 31), wl.Layer("t", 28, 28, 64, 64, 3, stride=2, depthwise=True), 1, 1, True, 0),
     # the largest ring and the most limbs the 128-bit ceiling allows (14 x 31 bits)
     ("n16384_max_limbs", (16384, 14, 31), wl.Layer("t", 14, 14, 16, 8, 3), 2, 1, True, 0),
 ]

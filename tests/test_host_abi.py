@@ -2,6 +2,7 @@
 (parameters, key generation, encryption, decryption, planning, packing)
 against the oracle. No GPU is touched: contexts are created host-only."""
 import ctypes
+import math
 import os
 import re
 
@@ -48,12 +49,26 @@ def test_params_match_oracle(N, L, bits, flags):
     assert ctx.psi == [orc.find_psi(q, N) for q in ctx.primes]
 
 
-def test_security_ceiling_enforced():
+@pytest.mark.parametrize("N", [4096, 8192, 16384])
+def test_security_ceiling_enforced_at_its_edge(N):
+    # the published 128-bit ceilings (tests/golden/he_standard_ternary_128.txt):
+    # the default primes give the largest L whose sum of log2 q_i fits, one
+    # limb more is refused unless HYENA_ALLOW_INSECURE
+    table = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "he_standard_ternary_128.txt")):
+        if line.strip() and not line.startswith("#"):
+            n, b = line.split()
+            table[int(n)] = int(b)
+    primes = orc.ntt_primes(N, 16, 31)
+    L = 0
+    while sum(math.log2(q) for q in primes[:L + 1]) <= table[N]:
+        L += 1
+    assert L == {4096: 3, 8192: 7, 16384: 14}[N]
+    hy.hyena_create(N, L, flags=HOST)
     with pytest.raises(hy.HyenaError) as e:
-        hy.hyena_create(4096, 4, flags=HOST)       # 124 bits > 109
+        hy.hyena_create(N, L + 1, flags=HOST)
     assert e.value.code == hy.HYENA_EUNSUPPORTED
-    hy.hyena_create(4096, 4, flags=HOST | hy.HYENA_ALLOW_INSECURE)
-    hy.hyena_create(8192, 7, flags=HOST)           # 217 bits <= 218
+    hy.hyena_create(N, L + 1, flags=HOST | hy.HYENA_ALLOW_INSECURE)
 
 
 def test_bad_primes_rejected():
@@ -113,7 +128,8 @@ def test_plan_matches_oracle(N, L, bits, layer):
     assert d.n_in == p.tiles * p.n_groups and d.n_out == p.tiles * p.Co
 
 
-@pytest.mark.parametrize("shape", [(4096, 16, 16, 16, 16, 3), (1024, 40, 40, 3, 2, 3), (1024, 9, 9, 10, 3, 1)])
+@pytest.mark.parametrize("shape", [(4096, 16, 16, 16, 16, 3), (1024, 40, 40, 3, 2, 3), (1024, 9, 9, 10, 3, 1),
+                                   (1024, 41, 39, 2, 3, 3)])
 def test_pack_unpack_match_oracle(shape):
     N, H, W, Ci, Co, k = shape
     ctx = hy.hyena_create(N, 2, flags=HOST | hy.HYENA_ALLOW_INSECURE)
@@ -125,6 +141,9 @@ def test_pack_unpack_match_oracle(shape):
     rng = np.random.default_rng(1)
     out = rng.integers(-1000, 1000, size=(p.tiles, Co, N)).astype(np.int32)
     assert np.array_equal(hy.hyena_unpack_output(d, N, out), orc.unpack_output(p, out))
+    # a stride-2 descriptor unpacks every second row and column
+    d2 = hy.hyena_conv_plan(ctx, H, W, Ci, Co, k, stride=2)
+    assert np.array_equal(hy.hyena_unpack_output(d2, N, out), orc.subsample(orc.unpack_output(p, out), 2))
 
 
 def test_plan_noise_and_shape_errors():
@@ -182,6 +201,11 @@ def test_synth_weights_refusals():
     assert L.hyena_synth_weights(ctx.handle, ctypes.byref(dd), fake, fake, null) == hy.HYENA_EUNSUPPORTED
     assert L.hyena_synth_weights(ctx.handle, ctypes.byref(d), fake, fake, null) == hy.HYENA_EINVAL
     assert "host-only" in L.hyena_last_error().decode()
+    # a c_n that is not a power of two (which hyena_conv_plan never returns)
+    d3 = hy.hyena_conv_plan(ctx, 16, 16, 16, 12, 3)
+    d3.c_n = 3
+    assert L.hyena_synth_weights(ctx.handle, ctypes.byref(d3), fake, fake, null) == hy.HYENA_EINVAL
+    assert "power of two" in L.hyena_last_error().decode()
 
 
 def test_simd_params_match_the_papers_example_and_the_oracle():

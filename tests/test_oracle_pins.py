@@ -83,9 +83,11 @@ def test_psi_is_smallest_primitive_2n_root(N, q):
     assert all(pow(x, N, q) != q - 1 for x in range(2, psi, max(1, (psi - 2) // 4000) if psi > 10**6 else 1))
 
 
-def test_security_table_monotone_in_n():
-    vals = [orc.SECURITY_LOGQ_128[n] for n in (2048, 4096, 8192, 16384)]
-    assert all(b > 1.9 * a for a, b in zip(vals, vals[1:]))
+def test_security_table_is_the_published_one():
+    # the HE Security Standard's 128-bit ceilings for a uniform ternary secret
+    # (tests/golden/he_standard_ternary_128.txt, with its citation)
+    table = {int(n): int(b) for n, b in _golden("he_standard_ternary_128.txt")}
+    assert orc.SECURITY_LOGQ_128 == table
 
 
 # ---------------------------------------------------------------- ring arithmetic
@@ -268,6 +270,41 @@ def test_he_conv_decrypts_to_plain_conv(case):
     dec = orc.decrypt(primes, 20, s, Y).reshape(pl.tiles, pl.Co, N)
     y = orc.unpack_output(pl, dec)
     assert np.array_equal(y, orc.direct_conv(x, w, k, dw))
+
+
+STRIDED = [
+    # (N, L, H, W, Ci, Co, depthwise): MobileNetV1's stride-2 layer kinds,
+    # scaled down (conv0: 3 -> 32 channels, 3x3, stride 2; dw: depthwise 3x3,
+    # stride 2), with even and odd input sizes
+    (1024, 2, 12, 12, 3, 8, False),
+    (1024, 2, 13, 11, 3, 4, False),
+    (1024, 2, 10, 10, 6, 6, True),
+    (2048, 2, 9, 9, 8, 8, True),
+]
+
+
+@pytest.mark.parametrize("case", STRIDED)
+def test_he_conv_subsampled_equals_strided_conv(case):
+    # stride-2 layers (MobileNetV1, the "End-to-end Evaluation" section): the
+    # server computes the stride-1 product; the decrypted, unpacked output
+    # taken at every second row and column must be torch's stride-2
+    # convolution with the same padding
+    N, L, H, W, Ci, Co, dw = case
+    primes = orc.ntt_primes(N, L, 31)
+    pl = orc.plan(N, H, W, Ci, Co, 3, dw)
+    lay = wl.Layer("t", H, W, Ci, Co, 3, stride=2, depthwise=dw)
+    x = wl.activations(21, Ci, H, W)
+    w = wl.weights(22, lay)
+    s = orc.keygen(N, 23)
+    ct = orc.encrypt(primes, 20, s, orc.pack_input(pl, x).reshape(-1, N), 24)
+    Y = orc.conv_products(pl, ct.reshape(pl.tiles, pl.n_groups, 2, L, N), w, primes)
+    y = orc.unpack_output(pl, orc.decrypt(primes, 20, s, Y).reshape(pl.tiles, pl.Co, N))
+    got = orc.subsample(y, 2)
+    ref = torch.nn.functional.conv2d(torch.tensor(x, dtype=torch.float64)[None],
+                                     torch.tensor(w, dtype=torch.float64), stride=2,
+                                     padding=1, groups=Ci if dw else 1)[0]
+    assert got.shape == tuple(ref.shape)
+    assert np.array_equal(got, ref.numpy().astype(np.int64))
 
 
 def test_plan_vgg16_ciphertext_counts_by_hand():
