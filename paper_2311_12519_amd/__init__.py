@@ -17,7 +17,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhyena.so")
+# HYENA_LIB names another build of the same library (the sanitizer build of
+# the host code loads this way); by default the in-tree libhyena.so
+LIB_PATH = os.environ.get("HYENA_LIB") or os.path.join(_HERE, "libhyena.so")
 
 HYENA_OK = 0
 HYENA_EINVAL = -1

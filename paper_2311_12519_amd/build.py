@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["params.cpp", "crypto.cpp", "plan.cpp", "ntt.hip", "conv.hip", "synth.hip", "direct.hip", "client.hip", "simd.hip", "batch.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-std=c++17", "--offload-arch=gfx950", "-O3", "-fPIC", "-Wall",
+FLAGS = ["-std=c++17", "--offload-arch=gfx950", "-O3", "-fPIC", "-Wall", "-Wextra", "-Werror",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 

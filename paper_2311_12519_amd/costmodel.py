@@ -220,9 +220,10 @@ class MLP:
     """The cost model: standardised features -> log(ms), trained with Adam on
     the GPU by the library's forward / backward / Adam kernels."""
 
-    def __init__(self, seed: int = 0):
+    def __init__(self, seed: int = 0, device: str = "cuda"):
         import torch
         self.torch = torch
+        self.device = device
         n = hyena_mlp_params()
         rng = np.random.default_rng(seed)
         th = np.zeros(n, dtype=np.float32)
@@ -230,35 +231,66 @@ class MLP:
         th[0:512] = rng.normal(0, math.sqrt(2 / 8), 512)
         th[576:576 + 4096] = rng.normal(0, math.sqrt(2 / 64), 4096)
         th[4736:4800] = rng.normal(0, math.sqrt(1 / 64), 64)
-        self.theta = torch.from_numpy(th).cuda()
+        self.theta = torch.from_numpy(th).to(device)
         self.mu = self.sd = None
         self.y_mu = 0.0
+        # Adam state, kept so that training can resume from a saved model
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.step = 0
+
+    def save(self, path: str) -> None:
+        """Parameters, feature standardisation and Adam state in one .npz
+        (plain arrays, no pickled objects)."""
+        np.savez(path, theta=self.theta.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 step=np.int64(self.step), mu=np.asarray(self.mu, dtype=np.float64),
+                 sd=np.asarray(self.sd, dtype=np.float64), y_mu=np.float64(self.y_mu))
+
+    @classmethod
+    def load(cls, path: str, device: str = "cuda") -> "MLP":
+        z = np.load(path, allow_pickle=False)
+        if z["theta"].shape != (hyena_mlp_params(),):
+            raise ValueError(f"{path}: parameter count {z['theta'].shape} is not the library's MLP")
+        mdl = cls(0, device)
+        mdl.theta = mdl.torch.from_numpy(z["theta"].astype(np.float32)).to(device)
+        mdl.m = mdl.torch.from_numpy(z["m"].astype(np.float32)).to(device)
+        mdl.v = mdl.torch.from_numpy(z["v"].astype(np.float32)).to(device)
+        mdl.step = int(z["step"])
+        mdl.mu, mdl.sd, mdl.y_mu = z["mu"], z["sd"], float(z["y_mu"])
+        return mdl
 
     def _std(self, X):
         return ((X - self.mu) / self.sd).astype(np.float32)
 
-    def fit(self, X: np.ndarray, y: np.ndarray, steps: int = 4000, lr: float = 3e-3, log=None):
-        """Full-batch Adam on the mean squared error of log(ms)."""
+    def fit(self, X: np.ndarray, y: np.ndarray, steps: int = 4000, lr: float = 3e-3, log=None,
+            resume: bool = False):
+        """Full-batch Adam on the mean squared error of log(ms). With
+        ``resume`` (a loaded model), training continues from the saved
+        parameters, Adam moments and step count, with the saved feature
+        standardisation; ``steps`` more steps are taken."""
         torch = self.torch
-        self.mu = X.mean(axis=0)
-        self.sd = X.std(axis=0) + 1e-6
-        self.y_mu = float(y.mean())
+        if not resume or self.mu is None:
+            self.mu = X.mean(axis=0)
+            self.sd = X.std(axis=0) + 1e-6
+            self.y_mu = float(y.mean())
+            self.m.zero_()
+            self.v.zero_()
+            self.step = 0
         Xd = torch.from_numpy(self._std(X)).cuda()
         yd = torch.from_numpy((y - self.y_mu).astype(np.float32)).cuda()
-        n = self.theta.numel()
-        grad = torch.zeros(n, dtype=torch.float32, device="cuda")
-        m = torch.zeros_like(grad)
-        v = torch.zeros_like(grad)
+        grad = torch.zeros_like(self.theta)
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
         work = torch.empty(hyena_mlp_workspace_floats(X.shape[0]), dtype=torch.float32, device="cuda")
         hist = []
-        for step in range(1, steps + 1):
+        for i in range(1, steps + 1):
+            self.step += 1
             hyena_mlp_loss_grad(self.theta, Xd, yd, grad, loss, work)
-            hyena_mlp_adam(self.theta, grad, m, v, step, lr * (0.1 if step > 0.75 * steps else 1.0))
-            if step % 500 == 0 or step == 1:
-                hist.append((step, float(loss.item())))
+            hyena_mlp_adam(self.theta, grad, self.m, self.v, self.step,
+                           lr * (0.1 if i > 0.75 * steps else 1.0))
+            if i % 500 == 0 or i == 1:
+                hist.append((self.step, float(loss.item())))
                 if log:
-                    log(f"  step {step}: mse {hist[-1][1]:.4f}")
+                    log(f"  step {self.step}: mse {hist[-1][1]:.4f}")
         return hist
 
     def predict(self, X: np.ndarray) -> np.ndarray:
@@ -354,22 +386,30 @@ def evaluate(timer: Timer, model: MLP, shapes, log=None):
             "candidates": sum(r["candidates"] for r in rows)}
 
 
-def run(train_shapes: int = 700, per_shape: int = 4, steps: int = 4000, seed: int = 0, log=None):
+def run(train_shapes: int = 700, per_shape: int = 4, steps: int = 4000, seed: int = 0, log=None,
+        save: str | None = None, load: str | None = None):
+    """Collect timed samples of random shapes, train the MLP (or, with
+    ``load``, continue training a saved one for ``steps`` more steps; with
+    steps = 0 it is used as saved), optionally save it, and evaluate it on
+    MobileNetV1 against exhaustive search and the default parameters."""
     timer = Timer()
     mob = mobilenet_shapes()
     shapes = random_shapes(seed, train_shapes, exclude=mob)
     t0 = time.perf_counter()
-    X, y = collect(timer, shapes, per_shape, seed, log)
+    X, y = collect(timer, shapes, per_shape, seed, log) if train_shapes else (np.zeros((0, 8)), np.zeros(0))
     t_collect = time.perf_counter() - t0
     if log:
         log(f"{len(y)} training samples in {t_collect:.1f} s")
-    model = MLP(seed)
+    model = MLP.load(load) if load else MLP(seed)
     t0 = time.perf_counter()
-    hist = model.fit(X, y, steps=steps, log=log)
+    hist = model.fit(X, y, steps=steps, log=log, resume=bool(load)) if steps and len(y) else []
     t_train = time.perf_counter() - t0
+    if save:
+        model.save(save)
     report = evaluate(timer, model, mob, log)
     report.update({"train_samples": int(len(y)), "train_shapes": train_shapes, "collect_s": t_collect,
-                   "train_s": t_train, "train_mse_history": hist, "mlp": "8-64-64-1 ReLU, fp32, Adam"})
+                   "train_s": t_train, "train_mse_history": hist, "mlp": "8-64-64-1 ReLU, fp32, Adam",
+                   "adam_steps": model.step})
     return report
 
 
@@ -380,12 +420,14 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write the trained model (.npz) here")
+    ap.add_argument("--load", default=None, help="start from this saved model (training resumes)")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    rep = run(a.train_shapes, a.per_shape, a.steps, a.seed, log)
+    rep = run(a.train_shapes, a.per_shape, a.steps, a.seed, log, save=a.save, load=a.load)
     summary = {k: v for k, v in rep.items() if k != "layers"}
     if a.out:
         with open(a.out, "w") as f:

@@ -60,9 +60,10 @@ __device__ __forceinline__ uint32_t draw_item(uint32_t *counters, const uint32_t
     return lfirst[l] + slice_start(lfirst[l + 1] - lfirst[l], x) + (c - qf[l]);
 }
 
-// three resident blocks per CU (at most 168 VGPRs), as the per-layer kernel
+// resident blocks per CU as the per-layer kernel (three, at most 168 VGPRs,
+// where the LDS stages allow)
 template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, (MacLdsShape<MT, OT, WR, WO, NS>::MIN_BLOCKS))
 mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
                       uint32_t *__restrict__ counters, uint32_t total) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];

@@ -85,6 +85,11 @@ struct MacLdsShape {
     static constexpr int RND = (ROWS + 15) / 16;   // loader rounds: 256 threads x 16 B = 16 rows
     static constexpr int PROWS = RND * 16;
     static constexpr int LDS_WORDS = NS * PROWS * 64;
+    // resident blocks per CU the launch asks for: three (at most 168 VGPRs
+    // per thread) unless the LDS stages of fewer blocks already fill the
+    // CU's 160 KiB (64 bytes spared for the persistent kernel's claim words)
+    static constexpr int FIT = (160 * 1024) / (LDS_WORDS * 4 + 64);
+    static constexpr int MIN_BLOCKS = FIT < 1 ? 1 : (FIT > 3 ? 3 : FIT);
 };
 
 struct NoHook {
@@ -229,7 +234,7 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
 }
 
 template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256, 3) mac_lds_kernel(MacArgs a) {
+__global__ void __launch_bounds__(256, (MacLdsShape<MT, OT, WR, WO, NS>::MIN_BLOCKS)) mac_lds_kernel(MacArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
     // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous
     // range of logical blocks so that the tiles of one slot chunk share an L2

@@ -77,6 +77,31 @@ def test_mlp_training_fits_a_smooth_function(dev):
     assert np.mean((pred - y) ** 2) < 0.02
 
 
+def test_mlp_training_resumes_from_a_saved_model(dev, tmp_path):
+    """A saved model predicts exactly as before saving, and training resumed
+    from it (parameters, Adam moments, step count) keeps lowering the loss
+    from where it stopped."""
+    from paper_2311_12519_amd.costmodel import MLP
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, size=(800, 8))
+    y = np.cos(X[:, 0]) + X[:, 1] * X[:, 4]
+    model = MLP(seed=5)
+    h1 = model.fit(X, y, steps=600, lr=3e-3)
+    path = str(tmp_path / "m.npz")
+    model.save(path)
+    back = MLP.load(path)
+    assert np.array_equal(back.predict(X), model.predict(X))
+    assert back.step == 600
+    h2 = back.fit(X, y, steps=600, lr=1e-3, resume=True)
+    assert back.step == 1200 and h2[0][0] == 601
+    assert h2[-1][1] < h1[-1][1]
+
+
+# regret of the model's picks over the exhaustive search's, in total time of
+# the six layers
+REGRET_BOUND = 0.5
+
+
 def test_cost_model_beats_default_parameters(dev):
     """Reduced experiment: train on timings of random layer shapes, choose
     parameters for six MobileNetV1 layers, judge with exhaustive timing."""
@@ -92,4 +117,4 @@ def test_cost_model_beats_default_parameters(dev):
     rep = cm.evaluate(timer, model, layers)
     print("regret", rep["regret"], "gain over default", rep["gain_over_default"])
     assert rep["gain_over_default"] > 1.0
-    assert rep["regret"] < 0.5
+    assert rep["regret"] < REGRET_BOUND
