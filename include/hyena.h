@@ -36,6 +36,8 @@
  *    read-only and may be shared by threads and streams.
  *  - No call allocates device memory except hyena_create, hyena_batch_create
  *    and the explicit workspace queries' callers.
+ *  - hyena_decrypt_device_noalloc uses a fixed device array of the library
+ *    instead of a caller workspace (see its comment).
  */
 #ifndef HYENA_H
 #define HYENA_H
@@ -167,6 +169,26 @@ int hyena_encrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const in
                          hyena_stream_t stream);
 int hyena_decrypt_device(const hyena_ctx *ctx, const uint32_t *d_s_hat, const uint32_t *d_ct,
                          size_t n, uint32_t *d_work, int32_t *d_msg, hyena_stream_t stream);
+
+/*
+ * hyena_decrypt_device without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same messages, bit for bit, from the
+ * same kernels. The n*L*N-word workspace is a fixed array of
+ * HYENA_NOALLOC_SCRATCH_WORDS uint32 words (16 MiB) in the library's device
+ * data, which every GPU the library runs on holds until the process ends; its
+ * address on a device is recorded when the first context is created there.
+ * The call allocates nothing and is asynchronous on `stream`. All calls on one
+ * GPU share that array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and give unspecified messages; serialise them.
+ * Arguments as for hyena_decrypt_device (d_msg must not overlap d_ct or
+ * d_s_hat). Errors: EINVAL (NULL argument, host-only context, n*L*N above
+ * HYENA_NOALLOC_SCRATCH_WORDS, e.g. n > 170 at N = 8192, L = 3), EHIP.
+ * n = 0 does nothing.
+ */
+#define HYENA_NOALLOC_SCRATCH_WORDS ((size_t)4 << 20)
+int hyena_decrypt_device_noalloc(const hyena_ctx *ctx, const uint32_t *d_s_hat, const uint32_t *d_ct,
+                                 size_t n, int32_t *d_msg, hyena_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * Planning and layout (host).

@@ -85,6 +85,7 @@ _SIGS = {
     "hyena_secret_prepare": [_P, _P, _P, _P],
     "hyena_encrypt_device": [_P, _P, _P, _sz, _u64, _P, _P, _P],
     "hyena_decrypt_device": [_P, _P, _P, _sz, _P, _P, _P],
+    "hyena_decrypt_device_noalloc": [_P, _P, _P, _sz, _P, _P],
     "hyena_simd_params": [_u32, _u32, _u32, _P, _P, _P],
     "hyena_simd_encode": [_P, _P, _sz, _P, _P],
     "hyena_simd_decode": [_P, _P, _sz, _P, _P],
@@ -365,6 +366,20 @@ def hyena_decrypt_device(ctx: Ctx, d_s_hat, d_ct, d_work, d_msg, stream=None) ->
         raise ValueError(f"d_work has {d_work.numel()} elements, needs {n * ctx.L * ctx.N}")
     _check(lib().hyena_decrypt_device(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_ct, "int32"), n,
                                       _dev_ptr(d_work, "int32"), _dev_ptr(d_msg, "int32"), _stream(stream)))
+
+
+HYENA_NOALLOC_SCRATCH_WORDS = 4 << 20
+
+
+def hyena_decrypt_device_noalloc(ctx: Ctx, d_s_hat, d_ct, d_msg, stream=None) -> None:
+    """hyena_decrypt_device with the library's fixed device workspace
+    (n*L*N <= HYENA_NOALLOC_SCRATCH_WORDS; the library refuses larger n)."""
+    n = d_ct.numel() // (2 * ctx.L * ctx.N)
+    _need(d_ct, n * 2 * ctx.L * ctx.N, "d_ct")
+    _need(d_msg, n * ctx.N, "d_msg")
+    _need(d_s_hat, ctx.L * ctx.N, "d_s_hat")
+    _check(lib().hyena_decrypt_device_noalloc(ctx.handle, _dev_ptr(d_s_hat, "int32"), _dev_ptr(d_ct, "int32"), n,
+                                              _dev_ptr(d_msg, "int32"), _stream(stream)))
 
 
 def hyena_simd_params(n: int, p: int, kmax: int):

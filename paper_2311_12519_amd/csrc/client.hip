@@ -9,6 +9,8 @@
 // with e the rounded Gaussian drawn from sm64(seed, 2(m N + j) + 1).
 // Decryption: v = [c0 + INTT(NTT(c1) . NTT(s))]_{q_i}, then the RNS rounding of
 // t v / q of Halevi, Polyakov and Shoup, in the same integer steps as the host.
+#include <mutex>
+
 #include "bfv.h"
 
 namespace {
@@ -174,7 +176,39 @@ ClientConst client_constants(const hyena_ctx *c) {
     return cc;
 }
 
+// Workspace of hyena_decrypt_device_noalloc: a file-scope device array that
+// every GPU the library runs on holds for the life of the process (its own
+// copy, at its own address). Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address that hipGetSymbolAddress returned for the device, recorded
+// once per device when a context is created on it.
+__device__ __align__(256) uint32_t scratch[HYENA_NOALLOC_SCRATCH_WORDS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch[kMaxDevices] = {};
+
+uint32_t *scratch_for(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
+
 }  // namespace
+
+// Called by hyena_create with the context's device current.
+int client_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices)
+        return set_error(HYENA_EUNSUPPORTED, "hyena_create: device index above the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return HYENA_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return set_error(HYENA_EHIP, std::string("hyena_create: scratch address: ") + hipGetErrorString(e));
+    g_scratch[device] = (uint32_t *)p;
+    return HYENA_OK;
+}
 
 extern "C" int hyena_secret_prepare(const hyena_ctx *c, const int8_t *d_sk, uint32_t *d_s_hat, hyena_stream_t stream) {
     static const char *who = "hyena_secret_prepare";
@@ -250,4 +284,20 @@ extern "C" int hyena_decrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_work, d_msg, n, c->logN,
                        L, c->log2_t, c->lt, cc);
     return launched(who);
+}
+
+extern "C" int hyena_decrypt_device_noalloc(const hyena_ctx *c, const uint32_t *d_s_hat, const uint32_t *d_ct,
+                                            size_t n, int32_t *d_msg, hyena_stream_t stream) {
+    static const char *who = "hyena_decrypt_device_noalloc";
+    if (!c) return set_error(HYENA_EINVAL, std::string(who) + ": NULL argument");
+    if (int rc = check_ctx(c, who)) return rc;
+    if ((size_t)c->L * c->N > HYENA_NOALLOC_SCRATCH_WORDS ||
+        n > HYENA_NOALLOC_SCRATCH_WORDS / ((size_t)c->L * c->N))
+        return set_error(HYENA_EINVAL, std::string(who) + ": n * L * N above the scratch size of " +
+                                           std::to_string(HYENA_NOALLOC_SCRATCH_WORDS) + " words");
+    uint32_t *work = scratch_for(c->device);
+    if (!work) return set_error(HYENA_EINVAL, std::string(who) + ": no scratch address for the context's device");
+    // the same kernels as hyena_decrypt_device, with this device's scratch as
+    // the workspace (it is written whole before it is read: nothing to clear)
+    return hyena_decrypt_device(c, d_s_hat, d_ct, n, work, d_msg, stream);
 }

@@ -44,6 +44,9 @@ struct hyena_ctx {
 
 // error reporting
 int set_error(int code, const std::string &msg);
+// Record this device's address of the no-allocation workspace (client.hip);
+// hyena_create calls it with the context's device current.
+int client_scratch_setup(int device);
 #define HIP_TRY(expr)                                                          \
     do {                                                                       \
         hipError_t _e = (expr);                                                \

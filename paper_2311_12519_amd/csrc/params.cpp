@@ -190,6 +190,12 @@ extern "C" int hyena_create(uint32_t N, uint32_t L, const uint32_t *primes, uint
         return HYENA_OK;
     }
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) {
+        if (int rc = client_scratch_setup(c->device)) {
+            hyena_destroy(c);
+            return rc;
+        }
+    }
     const size_t bytes = sizeof(uint32_t) * (size_t)L * N;
     if (e == hipSuccess) e = hipMalloc((void **)&c->d_fw, bytes);
     if (e == hipSuccess) e = hipMalloc((void **)&c->d_iw, bytes);
