@@ -110,6 +110,12 @@ def parse():
                     help="skip the supplementary run of the SIMD-setting kernels (HRot, batch encoding, PMult)")
     ap.add_argument("--no-synth", action="store_true",
                     help="skip the supplementary run of the evaluation-domain weight synthesis")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the supplementary run of the ImageNet ResNet layers with Walsh-Hadamard packing")
+    ap.add_argument("--no-costmodel", action="store_true",
+                    help="skip the supplementary run of the learned cost model on MobileNetV1")
+    ap.add_argument("--cm-shapes", type=int, default=700,
+                    help="random layer shapes timed to train the cost model (4 candidates each)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -483,6 +489,12 @@ def main():
         out["direct_depthwise"] = direct_depthwise(args, hy, wl, torch)
     if not args.no_simd:
         out["simd"] = simd_kernels(hy, torch)
+    c3_parity = None
+    if not args.no_config3:
+        out["config3"], c3_parity = walsh_layers(args, hy, wl, torch)
+    c5_parity = None
+    if not args.no_costmodel:
+        out["config5"], c5_parity = mobilenet_costmodel(args, hy, wl, torch)
     if not args.no_cpu_baseline:
         import oracle as orc
         log("cpu baseline (oracle), with the parity check of the sampled outputs ...")
@@ -493,6 +505,10 @@ def main():
             out["primes_below_2^30"]["parity_checked_outputs"] = n_alt
         out["parity_checked_outputs"] = checked - n_alt
         log(f"parity ok: {checked} sampled output ciphertexts bit-exact")
+        if c3_parity is not None:
+            out["config3"]["parity_checked_outputs"] = check_walsh_layers(orc, c3_parity)
+        if c5_parity is not None:
+            out["config5"]["end_to_end"]["parity_checked_outputs"] = check_mobilenet(orc, c5_parity)
     else:
         log("no oracle run: outputs not checked (--no-cpu-baseline)")
     print(json.dumps(out))
@@ -885,6 +901,294 @@ def simd_conv_layer(hy, torch, best, k, kh):
         f"output-packed {res['output_packed']['ms']:.3f} ms "
         f"(coefficient path {res['coefficient_path']['ms']:.3f} ms)")
     return res
+
+
+def walsh_layers(args, hy, wl, torch):
+    """Supplementary figure: the ImageNet ResNet-shaped layers with the
+    paper's Walsh-Hadamard output-channel packing and lazy reduction
+    (56x56x64 -> 64 at c_n = 4, 14x14x256 -> 256 at c_n = 64; N = 16384, four
+    primes below 2^31; one image each, as the workload states). Each layer is
+    timed as forward NTT of its inputs, multiply-accumulate over the Walsh
+    weights with the butterflies (fused into the MAC's epilogue where c_n
+    divides the register tile's outputs, else the separate butterfly pass
+    that hyena_conv launches), and inverse NTT; beside it the same layer
+    with c_n = 1 (no Walsh step) and with the butterflies always unfused
+    (hyena_conv without HYENA_FUSE_WHT, then hyena_wht_pack). Every variant
+    gives the same output ciphertexts: two per layer and variant are copied to
+    the host for the cpu_baseline leg to check against the oracle."""
+    N, L = 16384, 4
+    log("supplementary run: ResNet layers with Walsh-Hadamard packing (N = 16384, L = 4) ...")
+    ctx = hy.hyena_create(N, L)
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    wk = wl.WORKLOADS[3]
+    rows, parity = [], []
+    for li, (lay, cn) in enumerate(zip(wk.layers, wk.c_n)):
+        seed = wl.layer_seed(3, li)
+        w_host = wl.weights(seed, lay)
+        w = torch.from_numpy(w_host).to(dev)
+        variants = [("walsh", cn, True), ("walsh_unfused", cn, False), ("no_walsh", 1, True)]
+        d0 = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=1, flags=hy.HYENA_FUSE_WHT)
+        ct0 = torch.empty(d0.n_in * 2 * L * N, dtype=torch.int32, device=dev)
+        v = ct0.view(-1, L, N)
+        gen.manual_seed(seed)
+        for i, q in enumerate(ctx.primes):
+            v[:, i, :] = torch.randint(0, q, v[:, i, :].shape, generator=gen, device=dev,
+                                       dtype=torch.int64).to(torch.int32)
+        ct = torch.empty_like(ct0)
+        out = torch.empty(d0.n_out * 2 * L * N, dtype=torch.int32, device=dev)
+        row = {"layer": f"{lay.H}x{lay.W}x{lay.Ci}->{lay.Co} 3x3", "c_n": cn, "input_ciphertexts": d0.n_in,
+               "output_ciphertexts": d0.n_out, "channels_per_ciphertext": d0.ci}
+        macs = d0.n_groups * lay.Co * d0.tiles * 2 * L * N
+        sel = [(0, 0), (d0.tiles - 1, lay.Co - 1)]
+        samples = {}
+        for name, c, fuse in variants:
+            d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=c,
+                                   flags=hy.HYENA_FUSE_WHT if fuse else 0)
+            wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device=dev)
+            hy.hyena_encode_weights(ctx, d, w, wn)
+            G = d.n_out // c
+
+            def run(ev=None):
+                ct.copy_(ct0)
+                if ev:
+                    ev[0].record()
+                hy.hyena_ntt(ctx, ct)
+                if ev:
+                    ev[1].record()
+                hy.hyena_conv(ctx, d, ct, wn, out)
+                if not fuse and c > 1:
+                    hy.hyena_wht_pack(ctx, c, out, out, G)
+                if ev:
+                    ev[2].record()
+                hy.hyena_intt(ctx, out)
+                if ev:
+                    ev[3].record()
+
+            out.fill_(0)
+            run()
+            torch.cuda.synchronize()
+            o5 = out.view(d0.tiles, lay.Co, 2, L, N)
+            samples[name] = [o5[t, oc].cpu().numpy().view(np.uint32).copy() for t, oc in sel]
+            best = None
+            for _ in range(max(3, args.steps)):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                run(ev)
+                torch.cuda.synchronize()
+                t = (ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3]))
+                if best is None or sum(t) < sum(best):
+                    best = t
+            w_bytes = wn.numel() * 4
+            io_bytes = (d.n_in + d.n_out) * 2 * L * N * 4
+            mac_gbs = (w_bytes + io_bytes) / (best[1] * 1e-3) / 1e9
+            row[name] = {"c_n": c, "butterflies": ("HYENA_FUSE_WHT" if fuse else "hyena_wht_pack") if c > 1 else None,
+                         "ms": sum(best), "ntt_ms": best[0], "mac_ms": best[1], "intt_ms": best[2],
+                         "coeff_macs_per_s": macs / (sum(best) * 1e-3),
+                         "mac_coeff_macs_per_s": macs / (best[1] * 1e-3),
+                         "mac_GBs": mac_gbs, "mac_hbm_frac": mac_gbs / HBM_PEAK_GBS,
+                         "mac_algorithmic_bytes": w_bytes + io_bytes}
+            del wn
+        row["coeff_macs"] = macs
+        rows.append(row)
+        parity.append((lay, ct0.cpu().numpy().view(np.uint32).reshape(d0.tiles, d0.n_groups, 2, L, N).copy(),
+                       w_host, sel, samples))
+        log(f"  {row['layer']} c_n={cn}: {row['walsh']['ms']:.3f} ms (unfused {row['walsh_unfused']['ms']:.3f}, "
+            f"c_n=1 {row['no_walsh']['ms']:.3f}); MAC {row['walsh']['mac_GBs']:.0f} GB/s")
+        del ct0, ct, out
+    primes = list(ctx.primes)
+    hy.hyena_destroy(ctx)
+    res = {"workload": "ImageNet ResNet layers 56x56x64->64 (c_n=4) and 14x14x256->256 (c_n=64), 3x3 pad 1, "
+                       "1 image, N=16384, 4 primes < 2^31, lazy reduction",
+           "layers": rows, "parity_checked_outputs": 0,
+           "ms_walsh": sum(r["walsh"]["ms"] for r in rows),
+           "ms_no_walsh": sum(r["no_walsh"]["ms"] for r in rows)}
+    return res, (N, primes, parity)
+
+
+def check_walsh_layers(orc, c3):
+    """The oracle's products for the sampled outputs of walsh_layers; every
+    variant must equal them on every coefficient."""
+    N, primes, parity = c3
+    checked = 0
+    for lay, ct, w, sel, samples in parity:
+        pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k)
+        want = orc.conv_products(pl, ct, w, primes, outputs=sel)
+        for name, got in samples.items():
+            for u, (tau, oc) in enumerate(sel):
+                if not np.array_equal(got[u], want[u]):
+                    raise SystemExit(f"parity failure: ResNet layer {lay.name} variant {name} output {(tau, oc)}")
+                checked += 1
+    log(f"parity ok: {checked} sampled output ciphertexts of the Walsh-packed ResNet layers")
+    return checked
+
+
+class PickedLayer:
+    pass
+
+
+def run_picks(hy, wl, torch, picks, n_img, steps, warmup, batched, sample=False):
+    """MobileNetV1's 27 layers for n_img images, each computed with its picked
+    parameters (ring degree, limbs, channels per ciphertext, Walsh group, path).
+    batched: NTT-path layers sharing (N, L) run as one tuned batch object
+    (persistent multiply-accumulate, hipGraph), direct-path layers as one
+    hyena_conv_direct launch over all images; otherwise every image and layer
+    is launched on its own (ntt, conv, intt). Returns the time per step and,
+    with `sample`, the host copies the parity check needs."""
+    from paper_2311_12519_amd import costmodel as cm
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    ctxs, items = {}, []
+    for li, (lay, c) in enumerate(zip(wl.mobilenet_v1_layers(), picks)):
+        if (c.N, c.L) not in ctxs:
+            ctxs[(c.N, c.L)] = hy.hyena_create(c.N, c.L)
+        ctx = ctxs[(c.N, c.L)]
+        o = PickedLayer()
+        o.lay, o.c, o.ctx = lay, c, ctx
+        mk = dict(depthwise=lay.depthwise, c_n=c.c_n, ci_req=c.ci, flags=hy.HYENA_FUSE_WHT)
+        o.d_b = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, batch=n_img, **mk)
+        o.d_1 = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, batch=1, **mk)
+        LN = c.L * c.N
+        o.in_w, o.out_w = o.d_1.n_in * 2 * LN, o.d_1.n_out * 2 * LN
+        seed = wl.layer_seed(5, li)
+        o.w_host = wl.weights(seed, lay)
+        o.w = torch.from_numpy(o.w_host).to(dev)
+        o.ct0 = torch.empty((n_img, o.in_w), dtype=torch.int32, device=dev)
+        v = o.ct0.view(-1, c.L, c.N)
+        gen.manual_seed(seed)
+        for i, q in enumerate(ctx.primes):
+            v[:, i, :] = torch.randint(0, q, v[:, i, :].shape, generator=gen, device=dev,
+                                       dtype=torch.int64).to(torch.int32)
+        o.ct = o.ct0.clone()
+        o.out = torch.empty((n_img, o.out_w), dtype=torch.int32, device=dev)
+        if not c.direct:
+            o.wn = torch.empty(hy.wntt_words(ctx, o.d_b), dtype=torch.int32, device=dev)
+            hy.hyena_encode_weights(ctx, o.d_b, o.w, o.wn)
+        items.append(o)
+    del cm
+    batches = []
+    if batched:
+        flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH
+        for key, ctx in ctxs.items():
+            group = [o for o in items if not o.c.direct and (o.c.N, o.c.L) == key]
+            if group:
+                batches.append(hy.hyena_batch_create(ctx, [(o.d_b, o.ct, o.wn, o.out) for o in group], flags))
+
+    def step():
+        if batched:
+            for b in batches:
+                hy.hyena_batch_run(b)
+            for o in items:
+                if o.c.direct:
+                    hy.hyena_conv_direct(o.ctx, o.d_b, o.ct, o.w, o.out)
+        else:
+            for o in items:
+                for b in range(n_img):
+                    if o.c.direct:
+                        hy.hyena_conv_direct(o.ctx, o.d_1, o.ct[b], o.w, o.out[b])
+                    else:
+                        hy.hyena_ntt(o.ctx, o.ct[b])
+                        hy.hyena_conv(o.ctx, o.d_1, o.ct[b], o.wn, o.out[b])
+                        hy.hyena_intt(o.ctx, o.out[b])
+
+    samples = None
+    if sample:
+        for o in items:
+            o.ct.copy_(o.ct0)
+        torch.cuda.synchronize()
+        step()
+        torch.cuda.synchronize()
+        samples = []
+        for o in items:
+            c, d = o.c, o.d_1
+            o5 = o.out[0].view(d.tiles, o.lay.Co, 2, c.L, c.N)
+            sel = [(0, 0), (d.tiles - 1, o.lay.Co - 1)]
+            samples.append((o.lay, c, list(o.ctx.primes),
+                            o.ct0[0].cpu().numpy().view(np.uint32).reshape(d.tiles, d.n_groups, 2, c.L, c.N).copy(),
+                            o.w_host, sel, [o5[t, oc].cpu().numpy().view(np.uint32).copy() for t, oc in sel]))
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    for b in batches:
+        hy.hyena_batch_destroy(b)
+    for o in items:
+        o.ct = o.ct0 = o.out = o.w = None
+        o.wn = None
+    for ctx in ctxs.values():
+        hy.hyena_destroy(ctx)
+    torch.cuda.empty_cache()
+    return ms, samples
+
+
+def mobilenet_costmodel(args, hy, wl, torch):
+    """Supplementary figure: the learned cost model on MobileNetV1 (27 layers
+    at 224x224). The model (FP32 MLP 8-64-64-1, trained on the GPU by the
+    library's own kernels) is trained on timed samples of random layer shapes
+    (never MobileNetV1's), then picks (N, L, c_i, c_n, path) for every layer
+    among the secure, decryptable candidates; exhaustive timing of every
+    candidate judges its regret, and the default parameters (N = 8192, fewest
+    limbs, widest channel partition, c_n = 1, NTT path) its gain. End to end,
+    8 images of the whole network run with the default parameters launched per
+    image and layer (the plain path), and batched with the model's and with
+    the exhaustive search's picks."""
+    from paper_2311_12519_amd import costmodel as cm
+    log(f"supplementary run: learned cost model on MobileNetV1 ({args.cm_shapes} training shapes) ...")
+    t0 = time.perf_counter()
+    rep = cm.run(train_shapes=args.cm_shapes, per_shape=4, steps=4000, seed=0, log=log)
+    t_cm = time.perf_counter() - t0
+    rows = rep["layers"]
+    log(f"  {rep['train_samples']} samples, regret {rep['regret']:.4f}, gain over default "
+        f"{rep['gain_over_default']:.3f} ({t_cm:.1f} s)")
+    picks = {"model": [cm.Cand(**r["model"]) for r in rows],
+             "exhaustive": [cm.Cand(**r["best"]) for r in rows],
+             "default": [cm.Cand(**r["default"]) for r in rows]}
+    n_img, steps = args.images, max(2, min(args.steps, 5))
+    e2e = {"images": n_img, "layers": len(rows)}
+    samples = {}
+    for name, which, batched in [("default_plain", "default", False), ("default_batched", "default", True),
+                                 ("model_batched", "model", True), ("exhaustive_batched", "exhaustive", True)]:
+        want = name in ("default_plain", "model_batched") and not args.no_check
+        ms, smp = run_picks(hy, wl, torch, picks[which], n_img, steps, 1, batched, sample=want)
+        e2e[f"{name}_ms"] = ms
+        if smp is not None:
+            samples[name] = smp
+        log(f"  MobileNetV1 x {n_img}: {name} {ms:.2f} ms")
+    e2e["speedup_model_batched_vs_plain"] = e2e["default_plain_ms"] / e2e["model_batched_ms"]
+    e2e["speedup_model_batched_vs_default_batched"] = e2e["default_batched_ms"] / e2e["model_batched_ms"]
+    e2e["layers_per_s_model_batched"] = n_img * len(rows) / (e2e["model_batched_ms"] * 1e-3)
+    e2e["parity_checked_outputs"] = 0
+    res = {"workload": f"MobileNetV1 27 layers at 224x224; search N in {{4096, 8192, 16384}} x limbs meeting "
+                       f"128-bit security x channel partitions x c_n in {{1, 2, 4}} x NTT/direct path",
+           "mlp": rep["mlp"], "train_samples": rep["train_samples"], "train_shapes": rep["train_shapes"],
+           "candidates": rep["candidates"], "regret": rep["regret"], "gain_over_default": rep["gain_over_default"],
+           "total_best_ms": rep["total_best_ms"], "total_model_ms": rep["total_model_ms"],
+           "total_default_ms": rep["total_default_ms"], "collect_s": rep["collect_s"], "train_s": rep["train_s"],
+           "exhaustive_search_s": rep["exhaustive_search_s"], "model_search_s": rep["model_search_s"],
+           "wall_s": t_cm, "end_to_end": e2e,
+           "picks": [{"layer": lay.name, "model": r["model"], "exhaustive": r["best"], "model_ms": r["model_ms"],
+                      "best_ms": r["best_ms"], "default_ms": r["default_ms"]}
+                     for lay, r in zip(wl.mobilenet_v1_layers(), rows)]}
+    return res, samples
+
+
+def check_mobilenet(orc, samples):
+    """The oracle's products for the sampled outputs of the MobileNetV1 runs
+    (default parameters per image, the model's picks batched)."""
+    checked = 0
+    for name, smp in samples.items():
+        for lay, c, primes, ct, w, sel, got in smp:
+            pl = orc.plan(c.N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, lay.depthwise, c.ci)
+            want = orc.conv_products(pl, ct, w, primes, outputs=sel)
+            for u, (tau, oc) in enumerate(sel):
+                if not np.array_equal(got[u], want[u]):
+                    raise SystemExit(f"parity failure: MobileNetV1 {name} layer {lay.name} output {(tau, oc)}")
+                checked += 1
+    log(f"parity ok: {checked} sampled MobileNetV1 output ciphertexts")
+    return checked
 
 
 def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):

@@ -99,7 +99,7 @@ def test_mlp_training_resumes_from_a_saved_model(dev, tmp_path):
 
 # regret of the model's picks over the exhaustive search's, in total time of
 # the six layers
-REGRET_BOUND = 0.5
+REGRET_BOUND = 0.15
 
 
 def test_cost_model_beats_default_parameters(dev):
