@@ -154,6 +154,13 @@ def setup(args, hy, wl, torch):
         o.d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device=dev)
         o.d_w = torch.from_numpy(o.w).to(dev)
         hy.hyena_encode_weights(ctx, d, o.d_w, o.d_wn)
+        # layers with at most 18 taps per weight word also get their integer
+        # taps, so the autotuner can weigh synthesizing the weight words in the
+        # multiply-accumulate against streaming them
+        o.d_taps = None
+        if d.ci * d.k * d.k <= 18:
+            o.d_taps = torch.empty(hy.synth_taps_words(d), dtype=torch.int32, device=dev)
+            hy.hyena_synth_taps(ctx, d, o.d_w, o.d_taps)
         in_words = d.n_in * 2 * L * N
         out_words = d.n_out * 2 * L * N
         o.ct0 = torch.empty((args.images, in_words), dtype=torch.int32, device=dev)
@@ -350,7 +357,7 @@ def main():
     if "tuned" in modes:
         log("autotuning + graph capture ...")
         flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING
-        batch = hy.hyena_batch_create(ctx, [(o.desc_b, o.ct, o.d_wn, o.out) for o in layers], flags)
+        batch = hy.hyena_batch_create(ctx, [(o.desc_b, o.ct, o.d_wn, o.out, o.d_taps) for o in layers], flags)
 
     steps = {
         "plain": lambda: step_plain(ctx, layers, hy, n_img),
@@ -407,6 +414,7 @@ def main():
         torch.cuda.synchronize()
         enc.append(e0.elapsed_time(e1))
     synth = None if args.no_synth else weight_synthesis(ctx, layers, hy, torch)
+    synth_mac = None if args.no_synth else synth_in_mac(ctx, layers, hy, torch)
     out = {
         "metric": "HE-conv coeff-MACs/s + layers/s at N=8192, batched/tuned vs plain; bit-exact",
         "value": head["coeff_macs_per_s"],
@@ -432,6 +440,11 @@ def main():
     }
     if synth is not None:
         out["weight_synthesis"] = synth
+    if synth_mac is not None:
+        out["synth_in_mac"] = synth_mac
+    if head_mode == "tuned":
+        out["synthesized_layers"] = [o.lay.name for o, sid in zip(layers, head["schedules"]["mac_sched"])
+                                     if hy.hyena_conv_schedule_taps(sid) > 0]
     if "plain" in res:
         for m in ("batched", "tuned"):
             if m in res:
@@ -439,7 +452,12 @@ def main():
     if "kernels_ms" in head:
         km = head["kernels_ms"]
         mac_ms = km["mac"]
-        w_bytes = sum(o.d_wn.numel() * 4 for o in layers)
+        # layers whose multiply-accumulate synthesizes the weight words read
+        # only their integer taps
+        syn = [False] * len(layers)
+        if head_mode == "tuned":
+            syn = [hy.hyena_conv_schedule_taps(sid) > 0 for sid in head["schedules"]["mac_sched"]]
+        w_bytes = sum((o.d_taps.numel() if sy else o.d_wn.numel()) * 4 for o, sy in zip(layers, syn))
         io_bytes = sum((o.in_words + o.out_words) * 4 for o in layers) * n_img
         mac_gbs = (w_bytes + io_bytes) / (mac_ms * 1e-3) / 1e9
         ach = total_macs / (mac_ms * 1e-3) / 1e12
@@ -553,6 +571,57 @@ def weight_synthesis(ctx, layers, hy, torch):
         f"layers with <= 9 taps per word: {sum(r['encode_ms'] for r in c1):.3f} against "
         f"{sum(r['synth_ms'] for r in c1):.3f} ms")
     return {"encode_ms": tot_e, "synth_ms": tot_s, "bit_exact": True, "layers": rows}
+
+
+def synth_in_mac(ctx, layers, hy, torch):
+    """Supplementary figure: the multiply-accumulate of every VGG-16 layer with
+    at most 18 taps per weight word (conv1_1 ... conv3_3), streaming the
+    NTT-domain weights against synthesizing them in the block from the integer
+    taps (hyena_conv_synth's schedules), each at its fastest schedule, for the
+    batch of 8 images and for one image. Both must give the same output words
+    (the benchmark stops otherwise)."""
+    log("supplementary run: weights synthesized in the multiply-accumulate against streamed ...")
+    scheds = hy.hyena_conv_schedules()
+    streamed = [sid for sid, info in enumerate(scheds) if info[0] and hy.hyena_conv_schedule_taps(sid) == 0]
+
+    def timed(fn):
+        fn()
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    rows = []
+    for o in layers:
+        if o.d_taps is None:
+            continue
+        T = o.desc_b.ci * o.desc_b.k * o.desc_b.k
+        synth = [sid for sid in range(len(scheds)) if hy.hyena_conv_schedule_taps(sid) >= T]
+        row = {"layer": o.lay.name, "taps_per_word": T, "weight_bytes_streamed": o.d_wn.numel() * 4,
+               "taps_bytes": o.d_taps.numel() * 4}
+        for tag, d, ct, out in (("images_8", o.desc_b, o.ct, o.out), ("images_1", o.desc_1, o.ct[0], o.out[0])):
+            ts = {sid: timed(lambda: hy.hyena_conv_tiled(ctx, d, ct, o.d_wn, out, sid)) for sid in streamed}
+            bs = min(ts, key=ts.get)
+            hy.hyena_conv_tiled(ctx, d, ct, o.d_wn, out, bs)
+            ref = out.clone()
+            ty = {sid: timed(lambda: hy.hyena_conv_tiled(ctx, d, ct, o.d_taps, out, sid)) for sid in synth}
+            by = min(ty, key=ty.get)
+            if not torch.equal(out, ref):
+                raise SystemExit(f"synthesized and streamed weights give different outputs on {o.lay.name}")
+            row[tag] = {"streamed_ms": ts[bs], "streamed_sched": bs, "synth_ms": ty[by], "synth_sched": by,
+                        "synth_over_streamed": ty[by] / ts[bs]}
+            del ref
+        rows.append(row)
+        log(f"  {o.lay.name}: 8 images streamed {row['images_8']['streamed_ms']:.3f} ms, synthesized "
+            f"{row['images_8']['synth_ms']:.3f}; 1 image {row['images_1']['streamed_ms']:.3f} against "
+            f"{row['images_1']['synth_ms']:.3f}")
+    return {"layers": rows, "outputs_equal": True}
 
 
 def wht_bandwidth(ctx, layers, hy, torch):
@@ -1198,7 +1267,7 @@ def alt_primes(args, hy, wl, torch, layers31, n_img, total_macs):
     parity set for the cpu_baseline leg."""
     import argparse
     for o in layers31:   # release the first run's buffers
-        o.ct = o.ct0 = o.out = o.d_wn = o.d_w = None
+        o.ct = o.ct0 = o.out = o.d_wn = o.d_w = o.d_taps = None
     torch.cuda.empty_cache()
     a = argparse.Namespace(**vars(args))
     a.primes = 30

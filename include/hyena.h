@@ -376,14 +376,48 @@ int hyena_conv_direct(const hyena_ctx *ctx, const hyena_conv_desc *desc, const u
  * the schedule hyena_conv uses for a planned descriptor. hyena_conv_tiled is
  * hyena_conv with an explicit schedule (EINVAL if it does not exist or does
  * not fit the layer: depthwise layers need a register-only schedule whose ot
- * divides ci).
+ * divides ci). hyena_conv_schedule_taps returns 0 for a schedule that reads
+ * NTT-domain weights and, for one that synthesizes them (hyena_conv_synth),
+ * the most taps per weight word it takes; hyena_conv_tiled then reads d_wntt
+ * as the int32 taps of hyena_synth_taps.
  */
 int hyena_conv_schedules(int *count);
 int hyena_conv_schedule_info(int sched, int *info);
+int hyena_conv_schedule_taps(int sched);
 int hyena_conv_default_schedule(const hyena_conv_desc *desc);
 int hyena_conv_tiled(const hyena_ctx *ctx, const hyena_conv_desc *desc,
                      const uint32_t *d_ct_ntt, const uint32_t *d_wntt,
                      uint32_t *d_out_ntt, int sched, hyena_stream_t stream);
+
+/*
+ * Weights kept as integers, their NTT-domain words synthesized inside the
+ * multiply-accumulate (the paper stores the kernels as small integers rather
+ * than as plaintext polynomials, "Enabling Output Channel Packing"; the words
+ * are the evaluations at the NTT points that hyena_synth_weights writes out).
+ *
+ * hyena_synth_taps: the Walsh-combined integer taps of a standard layer,
+ *   d_taps[o][g][t] = sum_b H[j][b] f[G c_n + b][g ci + c'][di][dj]
+ * for o = G c_n + j, input group g < w_groups, tap t = c' k^2 + di k + dj <
+ * T = ci k^2 (0 past the last input channel and for T <= t < T4, T4 = T
+ * rounded up to a multiple of 4). d_w: device int8 [Co][Ci][k][k]; d_taps:
+ * device int32 [Co][w_groups][T4], 4-byte aligned (VGG-16's conv2_2: 786 KB
+ * against 1.5 GiB of NTT-domain words). Errors: EINVAL (NULL, unplanned,
+ * c_n not a power of two, host-only context), EUNSUPPORTED (depthwise), EHIP.
+ *
+ * hyena_conv_synth: hyena_conv (same d_ct_ntt, d_out_ntt, flags and result,
+ * bit for bit) with the weight word of (o, g) at NTT slot s computed in the
+ * block that uses it as sum_t taps[o][g][t] c_n^{-1} 2^32 r_s^e_t mod q_i
+ * (r_s = psi_i^(2 brv(s) + 1), e_t the exponent of tap t in the kernel
+ * polynomial) instead of read from an encoded-weight array: T multiply-adds
+ * and one reduction per word and block, in place of streaming 4 bytes per
+ * word. Layers with at most 18 taps per weight word (ci <= 2 at k = 3,
+ * ci <= 18 at k = 1). Errors: EINVAL, EUNSUPPORTED (depthwise, more than 18
+ * taps per word), EHIP.
+ */
+int hyena_synth_taps(const hyena_ctx *ctx, const hyena_conv_desc *desc, const int8_t *d_w,
+                     int32_t *d_taps, hyena_stream_t stream);
+int hyena_conv_synth(const hyena_ctx *ctx, const hyena_conv_desc *desc, const uint32_t *d_ct_ntt,
+                     const int32_t *d_taps, uint32_t *d_out_ntt, hyena_stream_t stream);
 
 /* ------------------------------------------------------------------------
  * The paper's own SIMD setting (batch encoding with a prime plaintext modulus
@@ -589,9 +623,12 @@ int hyena_wht_pack(const hyena_ctx *ctx, uint32_t c_n, const uint32_t *d_in,
 typedef struct {
     const hyena_conv_desc *desc;  /* planned; desc->batch images share the weights */
     uint32_t *d_ct;               /* device [batch][tiles][n_groups][2][L][N], coefficient domain */
-    const uint32_t *d_wntt;       /* device, from hyena_encode_weights */
+    const uint32_t *d_wntt;       /* device, from hyena_encode_weights, or NULL when d_taps is given */
     uint32_t *d_out;              /* device [batch][tiles][Co][2][L][N]; must not alias d_ct */
-} hyena_layer_io;                 /* all three 16-byte aligned */
+    const int32_t *d_taps;        /* device, from hyena_synth_taps, or NULL: with it the autotuner
+                                     also times the schedules that synthesize the weight words in
+                                     the multiply-accumulate (hyena_conv_synth) */
+} hyena_layer_io;                 /* d_ct, d_wntt, d_out 16-byte aligned; d_taps 4-byte */
 
 typedef struct hyena_batch hyena_batch;
 

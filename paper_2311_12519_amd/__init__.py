@@ -57,7 +57,7 @@ class ConvDesc(ctypes.Structure):
 class LayerIO(ctypes.Structure):
     """Mirror of hyena_layer_io."""
     _fields_ = [("desc", ctypes.c_void_p), ("d_ct", ctypes.c_void_p), ("d_wntt", ctypes.c_void_p),
-                ("d_out", ctypes.c_void_p)]
+                ("d_out", ctypes.c_void_p), ("d_taps", ctypes.c_void_p)]
 
 
 _lib = None
@@ -104,7 +104,10 @@ _SIGS = {
     "hyena_conv_tiled": [_P, _P, _P, _P, _P, ctypes.c_int, _P],
     "hyena_conv_schedules": [_P],
     "hyena_conv_schedule_info": [ctypes.c_int, _P],
+    "hyena_conv_schedule_taps": [ctypes.c_int],
     "hyena_conv_default_schedule": [_P],
+    "hyena_synth_taps": [_P, _P, _P, _P, _P],
+    "hyena_conv_synth": [_P, _P, _P, _P, _P, _P],
     "hyena_ntt_schedules": [_u32, _P, _P],
     "hyena_ntt_sched": [_P, _P, _sz, ctypes.c_int, ctypes.c_int, _P],
 }
@@ -577,6 +580,32 @@ def hyena_conv_schedules() -> list:
     return out
 
 
+def hyena_conv_schedule_taps(sched: int) -> int:
+    """0 for a schedule that streams NTT-domain weights, else the most taps per
+    weight word it synthesizes."""
+    r = lib().hyena_conv_schedule_taps(sched)
+    if r < 0:
+        _check(r)
+    return r
+
+
+def synth_taps_words(desc: ConvDesc) -> int:
+    """int32 words of the integer-tap array [Co][w_groups][T4]."""
+    T = desc.ci * desc.k * desc.k
+    return desc.Co * desc.w_groups * ((T + 3) & ~3)
+
+
+def hyena_synth_taps(ctx: Ctx, desc: ConvDesc, d_w, d_taps, stream=None) -> None:
+    _need(d_taps, synth_taps_words(desc), "d_taps")
+    _check(lib().hyena_synth_taps(ctx.handle, ctypes.byref(desc), _dev_ptr(d_w, "int8"), _dev_ptr(d_taps, "int32"),
+                                  _stream(stream)))
+
+
+def hyena_conv_synth(ctx: Ctx, desc: ConvDesc, d_ct_ntt, d_taps, d_out_ntt, stream=None) -> None:
+    _check(lib().hyena_conv_synth(ctx.handle, ctypes.byref(desc), _dev_ptr(d_ct_ntt, "int32"),
+                                  _dev_ptr(d_taps, "int32"), _dev_ptr(d_out_ntt, "int32"), _stream(stream)))
+
+
 def hyena_conv_default_schedule(desc: ConvDesc) -> int:
     return lib().hyena_conv_default_schedule(ctypes.byref(desc))
 
@@ -610,15 +639,20 @@ class Batch:
 
 
 def hyena_batch_create(ctx: Ctx, layers, flags: int = 0) -> Batch:
-    """layers: list of (ConvDesc, d_ct, d_wntt, d_out) with int32 device tensors."""
+    """layers: list of (ConvDesc, d_ct, d_wntt, d_out) or (ConvDesc, d_ct,
+    d_wntt, d_out, d_taps) with int32 device tensors; d_wntt or d_taps may be
+    None (not both)."""
     arr = (LayerIO * len(layers))()
     keep = []
-    for i, (desc, d_ct, d_wn, d_out) in enumerate(layers):
+    for i, lay in enumerate(layers):
+        desc, d_ct, d_wn, d_out = lay[:4]
+        d_taps = lay[4] if len(lay) > 4 else None
         arr[i].desc = ctypes.cast(ctypes.pointer(desc), ctypes.c_void_p)
         arr[i].d_ct = _dev_ptr(d_ct, "int32")
-        arr[i].d_wntt = _dev_ptr(d_wn, "int32")
+        arr[i].d_wntt = _dev_ptr(d_wn, "int32") if d_wn is not None else None
         arr[i].d_out = _dev_ptr(d_out, "int32")
-        keep.append((desc, d_ct, d_wn, d_out))
+        arr[i].d_taps = _dev_ptr(d_taps, "int32") if d_taps is not None else None
+        keep.append((desc, d_ct, d_wn, d_out, d_taps))
     out = ctypes.c_void_p()
     _check(lib().hyena_batch_create(ctx.handle, arr, len(layers), flags, ctypes.byref(out)))
     return Batch(out, (ctx, keep))

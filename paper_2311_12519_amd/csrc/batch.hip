@@ -27,13 +27,15 @@
 
 // schedule table and validity (conv.hip)
 int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                uint32_t *out, int sched, bool per_channel, hipStream_t s);
+                const int32_t *taps, uint32_t *out, int sched, bool per_channel, hipStream_t s);
 int conv_sched_info(int sched, int *info);
 int conv_num_scheds();
 bool conv_sched_valid(const hyena_conv_desc *d, int sched);
 int conv_default_sched(const hyena_conv_desc *d);
 MacArgs conv_make_args(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                       uint32_t *out, int sched, bool per_channel, bool *needs_wht);
+                       const int32_t *taps, uint32_t *out, int sched, bool per_channel, bool *needs_wht);
+int conv_sched_syn(int sched);
+int conv_default_synth_sched(const hyena_conv_desc *d);
 hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
                            hipStream_t s);
 
@@ -62,11 +64,11 @@ __device__ __forceinline__ uint32_t draw_item(uint32_t *counters, const uint32_t
 
 // resident blocks per CU as the per-layer kernel (three, at most 168 VGPRs,
 // where the LDS stages allow)
-template <int MT, int OT, int WR, int WO, int NS>
-__global__ void __launch_bounds__(256, (MacLdsShape<MT, OT, WR, WO, NS>::MIN_BLOCKS))
+template <int MT, int OT, int WR, int WO, int NS, int TM>
+__global__ void __launch_bounds__(256, (MacLdsShape<MT, OT, WR, WO, NS, TM>::MIN_BLOCKS))
 mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__restrict__ first, uint32_t n_layers,
                       uint32_t *__restrict__ counters, uint32_t total) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS>::LDS_WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[MacLdsShape<MT, OT, WR, WO, NS, TM>::LDS_WORDS];
     __shared__ uint32_t item_s[2], layer_s[2];  // claimed item and its layer, double buffered
     const uint32_t x = blockIdx.x & 7u;  // this block's XCD and queue
     uint32_t lq = 0;                     // layer of thread 0's last claim
@@ -89,7 +91,7 @@ mac_persistent_kernel(const MacArgs *__restrict__ layers, const uint32_t *__rest
                 layer_s[round ^ 1] = lq;
             }
         };
-        mac_lds_block<MT, OT, WR, WO, NS>(layers[l], it - first[l], lds, claim);
+        mac_lds_block<MT, OT, WR, WO, NS, TM>(layers[l], it - first[l], lds, claim);
         __syncthreads();  // LDS stages and the next claim ready for the next round
     }
 }
@@ -100,13 +102,14 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
 
 typedef void (*PersistentFn)(const MacArgs *, const uint32_t *, uint32_t, uint32_t *, uint32_t);
 
-PersistentFn persistent_fn(const int *info) {
-#define HY_P(M, O, R, W, S)                                                          \
-    if (info[1] == M && info[2] == O && info[3] == R && info[4] == W && info[5] == S) \
-        return mac_persistent_kernel<M, O, R, W, S>;
-    HY_P(8, 8, 2, 2, 4) HY_P(8, 8, 2, 2, 3) HY_P(4, 8, 2, 2, 4) HY_P(8, 8, 1, 4, 4)
-    HY_P(2, 16, 1, 4, 4) HY_P(4, 16, 1, 4, 3) HY_P(8, 4, 4, 1, 4) HY_P(4, 8, 1, 4, 4)
-    HY_P(8, 8, 2, 2, 5) HY_P(8, 8, 2, 2, 6)
+PersistentFn persistent_fn(const int *info, int syn) {
+#define HY_P(M, O, R, W, S, T)                                                                    \
+    if (info[1] == M && info[2] == O && info[3] == R && info[4] == W && info[5] == S && syn == T) \
+        return mac_persistent_kernel<M, O, R, W, S, T>;
+    HY_P(8, 8, 2, 2, 4, 0) HY_P(8, 8, 2, 2, 3, 0) HY_P(4, 8, 2, 2, 4, 0) HY_P(8, 8, 1, 4, 4, 0)
+    HY_P(2, 16, 1, 4, 4, 0) HY_P(4, 16, 1, 4, 3, 0) HY_P(8, 4, 4, 1, 4, 0) HY_P(4, 8, 1, 4, 4, 0)
+    HY_P(8, 8, 2, 2, 5, 0) HY_P(8, 8, 2, 2, 6, 0)
+    HY_P(8, 8, 2, 2, 4, 9) HY_P(8, 8, 4, 1, 4, 9) HY_P(8, 8, 2, 2, 4, 18) HY_P(8, 8, 4, 1, 4, 18)
 #undef HY_P
     return nullptr;
 }
@@ -194,8 +197,8 @@ static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
     const hyena_ctx *c = b->ctx;
     if (b->mac_solo) {
         for (uint32_t l = 0; l < b->desc.size(); l++) {
-            const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out,
-                                       b->mac_sched[l], true, s);
+            const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_taps,
+                                       b->io[l].d_out, b->mac_sched[l], true, s);
             if (rc) return rc;
             launches++;
         }
@@ -209,14 +212,15 @@ static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
         auto &g = b->groups[gi];
         int info[6];
         conv_sched_info(g.sched, info);
-        PersistentFn fn = persistent_fn(info);
+        PersistentFn fn = persistent_fn(info, conv_sched_syn(g.sched));
         hipLaunchKernelGGL(fn, dim3(g.grid), dim3(256), 0, s, (const MacArgs *)g.d_args,
                            (const uint32_t *)g.d_first, (uint32_t)g.layers.size(), b->d_counters + 8 * gi, g.total);
         launches++;
         // layers whose Walsh group is wider than the fused epilogue
         for (uint32_t l : g.layers) {
             bool wht = false;
-            conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, g.sched, true, &wht);
+            conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_taps, b->io[l].d_out, g.sched,
+                           true, &wht);
             if (wht) {
                 const hyena_conv_desc &d = b->desc[l];
                 const hipError_t e = conv_launch_wht(c, d.c_n, b->io[l].d_out, b->io[l].d_out,
@@ -229,8 +233,8 @@ static int issue_mac_phase(hyena_batch *b, hipStream_t s, int &launches) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_batch_run: ") + hipGetErrorString(e));
     for (uint32_t l : b->solo) {
-        const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, b->mac_sched[l],
-                                   true, s);
+        const int rc = conv_launch(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_taps, b->io[l].d_out,
+                                   b->mac_sched[l], true, s);
         if (rc) return rc;
         launches++;
     }
@@ -291,12 +295,20 @@ static float time_best(hipStream_t s, int reps, F fn) {
     return best;
 }
 
-static std::string layer_key(const hyena_ctx *c, const std::string &arch, const hyena_conv_desc &d) {
+static std::string layer_key(const hyena_ctx *c, const std::string &arch, const hyena_conv_desc &d,
+                             const hyena_layer_io &io) {
     std::ostringstream k;
     k << arch << "|mac|N" << c->N << "|L" << c->L << "|lazy" << c->lazy_ntt << "|" << d.H << "x" << d.W << "|"
       << d.Ci << ">" << d.Co << "|k" << d.k << "|dw" << d.depthwise << "|cn" << d.c_n << "|ci" << d.ci << "|b"
-      << d.batch << "|t" << d.tiles;
+      << d.batch << "|t" << d.tiles << "|w" << (io.d_wntt ? 1 : 0) << "|taps" << (io.d_taps ? 1 : 0);
     return k.str();
+}
+
+// a schedule the layer can run: valid for its shape, and its weights in the
+// form the schedule reads (NTT-domain words, or integer taps)
+static bool sched_usable(const hyena_conv_desc &d, const hyena_layer_io &io, int sid) {
+    if (!conv_sched_valid(&d, sid)) return false;
+    return conv_sched_syn(sid) ? io.d_taps != nullptr : io.d_wntt != nullptr;
 }
 
 static int tune(hyena_batch *b) {
@@ -312,23 +324,24 @@ static int tune(hyena_batch *b) {
     bool all_cached = true;
     for (size_t l = 0; l < b->desc.size(); l++) {
         const hyena_conv_desc &d = b->desc[l];
-        const std::string key = layer_key(c, arch, d) + (persistent ? "|persistent" : "");
+        const std::string key = layer_key(c, arch, d, b->io[l]) + (persistent ? "|persistent" : "");
         auto it = cache.find(key);
-        if (it != cache.end() && it->second >= 0 && it->second < ns && conv_sched_valid(&d, it->second)) {
+        if (it != cache.end() && it->second >= 0 && it->second < ns && sched_usable(d, b->io[l], it->second)) {
             b->mac_sched[l] = it->second;
             continue;
         }
         all_cached = false;
         float best = 1e30f;
-        int best_s = conv_default_sched(&d);
+        int best_s = b->mac_sched[l];
         for (int sid = 0; sid < ns; sid++) {
-            if (!conv_sched_valid(&d, sid)) continue;
+            if (!sched_usable(d, b->io[l], sid)) continue;
             int info[6];
             conv_sched_info(sid, info);
             if (!d.depthwise && !info[0] && info[1] * info[2] < 16) continue;  // tiny register tiles
             int rc = HYENA_OK;
             const float ms = time_best(s, 2, [&] {
-                if (!rc) rc = conv_launch(c, &d, b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, sid, true, s);
+                if (!rc) rc = conv_launch(c, &d, b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_taps, b->io[l].d_out, sid,
+                                          true, s);
             });
             if (rc) continue;
             times[l][sid] = ms;
@@ -369,7 +382,7 @@ static int tune(hyena_batch *b) {
             for (size_t l : lds_layers) b->mac_sched[l] = common;
     }
     for (size_t l = 0; l < b->desc.size(); l++)
-        cache[layer_key(c, arch, b->desc[l]) + (persistent ? "|persistent" : "")] = b->mac_sched[l];
+        cache[layer_key(c, arch, b->desc[l], b->io[l]) + (persistent ? "|persistent" : "")] = b->mac_sched[l];
     // NTT schedules per direction, each timed alone on the arrays it
     // transforms in a step: the forward on every layer's inputs (an untimed
     // default inverse after each timed forward restores them), the inverse on
@@ -455,7 +468,7 @@ static int build_groups(hyena_batch *b) {
     for (uint32_t l = 0; l < b->desc.size(); l++) {
         int info[6];
         conv_sched_info(b->mac_sched[l], info);
-        if ((b->flags & HYENA_BATCH_PERSISTENT) && info[0] && persistent_fn(info))
+        if ((b->flags & HYENA_BATCH_PERSISTENT) && info[0] && persistent_fn(info, conv_sched_syn(b->mac_sched[l])))
             by_sched[b->mac_sched[l]].push_back(l);
         else
             b->solo.push_back(l);
@@ -474,8 +487,8 @@ static int build_groups(hyena_batch *b) {
         uint32_t total = 0;
         for (uint32_t l : g.layers) {
             bool wht = false;
-            MacArgs a = conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_out, g.sched,
-                                       true, &wht);
+            MacArgs a = conv_make_args(c, &b->desc[l], b->io[l].d_ct, b->io[l].d_wntt, b->io[l].d_taps,
+                                       b->io[l].d_out, g.sched, true, &wht);
             args.push_back(a);
             first.push_back(total);
             total += mac_blocks(a);
@@ -498,7 +511,8 @@ static int build_groups(hyena_batch *b) {
         int info[6];
         conv_sched_info(g.sched, info);
         int per_cu = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)persistent_fn(info), 256, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)persistent_fn(info, conv_sched_syn(g.sched)), 256, 0));
         b->per_cu = per_cu;
         // every XCD queue needs its own blocks: a multiple of 8, at least 8
         g.grid = (uint32_t)std::max(1, per_cu) * (uint32_t)n_cu;
@@ -522,7 +536,8 @@ static int tune_mac_phase(hyena_batch *b) {
     const hyena_ctx *c = b->ctx;
     const std::string arch = arch_name(c->device);
     std::ostringstream all;
-    for (size_t l = 0; l < b->desc.size(); l++) all << layer_key(c, arch, b->desc[l]) << "#" << b->mac_sched[l] << ";";
+    for (size_t l = 0; l < b->desc.size(); l++)
+        all << layer_key(c, arch, b->desc[l], b->io[l]) << "#" << b->mac_sched[l] << ";";
     std::ostringstream k;
     k << arch << "|macphase|" << std::hex << std::hash<std::string>()(all.str());
     auto cache = load_cache();
@@ -629,20 +644,29 @@ extern "C" int hyena_batch_create(const hyena_ctx *c, const hyena_layer_io *laye
     b->flags = flags;
     for (uint32_t l = 0; l < n_layers; l++) {
         const hyena_layer_io &io = layers[l];
-        if (!io.desc || !io.d_ct || !io.d_wntt || !io.d_out || !io.desc->Bt) {
+        if (!io.desc || !io.d_ct || (!io.d_wntt && !io.d_taps) || !io.d_out || !io.desc->Bt) {
             delete b;
             return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
                                                " has a NULL buffer or an unplanned descriptor");
         }
-        if (((uintptr_t)io.d_ct | (uintptr_t)io.d_wntt | (uintptr_t)io.d_out) & 15u) {
+        if (((uintptr_t)io.d_ct | (uintptr_t)io.d_wntt | (uintptr_t)io.d_out) & 15u || ((uintptr_t)io.d_taps & 3u)) {
             delete b;
             return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
-                                               " has a buffer that is not 16-byte aligned");
+                                               " has a misaligned buffer");
         }
         b->desc.push_back(*io.desc);
         if (b->desc.back().batch == 0) b->desc.back().batch = 1;
         b->io.push_back(io);
-        b->mac_sched.push_back(conv_default_sched(io.desc));
+        // streamed weights by default; the synthesizing schedule when only
+        // the integer taps are given
+        const int def = io.d_wntt ? conv_default_sched(&b->desc.back()) : conv_default_synth_sched(&b->desc.back());
+        if (def < 0 || !sched_usable(b->desc.back(), io, def)) {
+            delete b;
+            return set_error(HYENA_EINVAL, "hyena_batch_create: layer " + std::to_string(l) +
+                                               " has only integer taps but cannot synthesize its weights "
+                                               "(depthwise, or more than 18 taps per word)");
+        }
+        b->mac_sched.push_back(def);
     }
     b->ntt_fwd = b->ntt_inv = ntt_default_schedule(c->logN);
     int rc = HYENA_OK;

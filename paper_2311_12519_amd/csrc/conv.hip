@@ -270,7 +270,7 @@ hipError_t launch_mac(const MacArgs &base, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int MT, int OT, int WR, int WO, int NS>
+template <int MT, int OT, int WR, int WO, int NS, int TM = 0>
 hipError_t launch_mac_lds(const MacArgs &base, hipStream_t s) {
     MacArgs a = base;
     a.n_ot = (a.Co + WO * OT - 1) / (WO * OT);
@@ -278,8 +278,40 @@ hipError_t launch_mac_lds(const MacArgs &base, hipStream_t s) {
     a.kchunks = a.N / 64;
     const size_t nb = (size_t)a.n_ot * a.n_mt * a.kchunks * a.L;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((mac_lds_kernel<MT, OT, WR, WO, NS>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mac_lds_kernel<MT, OT, WR, WO, NS, TM>), dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// Walsh-combined integer taps of a standard layer for the synthesizing MAC:
+// taps[o][g][t] = sum_b H[j][b] f[G c_n + b][g ci + c'][di][dj] with
+// o = G c_n + j, t = c' k^2 + di k + dj (0 past the last input channel and
+// for T <= t < T4).
+struct TapArgs {
+    const int8_t *w;
+    int32_t *taps;
+    uint32_t Co, Ci, k, ci, w_groups, c_n, T, T4;
+};
+
+__global__ void synth_taps_kernel(TapArgs a) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n = (size_t)a.Co * a.w_groups * a.T4;
+    if (idx >= n) return;
+    const uint32_t t = (uint32_t)(idx % a.T4);
+    const uint32_t g = (uint32_t)((idx / a.T4) % a.w_groups);
+    const uint32_t o = (uint32_t)(idx / ((size_t)a.T4 * a.w_groups));
+    int32_t v = 0;
+    const uint32_t kk = a.k * a.k;
+    if (t < a.T) {
+        const uint32_t cw = g * a.ci + t / kk, tap = t % kk;
+        if (cw < a.Ci) {
+            const uint32_t G = o / a.c_n, j = o % a.c_n;
+            for (uint32_t b = 0; b < a.c_n; b++) {
+                const int f = a.w[((size_t)(G * a.c_n + b) * a.Ci + cw) * kk + tap];
+                v += (__popc(j & b) & 1) ? -f : f;
+            }
+        }
+    }
+    a.taps[idx] = v;
 }
 
 hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,
@@ -307,22 +339,39 @@ hipError_t launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint3
 struct MacSched {
     int lds;            // 0: mac_kernel, 1: mac_lds_kernel
     int mt, ot, wr, wo, ns;
+    int syn;            // 0: streams the NTT-domain weights; > 0: synthesizes them
+                        // from at most `syn` integer taps per word
 };
 
 static const MacSched kScheds[] = {
-    {0, 2, 16, 0, 0, 0}, {0, 4, 8, 0, 0, 0}, {0, 4, 16, 0, 0, 0}, {0, 8, 4, 0, 0, 0},
-    {0, 8, 8, 0, 0, 0},  {0, 16, 4, 0, 0, 0}, {0, 2, 8, 0, 0, 0}, {0, 2, 4, 0, 0, 0},
-    {0, 2, 2, 0, 0, 0},  {0, 2, 1, 0, 0, 0},  {0, 4, 4, 0, 0, 0}, {0, 4, 2, 0, 0, 0},
-    {0, 4, 1, 0, 0, 0},  {0, 8, 2, 0, 0, 0},  {0, 8, 1, 0, 0, 0},
-    {1, 8, 8, 2, 2, 4},  {1, 8, 8, 2, 2, 3},  {1, 4, 8, 2, 2, 4},  {1, 8, 8, 1, 4, 4},
-    {1, 2, 16, 1, 4, 4}, {1, 4, 16, 1, 4, 3}, {1, 8, 4, 4, 1, 4},  {1, 4, 8, 1, 4, 4},
-    {1, 8, 8, 2, 2, 5},  {1, 8, 8, 2, 2, 6},
+    {0, 2, 16, 0, 0, 0, 0}, {0, 4, 8, 0, 0, 0, 0}, {0, 4, 16, 0, 0, 0, 0}, {0, 8, 4, 0, 0, 0, 0},
+    {0, 8, 8, 0, 0, 0, 0},  {0, 16, 4, 0, 0, 0, 0}, {0, 2, 8, 0, 0, 0, 0}, {0, 2, 4, 0, 0, 0, 0},
+    {0, 2, 2, 0, 0, 0, 0},  {0, 2, 1, 0, 0, 0, 0},  {0, 4, 4, 0, 0, 0, 0}, {0, 4, 2, 0, 0, 0, 0},
+    {0, 4, 1, 0, 0, 0, 0},  {0, 8, 2, 0, 0, 0, 0},  {0, 8, 1, 0, 0, 0, 0},
+    {1, 8, 8, 2, 2, 4, 0},  {1, 8, 8, 2, 2, 3, 0},  {1, 4, 8, 2, 2, 4, 0},  {1, 8, 8, 1, 4, 4, 0},
+    {1, 2, 16, 1, 4, 4, 0}, {1, 4, 16, 1, 4, 3, 0}, {1, 8, 4, 4, 1, 4, 0},  {1, 4, 8, 1, 4, 4, 0},
+    {1, 8, 8, 2, 2, 5, 0},  {1, 8, 8, 2, 2, 6, 0},
+    // weights synthesized in the block: 16 or 32 rows, up to 9 or 18 taps
+    {1, 8, 8, 2, 2, 4, 9},  {1, 8, 8, 4, 1, 4, 9},  {1, 8, 8, 2, 2, 4, 18}, {1, 8, 8, 4, 1, 4, 18},
 };
 static const int kNumScheds = sizeof(kScheds) / sizeof(kScheds[0]);
 
 static int find_sched(int lds, int mt, int ot) {
     for (int i = 0; i < kNumScheds; i++)
-        if (kScheds[i].lds == lds && kScheds[i].mt == mt && kScheds[i].ot == ot) return i;
+        if (kScheds[i].lds == lds && kScheds[i].mt == mt && kScheds[i].ot == ot && !kScheds[i].syn) return i;
+    return -1;
+}
+
+static uint32_t taps_per_word(const hyena_conv_desc *d) { return d->ci * d->k * d->k; }
+
+// the synthesizing schedule for a standard layer: the smallest tap bound that
+// covers its taps per word, 32 rows per block when there are that many
+static int default_synth_sched(const hyena_conv_desc *d) {
+    const uint32_t T = taps_per_word(d), rows = 2 * (d->batch ? d->batch : 1) * d->tiles;
+    const int syn = T <= 9 ? 9 : 18;
+    const int wr = rows >= 32 ? 4 : 2;
+    for (int i = 0; i < kNumScheds; i++)
+        if (kScheds[i].syn == syn && kScheds[i].wr == wr) return i;
     return -1;
 }
 
@@ -342,11 +391,20 @@ static int default_sched(const hyena_conv_desc *d) {
 }
 
 static bool sched_valid(const hyena_conv_desc *d, const MacSched &t) {
+    if (t.syn) return !d->depthwise && taps_per_word(d) <= (uint32_t)t.syn;
     if (!d->depthwise) return true;
     return t.lds == 0 && (d->ci % (uint32_t)t.ot == 0 || t.ot == 1) && (uint32_t)t.ot >= 1;
 }
 
 static hipError_t dispatch_mac(const MacArgs &a, const MacSched &t, hipStream_t s) {
+    if (t.syn) {
+#define HY_S(M, O, R, W, S, T) \
+    if (t.mt == M && t.ot == O && t.wr == R && t.wo == W && t.ns == S && t.syn == T) \
+        return launch_mac_lds<M, O, R, W, S, T>(a, s);
+        HY_S(8, 8, 2, 2, 4, 9) HY_S(8, 8, 4, 1, 4, 9) HY_S(8, 8, 2, 2, 4, 18) HY_S(8, 8, 4, 1, 4, 18)
+#undef HY_S
+        return hipErrorInvalidValue;
+    }
     if (t.lds) {
 #define HY_L(M, O, R, W, S) \
     if (t.mt == M && t.ot == O && t.wr == R && t.wo == W && t.ns == S) return launch_mac_lds<M, O, R, W, S>(a, s);
@@ -367,13 +425,27 @@ static hipError_t dispatch_mac(const MacArgs &a, const MacSched &t, hipStream_t 
 }
 
 MacArgs conv_make_args(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                       uint32_t *out, int sched, bool per_channel, bool *needs_wht) {
+                       const int32_t *taps, uint32_t *out, int sched, bool per_channel, bool *needs_wht) {
     const MacSched &t = kScheds[sched];
     const uint32_t cn = d->c_n ? d->c_n : 1;
     MacArgs a{};
     a.ct = ct;
     a.w = w;
     a.out = out;
+    if (t.syn) {
+        a.taps = taps;
+        a.fw = c->d_fw;
+        a.T = taps_per_word(d);
+        a.T4 = (a.T + 3) & ~3u;
+        const uint32_t kk = d->k * d->k;
+        for (uint32_t i = 0; i < a.T && i < (uint32_t)kSynthTapsMax; i++) {
+            const uint32_t cp = i / kk, di = (i % kk) / d->k, dj = i % d->k;
+            a.texp[i] = d->O - cp * d->Bt - di * d->Wp - dj;
+        }
+        // c_n^{-1} 2^64 mod q_i: Montgomery form of the output scale c_n^{-1} 2^32
+        for (uint32_t i = 0; i < c->L; i++)
+            a.wscale[i] = to_montgomery(to_montgomery(h_powmod(cn, c->q[i] - 2, c->q[i]), c->q[i]), c->q[i]);
+    }
     a.N = c->N;
     a.L = c->L;
     a.logN = c->logN;
@@ -401,6 +473,8 @@ MacArgs conv_make_args(const hyena_ctx *c, const hyena_conv_desc *d, const uint3
 }
 
 int conv_num_scheds() { return kNumScheds; }
+int conv_sched_syn(int sched) { return sched >= 0 && sched < kNumScheds ? kScheds[sched].syn : 0; }
+int conv_default_synth_sched(const hyena_conv_desc *d) { return default_synth_sched(d); }
 bool conv_sched_valid(const hyena_conv_desc *d, int sched) {
     return sched >= 0 && sched < kNumScheds && sched_valid(d, kScheds[sched]);
 }
@@ -416,19 +490,23 @@ hipError_t conv_launch_wht(const hyena_ctx *c, uint32_t cn, const uint32_t *in, 
 }
 
 int conv_launch(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *ct, const uint32_t *w,
-                uint32_t *out, int sched, bool per_channel, hipStream_t s) {
-    if (!c || !d || !ct || !w || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
-    if (((uintptr_t)ct | (uintptr_t)w | (uintptr_t)out) & 15u)
-        return set_error(HYENA_EINVAL, "hyena_conv: device arrays must be 16-byte aligned");
+                const int32_t *taps, uint32_t *out, int sched, bool per_channel, hipStream_t s) {
+    if (!c || !d || !ct || !out) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
     if (!d->Bt || !d->n_groups) return set_error(HYENA_EINVAL, "hyena_conv: descriptor not planned");
-    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
-    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
-    if (sched < 0) sched = default_sched(d);
+    if (sched < 0) sched = w ? default_sched(d) : default_synth_sched(d);
     if (sched < 0 || sched >= kNumScheds) return set_error(HYENA_EINVAL, "hyena_conv: unknown schedule");
     const MacSched &t = kScheds[sched];
+    if (t.syn ? !taps : !w)
+        return set_error(HYENA_EINVAL, t.syn ? "hyena_conv: a synthesizing schedule needs the integer taps"
+                                             : "hyena_conv: NULL weights");
+    if (((uintptr_t)ct | (uintptr_t)(t.syn ? nullptr : w) | (uintptr_t)out) & 15u)
+        return set_error(HYENA_EINVAL, "hyena_conv: device arrays must be 16-byte aligned");
+    if ((uintptr_t)taps & 3u) return set_error(HYENA_EINVAL, "hyena_conv: taps must be 4-byte aligned");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_conv: context was created host-only");
+    if (c->N % 256) return set_error(HYENA_EUNSUPPORTED, "hyena_conv: N must be a multiple of 256");
     if (!sched_valid(d, t)) return set_error(HYENA_EINVAL, "hyena_conv: schedule not valid for this layer");
     bool wht = false;
-    const MacArgs a = conv_make_args(c, d, ct, w, out, sched, per_channel, &wht);
+    const MacArgs a = conv_make_args(c, d, ct, w, taps, out, sched, per_channel, &wht);
     hipError_t e = dispatch_mac(a, t, s);
     if (e == hipErrorInvalidValue) return set_error(HYENA_EINVAL, "hyena_conv: unsupported MAC schedule");
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_conv: ") + hipGetErrorString(e));
@@ -460,16 +538,66 @@ extern "C" int hyena_conv_default_schedule(const hyena_conv_desc *d) {
 extern "C" int hyena_conv(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
                           const uint32_t *d_wntt, uint32_t *d_out_ntt, hyena_stream_t s) {
     if (!d) return set_error(HYENA_EINVAL, "hyena_conv: NULL descriptor");
+    if (!d_wntt) return set_error(HYENA_EINVAL, "hyena_conv: NULL argument");
     // without HYENA_FUSE_WHT the output holds the Walsh components
     const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
-    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, -1, per_channel, (hipStream_t)s);
+    return conv_launch(c, d, d_ct_ntt, d_wntt, nullptr, d_out_ntt, -1, per_channel, (hipStream_t)s);
+}
+
+extern "C" int hyena_conv_synth(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
+                                const int32_t *d_taps, uint32_t *d_out_ntt, hyena_stream_t s) {
+    if (!d) return set_error(HYENA_EINVAL, "hyena_conv_synth: NULL descriptor");
+    if (!d_taps) return set_error(HYENA_EINVAL, "hyena_conv_synth: NULL argument");
+    if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_conv_synth: descriptor not planned");
+    if (d->depthwise) return set_error(HYENA_EUNSUPPORTED, "hyena_conv_synth: depthwise layers stream their weights");
+    if (taps_per_word(d) > (uint32_t)kSynthTapsMax)
+        return set_error(HYENA_EUNSUPPORTED, "hyena_conv_synth: more than 18 taps per weight word");
+    const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
+    return conv_launch(c, d, d_ct_ntt, nullptr, d_taps, d_out_ntt, default_synth_sched(d), per_channel,
+                       (hipStream_t)s);
 }
 
 extern "C" int hyena_conv_tiled(const hyena_ctx *c, const hyena_conv_desc *d, const uint32_t *d_ct_ntt,
                                 const uint32_t *d_wntt, uint32_t *d_out_ntt, int sched, hyena_stream_t s) {
     if (!d) return set_error(HYENA_EINVAL, "hyena_conv_tiled: NULL descriptor");
     const bool per_channel = (d->flags & HYENA_FUSE_WHT) || d->c_n <= 1;
-    return conv_launch(c, d, d_ct_ntt, d_wntt, d_out_ntt, sched, per_channel, (hipStream_t)s);
+    // a synthesizing schedule takes the integer taps in place of d_wntt
+    const bool syn = sched >= 0 && sched < kNumScheds && kScheds[sched].syn;
+    return conv_launch(c, d, d_ct_ntt, syn ? nullptr : d_wntt, syn ? (const int32_t *)d_wntt : nullptr,
+                       d_out_ntt, sched, per_channel, (hipStream_t)s);
+}
+
+extern "C" int hyena_conv_schedule_taps(int sched) {
+    if (sched < 0 || sched >= kNumScheds) return set_error(HYENA_EINVAL, "hyena_conv_schedule_taps: bad schedule");
+    return kScheds[sched].syn;
+}
+
+extern "C" int hyena_synth_taps(const hyena_ctx *c, const hyena_conv_desc *d, const int8_t *d_w, int32_t *d_taps,
+                                hyena_stream_t s) {
+    if (!c || !d || !d_w || !d_taps) return set_error(HYENA_EINVAL, "hyena_synth_taps: NULL argument");
+    if (!d->Bt) return set_error(HYENA_EINVAL, "hyena_synth_taps: descriptor not planned");
+    if (d->c_n & (d->c_n - 1)) return set_error(HYENA_EINVAL, "hyena_synth_taps: c_n must be a power of two");
+    if (d->depthwise) return set_error(HYENA_EUNSUPPORTED, "hyena_synth_taps: depthwise layers stream their weights");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_synth_taps: context was created host-only");
+    if ((uintptr_t)d_taps & 3u) return set_error(HYENA_EINVAL, "hyena_synth_taps: d_taps must be 4-byte aligned");
+    TapArgs a{};
+    a.w = d_w;
+    a.taps = d_taps;
+    a.Co = d->Co;
+    a.Ci = d->Ci;
+    a.k = d->k;
+    a.ci = d->ci;
+    a.w_groups = d->w_groups;
+    a.c_n = d->c_n ? d->c_n : 1;
+    a.T = taps_per_word(d);
+    a.T4 = (a.T + 3) & ~3u;
+    const size_t n = (size_t)a.Co * a.w_groups * a.T4;
+    if (n == 0) return HYENA_OK;
+    if ((n + 255) / 256 > 0x7fffffff) return set_error(HYENA_EINVAL, "hyena_synth_taps: layer too large");
+    hipLaunchKernelGGL(synth_taps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_synth_taps: ") + hipGetErrorString(e));
+    return HYENA_OK;
 }
 
 extern "C" int hyena_wht_pack(const hyena_ctx *c, uint32_t cn, const uint32_t *in, uint32_t *out, size_t G,

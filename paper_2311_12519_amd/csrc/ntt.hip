@@ -76,6 +76,35 @@ __device__ __forceinline__ void gs_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, 
 
 __device__ __forceinline__ uint32_t lds_idx(uint32_t j) { return j + (j >> 5); }
 
+// Which waves an exchange between two passes connects. In the pass over
+// stages [S0, S0 + EP), thread tid holds the groups gi = tid + kg T, whose
+// residues have the index bits [b | r | o]: b = gi's high S0 bits, r the
+// register index, o = gi's low LOGN - S0 - EP bits. The wave number sits in
+// bits [6, LOGT) of gi, so bit p of it lands on residue bit p when
+// p < LOGN - S0 - EP and on residue bit p + EP otherwise. When the two passes
+// put every wave bit on the same residue bit, each wave writes to LDS exactly
+// the residues it reads back: the exchange needs no workgroup barrier, only
+// the wave's own LDS accesses kept in order.
+template <int LOGN, int LOGT, int SA, int EA, int SB, int EB>
+constexpr bool exchange_in_wave() {
+    for (int p = 6; p < LOGT; p++) {
+        const int fa = p < LOGN - SA - EA ? p : p + EA;
+        const int fb = p < LOGN - SB - EB ? p : p + EB;
+        if (fa != fb) return false;
+    }
+    return true;
+}
+
+// The wave's earlier LDS writes are complete before its later LDS reads
+// issue, and the compiler keeps LDS accesses on their side.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <bool IN_WAVE>
+__device__ __forceinline__ void exchange_sync() {
+    if constexpr (IN_WAVE) wave_lds_sync();
+    else __syncthreads();
+}
+
 // One pass of forward stages [s0, s0+e) on the thread's E registers.
 // Group gi of the pass holds indices b*(N>>s0) + o + r*(N>>(s0+e)), r < 2^e,
 // with o = gi mod (N>>(s0+e)), b = gi div (N>>(s0+e)); thread tid owns groups
@@ -186,20 +215,27 @@ __device__ __forceinline__ void fwd_front(uint32_t (&x)[1 << (LOGN - LOGT)], con
     constexpr int E = 1 << E_LOG;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
     static_assert(E0 == E_LOG && E1 <= E_LOG && E2 <= E_LOG && E3 <= E_LOG, "pass wider than the registers");
+    // Before each write to LDS, only this wave's own earlier reads have to be
+    // done: a wave writes back exactly the residues it read for the pass it
+    // just ran, which no other wave reads. So the barriers are those of the
+    // exchanges that cross waves.
+    constexpr bool X1 = exchange_in_wave<LOGN, LOGT, 0, E0, E0, E1>();
+    constexpr bool X2 = exchange_in_wave<LOGN, LOGT, E0, E1, E0 + E1, E2>();
+    constexpr bool X3 = exchange_in_wave<LOGN, LOGT, E0 + E1, E2, E0 + E1 + E2, E3>();
     fwd_pass<LOGN, LOGT, E_LOG, 0, E0, LAZY>(x, tw, q, qn, tid);
     to_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
-    __syncthreads();
+    exchange_sync<X1>();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     fwd_pass<LOGN, LOGT, E_LOG, E0, E1, LAZY>(x, tw, q, qn, tid);
-    __syncthreads();
+    wave_lds_sync();
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
-    __syncthreads();
+    exchange_sync<X2>();
     from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
     fwd_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, LAZY>(x, tw, q, qn, tid);
     if constexpr (E3 > 0) {
-        __syncthreads();
+        wave_lds_sync();
         to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-        __syncthreads();
+        exchange_sync<X3>();
         from_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
         fwd_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, LAZY>(x, tw, q, qn, tid);
     }
@@ -277,21 +313,25 @@ __device__ __forceinline__ void inv_front(uint32_t (&x)[1 << (LOGN - LOGT)], con
                                           const LimbConst &lc, uint32_t *lds, uint32_t tid) {
     constexpr int E_LOG = LOGN - LOGT;
     static_assert(E0 + E1 + E2 + E3 == LOGN, "schedule must cover every stage");
+    // barriers only where an exchange crosses waves (see fwd_front)
+    constexpr bool X1 = exchange_in_wave<LOGN, LOGT, 0, E0, E0, E1>();
+    constexpr bool X2 = exchange_in_wave<LOGN, LOGT, E0, E1, E0 + E1, E2>();
+    constexpr bool X3 = exchange_in_wave<LOGN, LOGT, E0 + E1, E2, E0 + E1 + E2, E3>();
     if constexpr (E3 > 0) {
         inv_pass<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3, false, LAZY>(x, tw, lc, tid);
         to_lds<LOGN, LOGT, E_LOG, E0 + E1 + E2, E3>(x, lds, tid);
-        __syncthreads();
+        exchange_sync<X3>();
         from_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
     }
     inv_pass<LOGN, LOGT, E_LOG, E0 + E1, E2, false, LAZY>(x, tw, lc, tid);
-    if constexpr (E3 > 0) __syncthreads();
+    if constexpr (E3 > 0) wave_lds_sync();
     to_lds<LOGN, LOGT, E_LOG, E0 + E1, E2>(x, lds, tid);
-    __syncthreads();
+    exchange_sync<X2>();
     from_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
     inv_pass<LOGN, LOGT, E_LOG, E0, E1, false, LAZY>(x, tw, lc, tid);
-    __syncthreads();
+    wave_lds_sync();
     to_lds<LOGN, LOGT, E_LOG, E0, E1>(x, lds, tid);
-    __syncthreads();
+    exchange_sync<X1>();
     from_lds<LOGN, LOGT, E_LOG, 0, E0>(x, lds, tid);
 }
 

@@ -240,3 +240,93 @@ def test_vgg_full_size_tuned_batch_sampled(dev, tmp_path, monkeypatch):
                 g = got[img, tau, o].cpu().numpy().view(np.uint32)
                 assert np.array_equal(g, wv), (rep, it["d"].Co, img, tau, o)
     hy.hyena_batch_destroy(b)
+
+
+# ------------------------------------------------- weights synthesized in the MAC
+
+@pytest.mark.parametrize("flags", [hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH,
+                                   hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH, 0])
+def test_batch_with_integer_taps_matches_oracle(dev, setup, flags, tmp_path, monkeypatch):
+    """Layers given as integer taps only (no encoded weights: their words are
+    synthesized in the multiply-accumulate), next to layers with encoded
+    weights and layers with both (the autotuner then also times the
+    synthesizing schedules): every output equals the oracle's, on every
+    replay."""
+    import torch
+    monkeypatch.setenv("HYENA_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    ctx, items = setup
+    bufs = _buffers(items)
+    pristine = [d_ct.clone() for d_ct, _ in bufs]
+    layers = []
+    for i, (it, (d_ct, d_out)) in enumerate(zip(items, bufs)):
+        d = it["d"]
+        T = d.ci * d.k * d.k
+        if d.depthwise or T > 18:
+            layers.append((d, d_ct, it["d_wn"], d_out))
+            continue
+        d_taps = torch.empty(hy.synth_taps_words(d), dtype=torch.int32, device="cuda")
+        hy.hyena_synth_taps(ctx, d, torch.from_numpy(it["w"]).cuda(), d_taps)
+        # layer "a": taps only; layer "e": both forms
+        layers.append((d, d_ct, None if i == 0 else it["d_wn"], d_out, d_taps))
+    assert layers[0][2] is None and len(layers[4]) == 5
+    b = hy.hyena_batch_create(ctx, layers, flags)
+    info = hy.hyena_batch_info(b)
+    assert hy.hyena_conv_schedule_taps(info["mac_sched"][0]) >= 9   # taps only: a synthesizing schedule
+    for rep in range(3):
+        for (d_ct, d_out), p in zip(bufs, pristine):
+            d_ct.copy_(p)
+            d_out.fill_(0)
+        torch.cuda.synchronize()
+        hy.hyena_batch_run(b)
+        _check(items, bufs, ("taps", flags, rep))
+    hy.hyena_batch_destroy(b)
+
+
+def test_vgg_conv2_2_synthesized_in_the_batch_full_size(dev):
+    """VGG-16 conv2_2 (112x112, 128 -> 128, 2 row tiles, 128 input groups, 9
+    taps per weight word) for 8 images at N = 8192, L = 3, its weights given
+    only as integer taps: the tuned persistent batch synthesizes every weight
+    word in the multiply-accumulate. All outputs equal those of the same batch
+    with encoded weights; sampled output ciphertexts equal the oracle's."""
+    import torch
+    lay = wl.vgg16_layers()[3]
+    assert (lay.H, lay.Ci, lay.Co) == (112, 128, 128)
+    ctx = hy.hyena_create(N, L)
+    images = 8
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, 3, flags=hy.HYENA_FUSE_WHT, batch=images)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, 3)
+    assert (pl.tiles, pl.n_groups, pl.ci) == (2, 128, 1)
+    w = wl.weights(4003, lay)
+    d_w = torch.from_numpy(w).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(44)
+    ct0 = torch.empty((images, pl.tiles, pl.n_groups, 2, L, N), dtype=torch.int32, device="cuda")
+    for i, q in enumerate(ctx.primes):
+        ct0[..., i, :] = torch.randint(0, q, ct0[..., i, :].shape, generator=g, device="cuda",
+                                       dtype=torch.int64).to(torch.int32)
+    d_taps = torch.empty(hy.synth_taps_words(d), dtype=torch.int32, device="cuda")
+    hy.hyena_synth_taps(ctx, d, d_w, d_taps)
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, d_w, d_wn)
+    outs = []
+    for form in ("taps", "encoded"):
+        ct = ct0.clone().reshape(-1)
+        out = torch.empty(images * pl.tiles * lay.Co * 2 * L * N, dtype=torch.int32, device="cuda")
+        io = (d, ct, None, out, d_taps) if form == "taps" else (d, ct, d_wn, out)
+        b = hy.hyena_batch_create(ctx, [io], hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH)
+        if form == "taps":
+            assert hy.hyena_conv_schedule_taps(hy.hyena_batch_info(b)["mac_sched"][0]) >= 9
+        ct.copy_(ct0.reshape(-1))
+        hy.hyena_batch_run(b)
+        torch.cuda.synchronize()
+        outs.append(out)
+        hy.hyena_batch_destroy(b)
+        del ct
+    assert torch.equal(outs[0], outs[1])
+    got = outs[0].view(images, pl.tiles, lay.Co, 2, L, N)
+    host_ct = ct0[5].cpu().numpy().view(np.uint32)
+    sel = [(0, 0), (1, 77), (1, 127)]
+    want = orc.conv_products(pl, host_ct, w, ctx.primes, outputs=sel)
+    for u, (tau, o) in enumerate(sel):
+        assert np.array_equal(got[5, tau, o].cpu().numpy().view(np.uint32), want[u]), (tau, o)
+    hy.hyena_destroy(ctx)

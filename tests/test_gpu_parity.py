@@ -360,7 +360,10 @@ def test_every_mac_schedule_matches_oracle(dev, lay, c_n, batch):
     hy.hyena_ntt(ctx, d_ct)
     want = [orc.conv_products(pl, ct[b], w, ctx.primes).reshape(pl.tiles, lay.Co, 2, L, N) for b in range(batch)]
     ran = 0
+    streamed = [sid for sid in range(len(hy.hyena_conv_schedules())) if hy.hyena_conv_schedule_taps(sid) == 0]
     for sid, info in enumerate(hy.hyena_conv_schedules()):
+        if sid not in streamed:
+            continue   # synthesizing schedules read integer taps (test_conv_synth_equals_streamed_weights)
         try:
             hy.hyena_conv_tiled(ctx, d, d_ct, d_wn, d_out, sid)
         except hy.HyenaError as e:
@@ -372,7 +375,7 @@ def test_every_mac_schedule_matches_oracle(dev, lay, c_n, batch):
         for b in range(batch):
             assert np.array_equal(got[b], want[b]), (sid, info, b)
         ran += 1
-    assert ran >= (4 if lay.depthwise else len(hy.hyena_conv_schedules()))
+    assert ran >= (4 if lay.depthwise else len(streamed))
 
 
 @pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (8192, 2, 30), (16384, 2, 31)])
@@ -513,3 +516,114 @@ def test_conv_direct_rejects_overlap_and_unplanned(dev):
     bad = hy.ConvDesc()
     with pytest.raises(hy.HyenaError):       # descriptor never planned
         hy.hyena_conv_direct(ctx, bad, buf[:n_in], w, buf[n_in:])
+
+
+# ---------------------------------------------------------------- weights synthesized in the MAC
+
+SYNTH_CASES = [
+    # id, (N, L, bits), layer, c_n, batch, fused, ci_req
+    ("ci1_k3", (8192, 3, 31), wl.Layer("t", 64, 64, 3, 20, 3), 1, 1, True, 0),          # 9 taps, 3 groups
+    ("ci2_k3_cn4", (8192, 3, 31), wl.Layer("t", 56, 56, 64, 64, 3), 4, 2, True, 0),     # 18 taps, 32 groups
+    ("rowtiles_cn2", (4096, 2, 30), wl.Layer("t", 70, 70, 3, 8, 3), 2, 3, True, 0),     # 2 row tiles, batch 3
+    ("k1_ci16_cn8", (8192, 3, 31), wl.Layer("t", 14, 14, 64, 40, 1), 8, 1, True, 16),   # 1x1, 16 taps, 4 groups
+    ("unfused_cn4", (8192, 3, 31), wl.Layer("t", 28, 28, 10, 16, 3), 4, 2, False, 2),   # Walsh components out
+    ("short_group", (8192, 3, 31), wl.Layer("t", 20, 20, 7, 12, 1), 1, 5, True, 4),     # ragged last group
+]
+
+
+def _synth_setup(ctx, lay, c_n, batch, fuse, ci_req, seed):
+    import torch
+    N, L = ctx.N, ctx.L
+    flags = hy.HYENA_FUSE_WHT if fuse else 0
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=c_n, flags=flags, batch=batch,
+                           ci_req=ci_req)
+    pl = orc.plan(N, lay.H, lay.W, lay.Ci, lay.Co, lay.k, False, ci_req or None)
+    rng = np.random.default_rng(seed)
+    ct = rand_res(rng, (batch, pl.tiles, pl.n_groups, 2, L, N), ctx.primes)
+    w = wl.weights(seed, lay)
+    d_w = torch.from_numpy(w).cuda()
+    d_wn = torch.empty(hy.wntt_words(ctx, d), dtype=torch.int32, device="cuda")
+    hy.hyena_encode_weights(ctx, d, d_w, d_wn)
+    d_taps = torch.full((hy.synth_taps_words(d),), 12345, dtype=torch.int32, device="cuda")
+    hy.hyena_synth_taps(ctx, d, d_w, d_taps)
+    d_ct = to_dev(ct)
+    hy.hyena_ntt(ctx, d_ct)
+    return d, pl, ct, w, d_wn, d_taps, d_ct
+
+
+@pytest.mark.parametrize("c_n", [1, 2, 4, 64])
+def test_synth_taps_are_the_walsh_weights(dev, c_n):
+    """The integer-tap table equals the oracle's Walsh weights (Eq. (hadamard2)
+    generalised) arranged per output, input group and tap, zero past the last
+    input channel and in the padding."""
+    import torch
+    say(f"synth taps c_n={c_n}")
+    ctx = ctx_for(8192, 3, 31)
+    lay = wl.Layer("t", 56, 56, 5, 64, 3)                       # ci = 2: 3 groups, the last one short
+    d = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=c_n)
+    w = np.random.default_rng(c_n).integers(-128, 128, size=(64, 5, 3, 3)).astype(np.int8)
+    d_taps = torch.full((hy.synth_taps_words(d),), 7, dtype=torch.int32, device="cuda")
+    hy.hyena_synth_taps(ctx, d, torch.from_numpy(w).cuda(), d_taps)
+    torch.cuda.synchronize()
+    got = d_taps.cpu().numpy().reshape(64, d.w_groups, -1)
+    gw = orc.walsh_weights(w, c_n)                              # [Co][Ci][3][3]
+    T = d.ci * 9
+    want = np.zeros_like(got)
+    for g in range(d.w_groups):
+        chans = gw[:, g * d.ci:(g + 1) * d.ci].reshape(64, -1)  # taps c' k^2 + di k + dj
+        want[:, g, :chans.shape[1]] = chans
+    assert got.shape[2] == (T + 3) // 4 * 4
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name,params,lay,c_n,batch,fuse,ci_req", SYNTH_CASES, ids=[c[0] for c in SYNTH_CASES])
+def test_conv_synth_equals_streamed_weights(dev, name, params, lay, c_n, batch, fuse, ci_req):
+    """hyena_conv_synth (weight words synthesized in the multiply-accumulate
+    from the integer taps) against hyena_conv with the encoded weights, on every
+    output word, by its default schedule and by every synthesizing schedule
+    that fits the layer; the first case also against the oracle."""
+    import torch
+    say(f"conv synth {name}")
+    ctx = ctx_for(*params)
+    N, L = ctx.N, ctx.L
+    d, pl, ct, w, d_wn, d_taps, d_ct = _synth_setup(ctx, lay, c_n, batch, fuse, ci_req, 7000 + len(name))
+    n_out = batch * pl.tiles * lay.Co * 2 * L * N
+    ref = torch.empty(n_out, dtype=torch.int32, device="cuda")
+    hy.hyena_conv(ctx, d, d_ct, d_wn, ref)
+    out = torch.full((n_out,), -1, dtype=torch.int32, device="cuda")
+    hy.hyena_conv_synth(ctx, d, d_ct, d_taps, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref), int((out != ref).sum())
+    T = d.ci * d.k * d.k
+    tried = 0
+    for sid in range(len(hy.hyena_conv_schedules())):
+        tm = hy.hyena_conv_schedule_taps(sid)
+        if tm == 0 or tm < T:
+            continue
+        out.fill_(-1)
+        hy.hyena_conv_tiled(ctx, d, d_ct, d_taps, out, sid)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (sid, int((out != ref).sum()))
+        tried += 1
+    assert tried >= 2
+    if name == "ci1_k3":
+        hy.hyena_intt(ctx, out)
+        got = from_dev(out).reshape(batch, pl.tiles, lay.Co, 2, L, N)
+        want = orc.conv_products(pl, ct[0], w, ctx.primes).reshape(pl.tiles, lay.Co, 2, L, N)
+        assert np.array_equal(got[0], want)
+
+
+def test_conv_synth_refusals(dev):
+    import torch
+    ctx = ctx_for(8192, 3, 31)
+    big = hy.hyena_conv_plan(ctx, 14, 14, 64, 32, 3)             # ci = 32: 288 taps per word
+    dw = hy.hyena_conv_plan(ctx, 14, 14, 32, 32, 3, depthwise=True)
+    buf = torch.zeros(1 << 20, dtype=torch.int32, device="cuda")
+    for d, code in ((big, hy.HYENA_EUNSUPPORTED), (dw, hy.HYENA_EUNSUPPORTED)):
+        with pytest.raises(hy.HyenaError) as e:
+            hy.hyena_conv_synth(ctx, d, buf, buf, buf)
+        assert e.value.code == code
+    # a streaming schedule cannot run on taps alone, nor a synthesizing one on a 288-tap layer
+    sid = next(s for s in range(len(hy.hyena_conv_schedules())) if hy.hyena_conv_schedule_taps(s) == 18)
+    with pytest.raises(hy.HyenaError):
+        hy.hyena_conv_tiled(ctx, big, buf, buf, buf, sid)

@@ -298,3 +298,29 @@ def test_simd_conv_weights_packed():
                 assert np.array_equal(wa[o2, sl], 11 * (a + b)) and np.array_equal(wb[o2, sl], a - b)
     with pytest.raises(hy.HyenaError):                    # odd output count
         hy.hyena_simd_conv_weights_packed(f[:3], 11)
+
+
+def test_synth_taps_and_conv_synth_refusals():
+    """The integer-tap calls check their arguments before any launch: NULL
+    arrays, unplanned descriptors, depthwise layers (EUNSUPPORTED), more than
+    18 taps per word (EUNSUPPORTED) and host-only contexts are refused."""
+    ctx = hy.hyena_create(8192, 3, flags=HOST)
+    L = hy.lib()
+    fake = ctypes.c_void_p(0x10000)      # never dereferenced: every call below fails its checks first
+    null = ctypes.c_void_p(0)
+    d = hy.hyena_conv_plan(ctx, 64, 64, 3, 8, 3)                      # 9 taps per word
+    dd = hy.hyena_conv_plan(ctx, 14, 14, 32, 32, 3, depthwise=True)
+    big = hy.hyena_conv_plan(ctx, 14, 14, 64, 32, 3)                  # 288 taps per word
+    assert L.hyena_synth_taps(ctx.handle, ctypes.byref(d), null, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_synth_taps(ctx.handle, ctypes.byref(dd), fake, fake, null) == hy.HYENA_EUNSUPPORTED
+    assert L.hyena_synth_taps(ctx.handle, ctypes.byref(d), fake, fake, null) == hy.HYENA_EINVAL
+    assert "host-only" in L.hyena_last_error().decode()
+    assert L.hyena_conv_synth(ctx.handle, ctypes.byref(d), fake, null, fake, null) == hy.HYENA_EINVAL
+    assert L.hyena_conv_synth(ctx.handle, ctypes.byref(dd), fake, fake, fake, null) == hy.HYENA_EUNSUPPORTED
+    assert L.hyena_conv_synth(ctx.handle, ctypes.byref(big), fake, fake, fake, null) == hy.HYENA_EUNSUPPORTED
+    assert L.hyena_conv_synth(ctx.handle, ctypes.byref(d), fake, fake, fake, null) == hy.HYENA_EINVAL
+    assert "host-only" in L.hyena_last_error().decode()
+    # schedule table: the streaming schedules report 0, the synthesizing ones their tap bound
+    taps = [hy.hyena_conv_schedule_taps(s) for s in range(len(hy.hyena_conv_schedules()))]
+    assert taps.count(0) >= 25 and sorted(set(taps) - {0}) == [9, 18]
+    assert hy.synth_taps_words(d) == 8 * 3 * 12
