@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--primes", type=int, choices=[30, 31], default=31,
                     help="RNS primes below 2^31 (default) or below 2^30")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--alu-calibration", action="store_true",
+                    help="measure the integer VALU rates (v_mad_u64_u32, v_mul_lo/hi_u32, v_add_u32)")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alt-primes", action="store_true",
@@ -331,6 +333,18 @@ def copy_calibration(args, torch):
                       "GBs": 2 * n * 4 / dt / 1e9}))
 
 
+def alu_calibration(hy, torch):
+    """Lane operations per second of the integer instructions the kernels are
+    made of: eight independent chains per lane over 8192 blocks of 256 threads.
+    The ALU roof of a coeff-MAC is the v_mad_u64_u32 rate."""
+    blocks = 8192
+    d = torch.zeros(blocks * 256, dtype=torch.int32, device="cuda")
+    rates = {name: hy.hyena_valu_rate(i, d, blocks) / 1e12 for i, name in enumerate(hy.VALU_OPS)}
+    print(json.dumps({"unit": "T lane-ops/s", "rates": rates,
+                      "issue_peak_nominal": 256 * 4 * 32 * 2.4e9 / 1e12,
+                      "valu_peak_tops_used": VALU_PEAK_TOPS}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -344,6 +358,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.copy_calibration:
         copy_calibration(args, torch)
+        return
+    if args.alu_calibration:
+        alu_calibration(hy, torch)
         return
     hy.lib()
     log("setup ...")

@@ -694,6 +694,18 @@ int hyena_mlp_loss_grad(const float *d_theta, const float *d_x, const float *d_t
 int hyena_mlp_adam(float *d_theta, const float *d_grad, float *d_m, float *d_v, uint32_t step,
                    float lr, float beta1, float beta2, float eps, hyena_stream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Measurement helper: the integer instruction rates of the device, which the
+ * multiply-accumulate's and the NTT's ALU roofline fractions are quoted
+ * against. Runs `blocks` x 256 threads, each with eight independent chains of
+ * iters x 4 operations op (0: v_mad_u64_u32, 32 x 32 -> 64-bit product plus a
+ * 64-bit addend; 1: v_mul_lo_u32; 2: v_mul_hi_u32; 3: v_add_u32) on the null
+ * stream, after two untimed launches; returns the timed launch's duration in
+ * ms and its lane operations (rate = lane_ops / ms). d_out: device uint32
+ * [blocks * 256], overwritten. Synchronous. Errors: EINVAL, EHIP.
+ * ---------------------------------------------------------------------- */
+int hyena_valu_rate(int op, uint32_t blocks, uint32_t iters, uint32_t *d_out, float *ms, double *lane_ops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,6 +109,7 @@ _SIGS = {
     "hyena_synth_taps": [_P, _P, _P, _P, _P],
     "hyena_conv_synth": [_P, _P, _P, _P, _P, _P],
     "hyena_ntt_schedules": [_u32, _P, _P],
+    "hyena_valu_rate": [ctypes.c_int, _u32, _u32, _P, _P, _P],
     "hyena_ntt_sched": [_P, _P, _sz, ctypes.c_int, ctypes.c_int, _P],
 }
 
@@ -714,3 +715,16 @@ def hyena_mlp_adam(d_theta, d_grad, d_m, d_v, step: int, lr: float, beta1: float
     _check(lib().hyena_mlp_adam(_dev_ptr(d_theta, "float32"), _dev_ptr(d_grad, "float32"),
                                 _dev_ptr(d_m, "float32"), _dev_ptr(d_v, "float32"), step, lr, beta1, beta2,
                                 eps, _stream(stream)))
+
+
+VALU_OPS = ("v_mad_u64_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_add_u32")
+
+
+def hyena_valu_rate(op: int, d_out, blocks: int = 8192, iters: int = 2048) -> float:
+    """Measured lane operations per second of VALU_OPS[op] (d_out: int32 device
+    tensor of blocks * 256 elements)."""
+    _need(d_out, blocks * 256, "d_out")
+    ms = ctypes.c_float()
+    ops = ctypes.c_double()
+    _check(lib().hyena_valu_rate(op, blocks, iters, _dev_ptr(d_out, "int32"), ctypes.byref(ms), ctypes.byref(ops)))
+    return ops.value / (ms.value * 1e-3)

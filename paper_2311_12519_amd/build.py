@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhyena.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["params.cpp", "crypto.cpp", "plan.cpp", "ntt.hip", "conv.hip", "synth.hip", "direct.hip", "client.hip", "simd.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["params.cpp", "crypto.cpp", "plan.cpp", "ntt.hip", "conv.hip", "synth.hip", "direct.hip", "client.hip", "simd.hip", "batch.hip", "mlp.hip", "calib.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "--offload-arch=gfx950", "-O3", "-fPIC", "-Wall", "-Wextra", "-Werror",

@@ -245,10 +245,38 @@ __device__ __forceinline__ void fwd_front(uint32_t (&x)[1 << (LOGN - LOGT)], con
     }
 }
 
+// Store of the last pass's residues through LDS: each wave holds, per group
+// round kg, the 64 * 2^EP consecutive residues starting at 2^EP (kg T + 64 w);
+// it writes them to LDS where it read them and reads them back as 16-byte
+// pieces contiguous across lanes, so every global store instruction covers
+// 1 KiB contiguous (against 16-byte pieces 2^EP words apart when the runs are
+// stored from registers). Only the wave's own LDS words move: no barrier.
+template <int LOGN, int LOGT, int E_LOG, int EP>
+__device__ __forceinline__ void store_staged(const uint32_t (&x)[1 << E_LOG], uint32_t *__restrict__ a,
+                                             uint32_t *lds, uint32_t tid) {
+    constexpr int GE = 1 << EP, NG = (1 << E_LOG) >> EP;
+    static_assert(GE >= 4, "runs of at least four residues");
+    wave_lds_sync();
+    to_lds<LOGN, LOGT, E_LOG, LOGN - EP, EP>(x, lds, tid);
+    wave_lds_sync();
+    const uint32_t lane = tid & 63, w0 = tid & ~63u;
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++) {
+        const uint32_t base = (uint32_t)GE * ((uint32_t)kg * (1u << LOGT) + w0);
+#pragma unroll
+        for (int c = 0; c < GE / 4; c++) {
+            const uint32_t j = base + 4 * ((uint32_t)c * 64 + lane);
+            *reinterpret_cast<uint4 *>(a + j) =
+                make_uint4(lds[lds_idx(j)], lds[lds_idx(j + 1)], lds[lds_idx(j + 2)], lds[lds_idx(j + 3)]);
+        }
+    }
+}
+
 // Forward transform of one limb-polynomial a (N residues) by the block:
 // passes of E0, E1, E2 (, E3) stages; E0 = LOGN - LOGT is the register radix
 // (every thread holds 2^E0 residues). The first pass reads HBM with unit
-// stride across lanes, the last writes runs of consecutive residues; the
+// stride across lanes, the last writes runs of consecutive residues (staged
+// through the wave's LDS words into stores contiguous across lanes); the
 // passes between exchange residues through LDS.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
 __device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uint32_t *__restrict__ tw,
@@ -260,7 +288,9 @@ __device__ __forceinline__ void ntt_fwd_body(uint32_t *__restrict__ a, const uin
 #pragma unroll
     for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
     fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
-    store_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
+    constexpr int EF = E3 > 0 ? E3 : E2;
+    if constexpr ((1 << EF) >= 4) store_staged<LOGN, LOGT, E_LOG, EF>(x, a, lds, tid);
+    else store_runs<LOGT, E_LOG, EF>(x, a, tid);
 }
 
 // Inverse: Gentleman-Sande stages run in the reverse order of the forward

@@ -86,6 +86,36 @@ __global__ void __launch_bounds__(STH) automorphism_kernel(const uint32_t *in, u
     }
 }
 
+// The same permutation with the limb-polynomial staged in LDS: a block takes
+// whole limb-polynomials (grid-stride), reads one with 16-byte loads
+// contiguous across lanes, gathers the permuted coefficients from LDS and
+// writes them back with 16-byte stores contiguous across lanes, so HBM sees
+// one plain read and one plain write of every word. N words of dynamic LDS.
+__global__ void __launch_bounds__(STH) automorphism_lds_kernel(const uint32_t *in, uint32_t *out, size_t polys,
+                                                               uint32_t logN, uint32_t L, uint32_t ginv,
+                                                               LimbTable lt) {
+    extern __shared__ uint32_t sh[];
+    const uint32_t N = 1u << logN, mask = 2 * N - 1;
+    for (size_t poly = blockIdx.x; poly < polys; poly += gridDim.x) {
+        const uint32_t q = lt.c[poly % L].q;
+        const uint4 *src = reinterpret_cast<const uint4 *>(in + (poly << logN));
+        uint4 *dst = reinterpret_cast<uint4 *>(out + (poly << logN));
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) reinterpret_cast<uint4 *>(sh)[c] = src[c];
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t j = ((4 * c + u) * ginv) & mask;
+                const uint32_t a = sh[j & (N - 1)];
+                v[u] = (j < N || a == 0) ? a : q - a;
+            }
+            dst[c] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();   // the gathers precede the next polynomial's loads
+    }
+}
+
 struct Sparse {
     uint32_t n;                       // monomials
     uint32_t e[MAX_TERMS];            // exponents, < 2N
@@ -112,6 +142,39 @@ __global__ void __launch_bounds__(STH) pmult_sparse_kernel(const uint32_t *in, u
             acc = scsub(acc + smont(a, sp.cm[limb][t], q, qn), q);
         }
         out[base + i] = acc;
+    }
+}
+
+// The same sparse product with the limb-polynomial staged in LDS (16-byte
+// loads and stores contiguous across lanes; the shifted reads hit LDS).
+__global__ void __launch_bounds__(STH) pmult_sparse_lds_kernel(const uint32_t *in, uint32_t *out, size_t polys,
+                                                               uint32_t logN, uint32_t L, LimbTable lt, Sparse sp) {
+    extern __shared__ uint32_t sh[];
+    const uint32_t N = 1u << logN, mask = 2 * N - 1;
+    for (size_t poly = blockIdx.x; poly < polys; poly += gridDim.x) {
+        const uint32_t limb = (uint32_t)(poly % L);
+        const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg;
+        const uint4 *src = reinterpret_cast<const uint4 *>(in + (poly << logN));
+        uint4 *dst = reinterpret_cast<uint4 *>(out + (poly << logN));
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) reinterpret_cast<uint4 *>(sh)[c] = src[c];
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t i = 4 * c + u;
+                uint32_t acc = 0;
+                for (uint32_t t = 0; t < sp.n; t++) {
+                    const uint32_t d = (i - sp.e[t]) & mask;
+                    uint32_t a = sh[d & (N - 1)];
+                    if (d >= N) a = a ? q - a : 0;
+                    acc = scsub(acc + smont(a, sp.cm[limb][t], q, qn), q);
+                }
+                v[u] = acc;
+            }
+            dst[c] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();
     }
 }
 
@@ -444,8 +507,14 @@ extern "C" int hyena_automorphism(const hyena_ctx *c, const uint32_t *d_in, size
     uint32_t x = g;   // correct to 3 bits (g g = 1 mod 8)
     for (int it = 0; it < 5; it++) x *= 2u - g * x;
     const uint32_t ginv = x & mask;
-    hipLaunchKernelGGL(automorphism_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, (hipStream_t)stream,
-                       d_in, d_out, polys, c->logN, c->L, ginv, c->lt);
+    if ((((uintptr_t)d_in | (uintptr_t)d_out) & 15u) == 0) {
+        // whole limb-polynomials through LDS; a few resident blocks per CU
+        hipLaunchKernelGGL(automorphism_lds_kernel, dim3((unsigned)std::min<size_t>(polys, 4096)), dim3(STH),
+                           c->N * 4, (hipStream_t)stream, d_in, d_out, polys, c->logN, c->L, ginv, c->lt);
+    } else {
+        hipLaunchKernelGGL(automorphism_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0,
+                           (hipStream_t)stream, d_in, d_out, polys, c->logN, c->L, ginv, c->lt);
+    }
     return slaunched(who);
 }
 
@@ -468,8 +537,13 @@ extern "C" int hyena_pmult_sparse(const hyena_ctx *c, const uint32_t *d_in, size
         sp.e[t] = exps[t];
         for (uint32_t i = 0; i < c->L; i++) sp.cm[i][t] = to_montgomery(coefs[t] % c->q[i], c->q[i]);
     }
-    hipLaunchKernelGGL(pmult_sparse_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0, (hipStream_t)stream,
-                       d_in, d_out, polys, c->logN, c->L, c->lt, sp);
+    if ((((uintptr_t)d_in | (uintptr_t)d_out) & 15u) == 0) {
+        hipLaunchKernelGGL(pmult_sparse_lds_kernel, dim3((unsigned)std::min<size_t>(polys, 4096)), dim3(STH),
+                           c->N * 4, (hipStream_t)stream, d_in, d_out, polys, c->logN, c->L, c->lt, sp);
+    } else {
+        hipLaunchKernelGGL(pmult_sparse_kernel, dim3(sgrid(polys << (c->logN - 8))), dim3(STH), 0,
+                           (hipStream_t)stream, d_in, d_out, polys, c->logN, c->L, c->lt, sp);
+    }
     return slaunched(who);
 }
 

@@ -120,6 +120,15 @@ def test_automorphism_matches_oracle(dev, N, L, bits):
         for r in range(P):
             for i, q in enumerate(ctx.primes):
                 assert np.array_equal(got[r, i], simd.automorphism(a[r, i], g % (2 * N), q)), (g, r, i)
+    # arrays that are not 16-byte aligned take the coefficient-gather kernel
+    import torch
+    d_a4 = torch.zeros(a.size + 1, dtype=torch.int32, device="cuda")
+    d_a4[1:] = d_a.reshape(-1)
+    d_o4 = torch.zeros(a.size + 1, dtype=torch.int32, device="cuda")
+    hy.hyena_automorphism(ctx, d_a4[1:], 5, d_o4[1:])
+    got = from_dev(d_o4[1:]).reshape(P, L, N)
+    for i, q in enumerate(ctx.primes):
+        assert np.array_equal(got[1, i], simd.automorphism(a[1, i], 5, q))
 
 
 @pytest.mark.parametrize("N,L,bits", [(2048, 2, 30), (8192, 3, 31)])
@@ -137,9 +146,16 @@ def test_pmult_sparse_matches_oracle(dev, N, L, bits):
     _, _, kh = hy.hyena_simd_params(2048, 307201, 61)
     cases = [([N // 4, 3 * N // 4], [kh, kh]),
              (sorted(rng.choice(2 * N, 16, replace=False).tolist()), rng.integers(0, 307201, 16).tolist())]
+    import torch
+    d_a4 = torch.zeros(a.size + 1, dtype=torch.int32, device="cuda")
+    d_a4[1:] = d_a.reshape(-1)
+    d_o4 = torch.zeros(a.size + 1, dtype=torch.int32, device="cuda")
     for exps, coefs in cases:
         hy.hyena_pmult_sparse(ctx, d_a, exps, coefs, d_o)
         got = from_dev(d_o).reshape(P, L, N)
+        # arrays that are not 16-byte aligned take the coefficient-gather kernel
+        hy.hyena_pmult_sparse(ctx, d_a4[1:], exps, coefs, d_o4[1:])
+        assert np.array_equal(from_dev(d_o4[1:]).reshape(P, L, N), got)
         for i, q in enumerate(ctx.primes):
             w = np.zeros(N, dtype=np.int64)
             for e, c in zip(exps, coefs):                 # X^e = -X^{e-N} for e >= N
