@@ -51,10 +51,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# ALU roof of a coeff-MAC (one v_mad_u64_u32): full-rate VALU issue is
-# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-ops/s (the fp32 vector
-# peak of 157.3 TFLOP/s counts an FMA as two); v_mad_u64_u32 issues at half rate
-VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 2 / 1e12
+# ALU roof of a coeff-MAC (one v_mad_u64_u32): 32-bit integer VALU
+# instructions, the 64-bit multiply-add included, issue at 16 lanes per clock
+# per SIMD: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
+# (measured 36.7-38.7 T/s by --alu-calibration; the fp32 vector peak of
+# 157.3 TFLOP/s counts packed fp32 FMAs, which integer code has no form of)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# integer VALU instructions of one exact butterfly with primes below 2^31: a
+# Montgomery product (two v_mad_u64_u32, one v_mul_lo_u32) and seven adds,
+# subtracts and minima (the modular sum, difference and corrections)
+NTT_OPS_PER_BUTTERFLY = 10
 
 
 def log(*a):
@@ -505,10 +511,22 @@ def main():
                                **common}
         ntt_bytes = sum(o.in_words * 4 * 2 for o in layers) * n_img
         intt_bytes = sum(o.out_words * 4 * 2 for o in layers) * n_img
+
+        def ntt_roof(ms, nbytes):
+            # limb-polynomials of N words; N/2 log2 N butterflies each, every one
+            # at least NTT_OPS_PER_BUTTERFLY integer VALU instructions
+            polys = nbytes / 8 / 8192
+            ops = polys * 4096 * 13 * NTT_OPS_PER_BUTTERFLY
+            t_hbm = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+            t_alu = ops / (VALU_PEAK_TOPS * 1e12) * 1e3
+            return {"ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": t_hbm / ms,
+                    "alu_Tops": ops / (ms * 1e-3) / 1e12, "alu_frac": t_alu / ms,
+                    "roof_ms": {"hbm": t_hbm, "alu": t_alu}, "bound": "alu" if t_alu > t_hbm else "hbm"}
+
         out["kernels"] = {
-            "ntt": {"ms": km["ntt"], "GBs": ntt_bytes / (km["ntt"] * 1e-3) / 1e9},
+            "ntt": ntt_roof(km["ntt"], ntt_bytes),
             "mac": {"ms": mac_ms, "GBs": mac_gbs, "Tcoeff_macs": ach},
-            "intt": {"ms": km["intt"], "GBs": intt_bytes / (km["intt"] * 1e-3) / 1e9},
+            "intt": ntt_roof(km["intt"], intt_bytes),
         }
     if head_mode == "tuned":
         out["kernels"]["wht"] = wht_bandwidth(ctx, layers, hy, torch)
