@@ -28,6 +28,21 @@ __device__ __forceinline__ uint32_t smont(uint32_t a, uint32_t b, uint32_t q, ui
 
 __device__ __forceinline__ uint32_t brev(uint32_t x, uint32_t logn) { return __brev(x) >> (32 - logn); }
 
+// Lazy key-switch sums: products of residues below q summed in 64 bits,
+// folded (hi 2^32 + lo -> hi r32 + lo, r32 = 2^32 mod q) after every lc.fold
+// of them, which keeps the sum below 2^64; ks_reduce then folds once more
+// (bringing it below q 2^32) and takes one Montgomery reduction: the sum
+// times 2^-32 mod q, in [0, q).
+__device__ __forceinline__ uint64_t ks_fold(uint64_t acc, uint32_t r32) {
+    return (uint64_t)(uint32_t)(acc >> 32) * r32 + (uint32_t)acc;
+}
+
+__device__ __forceinline__ uint32_t ks_reduce(uint64_t acc, const LimbConst &lc) {
+    const uint64_t y = ks_fold(acc, lc.r32);
+    const uint32_t m = (uint32_t)y * lc.qinv_neg;
+    return scsub((uint32_t)(((uint64_t)m * lc.q + y) >> 32), lc.q);
+}
+
 // NTT index (evaluation at psi^(2 brv(k) + 1)) of slot s
 __device__ __forceinline__ uint32_t slot_to_ntt(uint32_t s, uint32_t logN) {
     const uint32_t N = 1u << logN, mask = 2 * N - 1, h = N / 2;
@@ -287,7 +302,7 @@ __global__ void __launch_bounds__(STH) keyswitch_keys_kernel(const uint32_t *wor
         const uint32_t e = ((2 * brev(s, logN) + 1) * ra.g[r]) & mask;
         const uint32_t sr = brev(e >> 1, logN);
         const LimbConst &lc = lt.c[k];
-        const uint32_t q = lc.q, qn = lc.qinv_neg;
+        const uint32_t q = lc.q;
         const uint32_t *kr = ksk + (size_t)r * TD * 2 * LN + (size_t)k * N + s;
         uint32_t k0[TD], k1[TD];
 #pragma unroll
@@ -301,15 +316,106 @@ __global__ void __launch_bounds__(STH) keyswitch_keys_kernel(const uint32_t *wor
             uint32_t d[TD + 1];
 #pragma unroll
             for (uint32_t t = 0; t <= TD; t++) d[t] = wm[(size_t)t * LN];
-            uint32_t acc0 = d[TD], acc1 = 0;
+            uint64_t a0 = 0, a1 = 0;
+            uint32_t since = 0;
 #pragma unroll
             for (uint32_t t = 0; t < TD; t++) {
-                acc0 = scsub(acc0 + smont(d[t], k0[t], q, qn), q);
-                acc1 = scsub(acc1 + smont(d[t], k1[t], q, qn), q);
+                a0 += (uint64_t)d[t] * k0[t];
+                a1 += (uint64_t)d[t] * k1[t];
+                if (++since == lc.fold) {
+                    a0 = ks_fold(a0, lc.r32);
+                    a1 = ks_fold(a1, lc.r32);
+                    since = 0;
+                }
             }
             uint32_t *o = out + ((size_t)m * ra.n_rot + r) * 2 * LN + (size_t)k * N + s;
-            o[0] = acc0;
-            o[LN] = acc1;
+            o[0] = scsub(ks_reduce(a0, lc) + d[TD], q);
+            o[LN] = ks_reduce(a1, lc);
+        }
+    }
+}
+
+// The same key switching with the rotations in the inner loop: a thread owns
+// one digit slot sd of KS_R ciphertexts and one limb, loads their TD digits
+// and c0 there once, and for every rotation r sums the output slot s whose
+// permuted source is sd (s = brv((e_d g_r^-1 mod 2N - 1) / 2) for
+// e_d = 2 brv(sd) + 1) with that rotation's keys at s. The digits are read
+// once for all rotations instead of once per rotation; the keys of a
+// rotation are read once per KS_R ciphertexts. The permutation maps the
+// wave's aligned block of 64 source slots onto one aligned block of output
+// slots, so keys are loaded and sums stored in slot order (lane j at slot
+// block + j, 256 contiguous bytes per access) and permuted across the wave's
+// lanes in registers.
+constexpr uint32_t KS_R = 8;
+
+struct RotInv {
+    uint32_t ginv[MAX_ROT];   // g_r^-1 mod 2N
+};
+
+template <uint32_t TD>
+__global__ void __launch_bounds__(STH) keyswitch_rot_kernel(const uint32_t *work, const uint32_t *ksk, uint32_t *out,
+                                                            uint32_t n_ct, uint32_t logN, uint32_t L, LimbTable lt,
+                                                            RotArgs ra, RotInv ri) {
+    const uint32_t N = 1u << logN, mask = 2 * N - 1, cpl = 1u << (logN - 8);
+    const size_t LN = (size_t)L << logN;
+    const uint32_t groups = (n_ct + KS_R - 1) / KS_R;
+    const uint32_t chunks = groups * L * cpl;   // < 2^31 (checked on the host)
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const uint32_t sch = c % cpl, rest = c / cpl;
+        const uint32_t k = rest % L, mg = rest / L;
+        const uint32_t sd = (sch << 8) + threadIdx.x;
+        const uint32_t ed = 2 * brev(sd, logN) + 1;
+        const LimbConst &lc = lt.c[k];
+        const uint32_t q = lc.q;
+        const uint32_t m0 = mg * KS_R, nm = min(KS_R, n_ct - m0);
+        uint32_t d[KS_R][TD + 1];
+#pragma unroll
+        for (uint32_t u = 0; u < KS_R; u++) {
+            if (u >= nm) break;
+            const uint32_t *wm = work + (size_t)(m0 + u) * (TD + 1) * LN + (size_t)k * N + sd;
+#pragma unroll
+            for (uint32_t t = 0; t <= TD; t++) d[u][t] = wm[(size_t)t * LN];
+        }
+        const uint32_t lane = threadIdx.x & 63, sbase = sd - lane;
+        for (uint32_t r = 0; r < ra.n_rot; r++) {
+            // output slot of this lane's source slot; the wave's 64 source
+            // slots fill the aligned output block at obase
+            const uint32_t s = brev((((ed * ri.ginv[r]) & mask) - 1) >> 1, logN);
+            const uint32_t obase = __builtin_amdgcn_readfirstlane(s & ~63u);
+            // the lane stores output slot so, whose source slot is sr; keys
+            // are read and sums stored at so (whole 256-byte rows), and moved
+            // between lanes by ds_bpermute
+            const uint32_t so = obase + lane;
+            const uint32_t sr = brev((((2 * brev(so, logN) + 1) * ra.g[r]) & mask) >> 1, logN);
+            const int kaddr = (int)((s - obase) << 2);   // lane that read the keys of slot s
+            const int oaddr = (int)((sr - sbase) << 2);  // lane that summed slot so
+            const uint32_t *kr = ksk + (size_t)r * TD * 2 * LN + (size_t)k * N + so;
+            uint32_t k0[TD], k1[TD];
+#pragma unroll
+            for (uint32_t t = 0; t < TD; t++) {
+                k0[t] = (uint32_t)__builtin_amdgcn_ds_bpermute(kaddr, (int)kr[(size_t)(2 * t) * LN]);
+                k1[t] = (uint32_t)__builtin_amdgcn_ds_bpermute(kaddr, (int)kr[(size_t)(2 * t + 1) * LN]);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < KS_R; u++) {
+                if (u >= nm) break;
+                uint64_t a0 = 0, a1 = 0;
+                uint32_t since = 0;
+#pragma unroll
+                for (uint32_t t = 0; t < TD; t++) {
+                    a0 += (uint64_t)d[u][t] * k0[t];
+                    a1 += (uint64_t)d[u][t] * k1[t];
+                    if (++since == lc.fold) {
+                        a0 = ks_fold(a0, lc.r32);
+                        a1 = ks_fold(a1, lc.r32);
+                        since = 0;
+                    }
+                }
+                const uint32_t v0 = scsub(ks_reduce(a0, lc) + d[u][TD], q), v1 = ks_reduce(a1, lc);
+                uint32_t *o = out + ((size_t)(m0 + u) * ra.n_rot + r) * 2 * LN + (size_t)k * N + so;
+                o[0] = (uint32_t)__builtin_amdgcn_ds_bpermute(oaddr, (int)v0);
+                o[LN] = (uint32_t)__builtin_amdgcn_ds_bpermute(oaddr, (int)v1);
+            }
         }
     }
 }
@@ -596,18 +702,40 @@ static int hrot_impl(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint
     if (int rc = launch_ntt(c, d_work, n_ct * T, false, s)) return rc;
     const uint32_t TD = c->L * ra.D;
     const size_t kchunks = (((n_ct + KS_M - 1) / KS_M) * n_rot * c->L) << (c->logN - 8);
+    const size_t rchunks = (((n_ct + KS_R - 1) / KS_R) * c->L) << (c->logN - 8);
+    RotInv ri{};
+    for (uint32_t r = 0; r < n_rot; r++) {
+        // g^-1 mod 2N for odd g: Newton's iteration x <- x (2 - g x) doubles the correct low bits
+        uint32_t x = ra.g[r];
+        for (int it = 0; it < 5; it++) x *= 2u - ra.g[r] * x;
+        ri.ginv[r] = x & (2 * c->N - 1);
+    }
+    // with several rotations and few enough digit terms to hold KS_R
+    // ciphertexts' digits in registers, the rotation-looping kernel
+#define HY_KR(td)                                                                                                  \
+    case td:                                                                                                       \
+        hipLaunchKernelGGL(keyswitch_rot_kernel<td>, dim3(sgrid(rchunks)), dim3(STH), 0, s, d_work, d_ksk, d_out, \
+                           (uint32_t)n_ct, c->logN, c->L, c->lt, ra, ri);                                          \
+        looped = true;                                                                                             \
+        break;
 #define HY_KS(td)                                                                                               \
     case td:                                                                                                    \
         hipLaunchKernelGGL(keyswitch_keys_kernel<td>, dim3(sgrid(kchunks)), dim3(STH), 0, s, d_work, d_ksk, d_out, \
                            (uint32_t)n_ct, c->logN, c->L, c->lt, ra);                                           \
         break;
-    switch (TD) {
+    bool looped = false;
+    if (n_rot >= 2) switch (TD) {
+            HY_KR(1) HY_KR(2) HY_KR(3) HY_KR(4) HY_KR(6) HY_KR(8)
+            default: break;
+        }
+    if (!looped) switch (TD) {
         HY_KS(1) HY_KS(2) HY_KS(3) HY_KS(4) HY_KS(6) HY_KS(8) HY_KS(9) HY_KS(12)
         default:
             hipLaunchKernelGGL(keyswitch_kernel, dim3(sgrid(((n_ct * n_rot) * c->L) << (c->logN - 8))), dim3(STH), 0,
                                s, d_work, d_ksk, d_out, n_ct, c->logN, c->L, c->lt, ra);
     }
 #undef HY_KS
+#undef HY_KR
     if (int rc = slaunched(who)) return rc;
     return intt_out ? launch_ntt(c, d_out, n_ct * n_rot * 2, true, s) : HYENA_OK;
 }

@@ -184,9 +184,9 @@ def test_simd_calls_reject_bad_arguments(dev):
         hy.hyena_pmult_sparse(cctx, buf[:2 * 2048], list(range(17)), [1] * 17, buf[4 * 2048:6 * 2048])
 
 
-def _hrot_setup(N, L, b, gs, n_ct, seed):
+def _hrot_setup(N, L, b, gs, n_ct, seed, bits=30):
     import torch
-    ctx = ctx_for(N, L, 30)
+    ctx = ctx_for(N, L, bits)
     primes = ctx.primes
     s = orc.keygen(N, seed)
     rng = np.random.default_rng(seed)
@@ -237,6 +237,33 @@ def test_hrot_hoisted_papers_parameters_nine_rotations(dev):
         for r, g in enumerate(gs):
             want = simd.automorphism(msg[m] % t, g, t).astype(np.int64)
             assert np.array_equal(dec[m, r], np.where(want > t // 2, want - t, want)), (m, r)
+
+
+def test_hrot_hoisted_ragged_ciphertext_groups(dev):
+    """11 ciphertexts (groups of eight and a ragged three) under three
+    rotations at b = 11: every output equals the oracle's hoisted HRot bit
+    for bit."""
+    N, L, b = 1024, 2, 11
+    gs = [5, 2 * N - 3, 3]
+    say(f"hrot hoisted N={N} L={L} b={b}, 11 ciphertexts")
+    ctx, s, msg, ct, keys, got = _hrot_setup(N, L, b, gs, 11, 23)
+    for m in range(11):
+        for r, g in enumerate(gs):
+            assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
+
+
+@pytest.mark.parametrize("L,b", [(2, 16), (3, 8), (3, 11)])
+def test_hrot_hoisted_31_bit_primes(dev, L, b):
+    """Primes below 2^31, where the key switch's 64-bit sums are folded after
+    every few products (L D = 4, 12 and 9 digit terms): every output equals
+    the oracle's hoisted HRot bit for bit."""
+    N = 1024
+    gs = [3, 2 * N - 1, 25]
+    say(f"hrot hoisted N={N} L={L} b={b}, primes < 2^31")
+    ctx, s, msg, ct, keys, got = _hrot_setup(N, L, b, gs, 3, 60 + b, bits=31)
+    for m in range(3):
+        for r, g in enumerate(gs):
+            assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
 
 
 def test_hrot_rejects_bad_arguments(dev):
