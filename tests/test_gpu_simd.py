@@ -266,6 +266,18 @@ def test_hrot_hoisted_31_bit_primes(dev, L, b):
             assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
 
 
+@pytest.mark.parametrize("N,L,b", [(4096, 2, 16), (8192, 3, 11), (16384, 2, 16)])
+def test_hrot_hoisted_larger_rings(dev, N, L, b):
+    """n = 4096, 8192 and 16384 (primes below 2^31): every output equals the
+    oracle's hoisted HRot bit for bit."""
+    gs = [3, 2 * N - 1]
+    say(f"hrot hoisted N={N} L={L} b={b}")
+    ctx, s, msg, ct, keys, got = _hrot_setup(N, L, b, gs, 2, 80 + b, bits=31)
+    for m in range(2):
+        for r, g in enumerate(gs):
+            assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
+
+
 def test_hrot_rejects_bad_arguments(dev):
     import torch
     ctx = ctx_for(1024, 2, 30)
