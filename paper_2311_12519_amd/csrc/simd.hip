@@ -28,11 +28,10 @@ __device__ __forceinline__ uint32_t smont(uint32_t a, uint32_t b, uint32_t q, ui
 
 __device__ __forceinline__ uint32_t brev(uint32_t x, uint32_t logn) { return __brev(x) >> (32 - logn); }
 
-// Lazy key-switch sums: products of residues below q summed in 64 bits,
-// folded (hi 2^32 + lo -> hi r32 + lo, r32 = 2^32 mod q) after every lc.fold
-// of them, which keeps the sum below 2^64; ks_reduce then folds once more
-// (bringing it below q 2^32) and takes one Montgomery reduction: the sum
-// times 2^-32 mod q, in [0, q).
+// Lazy key-switch sums: products of residues below q summed in 64 bits and
+// folded (hi 2^32 + lo -> hi r32 + lo, r32 = 2^32 mod q) before they could
+// reach 2^64; ks_reduce folds once more (bringing the sum below q 2^32) and
+// takes one Montgomery reduction: the sum times 2^-32 mod q, in [0, q).
 __device__ __forceinline__ uint64_t ks_fold(uint64_t acc, uint32_t r32) {
     return (uint64_t)(uint32_t)(acc >> 32) * r32 + (uint32_t)acc;
 }
@@ -41,6 +40,25 @@ __device__ __forceinline__ uint32_t ks_reduce(uint64_t acc, const LimbConst &lc)
     const uint64_t y = ks_fold(acc, lc.r32);
     const uint32_t m = (uint32_t)y * lc.qinv_neg;
     return scsub((uint32_t)(((uint64_t)m * lc.q + y) >> 32), lc.q);
+}
+
+// sum_t d[t] k[t] 2^-32 mod q for TD terms below q < 2^31: even and odd terms
+// in two independent chains, each folded after every second product (a
+// fold leaves less than (r32 + 1) 2^32 <= 2^63, and two products add less
+// than 2^63, so no sum reaches 2^64, with no branch between the terms)
+template <uint32_t TD>
+__device__ __forceinline__ uint32_t ks_dot(const uint32_t (&d)[TD + 1], const uint32_t (&k)[TD], const LimbConst &lc) {
+    uint64_t a[2] = {0, 0};
+#pragma unroll
+    for (uint32_t t = 0; t < TD; t++) {
+        a[t & 1] += (uint64_t)d[t] * k[t];
+        if ((t & 3) == 3 && t + 1 < TD) {
+            a[0] = ks_fold(a[0], lc.r32);
+            a[1] = ks_fold(a[1], lc.r32);
+        }
+    }
+    // each folded chain is below (r32 + 1) 2^32, so their sum fits 64 bits
+    return ks_reduce(ks_fold(a[0], lc.r32) + ks_fold(a[1], lc.r32), lc);
 }
 
 // NTT index (evaluation at psi^(2 brv(k) + 1)) of slot s
@@ -316,21 +334,9 @@ __global__ void __launch_bounds__(STH) keyswitch_keys_kernel(const uint32_t *wor
             uint32_t d[TD + 1];
 #pragma unroll
             for (uint32_t t = 0; t <= TD; t++) d[t] = wm[(size_t)t * LN];
-            uint64_t a0 = 0, a1 = 0;
-            uint32_t since = 0;
-#pragma unroll
-            for (uint32_t t = 0; t < TD; t++) {
-                a0 += (uint64_t)d[t] * k0[t];
-                a1 += (uint64_t)d[t] * k1[t];
-                if (++since == lc.fold) {
-                    a0 = ks_fold(a0, lc.r32);
-                    a1 = ks_fold(a1, lc.r32);
-                    since = 0;
-                }
-            }
             uint32_t *o = out + ((size_t)m * ra.n_rot + r) * 2 * LN + (size_t)k * N + s;
-            o[0] = scsub(ks_reduce(a0, lc) + d[TD], q);
-            o[LN] = ks_reduce(a1, lc);
+            o[0] = scsub(ks_dot<TD>(d, k0, lc) + d[TD], q);
+            o[LN] = ks_dot<TD>(d, k1, lc);
         }
     }
 }
@@ -399,19 +405,7 @@ __global__ void __launch_bounds__(STH) keyswitch_rot_kernel(const uint32_t *work
 #pragma unroll
             for (uint32_t u = 0; u < KS_R; u++) {
                 if (u >= nm) break;
-                uint64_t a0 = 0, a1 = 0;
-                uint32_t since = 0;
-#pragma unroll
-                for (uint32_t t = 0; t < TD; t++) {
-                    a0 += (uint64_t)d[u][t] * k0[t];
-                    a1 += (uint64_t)d[u][t] * k1[t];
-                    if (++since == lc.fold) {
-                        a0 = ks_fold(a0, lc.r32);
-                        a1 = ks_fold(a1, lc.r32);
-                        since = 0;
-                    }
-                }
-                const uint32_t v0 = scsub(ks_reduce(a0, lc) + d[u][TD], q), v1 = ks_reduce(a1, lc);
+                const uint32_t v0 = scsub(ks_dot<TD>(d[u], k0, lc) + d[u][TD], q), v1 = ks_dot<TD>(d[u], k1, lc);
                 uint32_t *o = out + ((size_t)(m0 + u) * ra.n_rot + r) * 2 * LN + (size_t)k * N + so;
                 o[0] = (uint32_t)__builtin_amdgcn_ds_bpermute(oaddr, (int)v0);
                 o[LN] = (uint32_t)__builtin_amdgcn_ds_bpermute(oaddr, (int)v1);
@@ -724,7 +718,9 @@ static int hrot_impl(const hyena_ctx *c, const uint32_t *d_ct, size_t n_ct, uint
                            (uint32_t)n_ct, c->logN, c->L, c->lt, ra);                                           \
         break;
     bool looped = false;
-    if (n_rot >= 2) switch (TD) {
+    // (only when it still gives every CU several blocks: it has n_rot times
+    // fewer than the per-rotation kernel)
+    if (n_rot >= 2 && rchunks >= 2048) switch (TD) {
             HY_KR(1) HY_KR(2) HY_KR(3) HY_KR(4) HY_KR(6) HY_KR(8)
             default: break;
         }

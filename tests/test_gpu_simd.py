@@ -278,6 +278,37 @@ def test_hrot_hoisted_larger_rings(dev, N, L, b):
             assert np.array_equal(got[m, r], simd.hrot(ctx.primes, ct[m], g, keys[r], b)), (m, g)
 
 
+def test_hrot_hoisted_many_ciphertexts_rotation_loop(dev):
+    """2045 random ciphertexts (a ragged last group of five) under three
+    rotations, enough that the key switch loops over the rotations inside the
+    thread, with primes below 2^31 (sums folded after every few products):
+    sampled outputs equal the oracle's hoisted HRot bit for bit (keys from the
+    oracle's key generation)."""
+    import torch
+    N, L, b = 1024, 2, 11
+    gs = [3, 5, 2 * N - 1]
+    n_ct = 2045
+    say(f"hrot hoisted N={N} L={L} b={b}, {n_ct} ciphertexts")
+    ctx = ctx_for(N, L, 31)
+    primes = ctx.primes
+    s = orc.keygen(N, 31)
+    rng = np.random.default_rng(31)
+    ct = np.empty((n_ct, 2, L, N), dtype=np.uint32)
+    for k, q in enumerate(primes):
+        ct[:, :, k, :] = rng.integers(0, q, size=(n_ct, 2, N), dtype=np.uint64).astype(np.uint32)
+    keys = np.stack([simd.galois_keygen(primes, s, g, b, 700 + g) for g in gs])
+    d_k = to_dev(keys)
+    hy.hyena_ksk_prepare(ctx, d_k)
+    D = hy.n_digits(b)
+    d_work = torch.empty(n_ct * (L * D + 1) * L * N, dtype=torch.int32, device="cuda")
+    d_out = torch.empty(n_ct * len(gs) * 2 * L * N, dtype=torch.int32, device="cuda")
+    hy.hyena_hrot_hoisted(ctx, to_dev(ct), gs, b, d_k, d_work, d_out)
+    got = from_dev(d_out).reshape(n_ct, len(gs), 2, L, N)
+    for m in (0, 7, 8, 1001, 2039, 2040, 2044):
+        for r, g in enumerate(gs):
+            assert np.array_equal(got[m, r], simd.hrot(primes, ct[m], g, keys[r], b)), (m, g)
+
+
 def test_hrot_rejects_bad_arguments(dev):
     import torch
     ctx = ctx_for(1024, 2, 30)
