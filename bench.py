@@ -51,11 +51,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# ALU roof of a coeff-MAC (one v_mad_u64_u32): 32-bit integer VALU
-# instructions, the 64-bit multiply-add included, issue at 16 lanes per clock
-# per SIMD: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s
-# (measured 36.7-38.7 T/s by --alu-calibration; the fp32 vector peak of
-# 157.3 TFLOP/s counts packed fp32 FMAs, which integer code has no form of)
+# ALU roof of the integer kernels: 32-bit integer VALU instructions, the
+# 64-bit multiply-add included, issue at 16 lanes per clock per SIMD:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (measured
+# 36.7-38.7 T/s by --alu-calibration; the fp32 vector peak of 157.3 TFLOP/s
+# counts packed fp32 FMAs, which integer code has no form of). A coeff-MAC is
+# one v_mad_u64_u32 plus its share of the accumulator folds: a v_mov and a
+# v_mad_u64_u32 per accumulator after every F products (F from the primes,
+# lazy_fold_interval; the instructions of the multiply-accumulate loop)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # integer VALU instructions of one exact butterfly with primes below 2^31: a
 # Montgomery product (two v_mad_u64_u32, one v_mul_lo_u32) and seven adds,
@@ -484,11 +487,15 @@ def main():
         io_bytes = sum((o.in_words + o.out_words) * 4 for o in layers) * n_img
         mac_gbs = (w_bytes + io_bytes) / (mac_ms * 1e-3) / 1e9
         ach = total_macs / (mac_ms * 1e-3) / 1e12
+        # VALU instructions per coeff-MAC: the multiply-add and the folds
+        fold_f = lazy_fold_interval(ctx.primes)
+        ops_per_mac = 1 + 2 / fold_f
+        ach_ops = ach * ops_per_mac
         # the binding roof is the one whose time at peak is longer: the HBM
-        # time of the algorithmic bytes or the VALU time of one
-        # v_mad_u64_u32 per coeff-MAC
+        # time of the algorithmic bytes or the VALU time of the
+        # multiply-accumulate's instructions
         t_hbm = (w_bytes + io_bytes) / (HBM_PEAK_GBS * 1e9)
-        t_alu = total_macs / (VALU_PEAK_TOPS * 1e12)
+        t_alu = total_macs * ops_per_mac / (VALU_PEAK_TOPS * 1e12)
         # the tuned step runs the multiply-accumulate as one persistent launch
         # unless its autotuner found per-layer launches clearly faster
         persistent = head_mode == "tuned" and head["schedules"]["persistent_launches"] > 0
@@ -500,15 +507,16 @@ def main():
                   "algorithmic_bytes_per_step": w_bytes + io_bytes,
                   "launches_per_step": launches,
                   "roof_ms": {"hbm": t_hbm * 1e3, "alu": t_alu * 1e3},
-                  "alu_achieved_TOPs": ach, "alu_peak_TOPs": VALU_PEAK_TOPS, "alu_frac": ach / VALU_PEAK_TOPS,
+                  "alu_ops_per_coeff_mac": ops_per_mac, "fold_interval": fold_f,
+                  "alu_achieved_TOPs": ach_ops, "alu_peak_TOPs": VALU_PEAK_TOPS, "alu_frac": ach_ops / VALU_PEAK_TOPS,
                   "hbm_achieved_GBs": mac_gbs, "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": mac_gbs / HBM_PEAK_GBS}
         if t_hbm >= t_alu:
             out["roofline"] = {"bound": "hbm", "achieved": mac_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": mac_gbs / HBM_PEAK_GBS, **common}
         else:
-            out["roofline"] = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
-                               "unit": "TOP/s (one v_mad_u64_u32 per coeff-MAC)", "frac": ach / VALU_PEAK_TOPS,
-                               **common}
+            out["roofline"] = {"bound": "alu", "achieved": ach_ops, "peak": VALU_PEAK_TOPS,
+                               "unit": "T VALU instructions/s (1 + 2/F per coeff-MAC)",
+                               "frac": ach_ops / VALU_PEAK_TOPS, **common}
         ntt_bytes = sum(o.in_words * 4 * 2 for o in layers) * n_img
         intt_bytes = sum(o.out_words * 4 * 2 for o in layers) * n_img
 
