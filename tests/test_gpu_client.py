@@ -125,7 +125,8 @@ def test_encrypt_device_matches_host_at_scale(dev, N, L, bits, n):
         assert np.array_equal(got, orc.encrypt(ctx.primes, 20, sk, msg, 4242 + n))
 
 
-@pytest.mark.parametrize("N,L,bits,n", [(1024, 2, 31, 4), (8192, 3, 31, 3), (4096, 2, 30, 5)])
+@pytest.mark.parametrize("N,L,bits,n", [(1024, 2, 31, 4), (8192, 3, 31, 3), (4096, 2, 30, 5), (2048, 1, 31, 3),
+                                        (16384, 4, 31, 2), (8192, 5, 30, 2)])
 def test_decrypt_device_matches_host_on_arbitrary_residues(dev, N, L, bits, n):
     """Uniform residues put the rounded fraction everywhere in [0, 1); the
     device must take every rounding decision the host takes."""
@@ -161,6 +162,30 @@ def test_decrypt_device_matches_host_on_arbitrary_residues(dev, N, L, bits, n):
                 assert got[m, j] == want[m, j], (m, j)
                 outside += 1
     assert outside >= n * N - 4
+
+
+def test_decrypt_device_many_ciphertexts(dev):
+    """300 ciphertexts of arbitrary residues at n = 4096: the device
+    decryption equals the host library's on every coefficient, and so does
+    the allocation-free entry point in two calls of 128 and 172."""
+    import torch
+    N, L, n = 4096, 2, 300
+    say(f"decrypt_device N={N} L={L} n={n}")
+    ctx = ctx_for(N, L, 31)
+    rng = np.random.default_rng(17)
+    ct = np.empty((n, 2, L, N), dtype=np.uint32)
+    for i, q in enumerate(ctx.primes):
+        ct[:, :, i, :] = rng.integers(0, q, size=(n, 2, N))
+    sk = hy.hyena_keygen(ctx, 5)
+    d_s_hat = prepared(ctx, sk)
+    d_ct = torch.from_numpy(ct.view(np.int32)).cuda().reshape(-1)
+    got = decrypt_dev(ctx, d_s_hat, d_ct)
+    assert np.array_equal(got, hy.hyena_decrypt(ctx, sk, ct))
+    for lo, hi in ((0, 128), (128, 300)):   # within the scratch size (n L N <= 2^22)
+        d_msg = torch.full((hi - lo, N), 7, dtype=torch.int32, device="cuda")
+        hy.hyena_decrypt_device_noalloc(ctx, d_s_hat, d_ct[lo * 2 * L * N:hi * 2 * L * N], d_msg)
+        torch.cuda.synchronize()
+        assert np.array_equal(d_msg.cpu().numpy(), got[lo:hi])
 
 
 def test_decrypt_device_of_convolution_output(dev):
