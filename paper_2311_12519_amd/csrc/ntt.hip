@@ -707,7 +707,7 @@ struct NttSched {
 };
 const NttSched kNtt[] = {
     {10, 6, 4, 3, 3, 0, 0},
-    {11, 7, 4, 4, 3, 0, 0},
+    {11, 7, 4, 4, 3, 0, 0}, {11, 6, 5, 3, 3, 0, 0}, {11, 6, 5, 5, 1, 0, 0},
     {12, 8, 4, 4, 4, 0, 0}, {12, 7, 5, 5, 2, 0, 0}, {12, 6, 6, 3, 3, 0, 0},
     {12, 8, 4, 4, 4, 0, 1}, {12, 7, 5, 5, 2, 0, 1}, {12, 8, 4, 4, 4, 0, 2}, {12, 7, 5, 5, 2, 0, 2},
     {13, 8, 5, 4, 4, 0, 0}, {13, 9, 4, 4, 4, 1, 0}, {13, 7, 6, 6, 1, 0, 0},
@@ -721,27 +721,29 @@ hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hip
     switch (i) {
         case 0: return launch_sched<10, 6, 4, 3, 3, 0>(d, c, inv, s);
         case 1: return launch_sched<11, 7, 4, 4, 3, 0>(d, c, inv, s);
-        case 2: return launch_sched<12, 8, 4, 4, 4, 0>(d, c, inv, s);
-        case 3: return launch_sched<12, 7, 5, 5, 2, 0>(d, c, inv, s);
-        case 4: return launch_sched<12, 6, 6, 3, 3, 0>(d, c, inv, s);
-        case 5: return launch_persist<12, 8, 4, 4, 4, 0>(d, c, inv, s);
-        case 6: return launch_persist<12, 7, 5, 5, 2, 0>(d, c, inv, s);
-        case 7: return launch_stream<12, 8, 4, 4, 4, 0>(d, c, inv, s);
-        case 8: return launch_stream<12, 7, 5, 5, 2, 0>(d, c, inv, s);
-        case 9: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 10: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 11: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
-        case 12: return launch_persist<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 13: return launch_persist<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 14: return launch_stream<13, 8, 5, 4, 4, 0>(d, c, inv, s);
-        case 15: return launch_stream<13, 9, 4, 4, 4, 1>(d, c, inv, s);
-        case 16: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 17: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
-        case 18: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
-        case 19: return launch_persist<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 20: return launch_persist<14, 10, 4, 4, 4, 2>(d, c, inv, s);
-        case 21: return launch_stream<14, 9, 5, 5, 4, 0>(d, c, inv, s);
-        case 22: return launch_stream<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 2: return launch_sched<11, 6, 5, 3, 3, 0>(d, c, inv, s);
+        case 3: return launch_sched<11, 6, 5, 5, 1, 0>(d, c, inv, s);
+        case 4: return launch_sched<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 5: return launch_sched<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 6: return launch_sched<12, 6, 6, 3, 3, 0>(d, c, inv, s);
+        case 7: return launch_persist<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 8: return launch_persist<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 9: return launch_stream<12, 8, 4, 4, 4, 0>(d, c, inv, s);
+        case 10: return launch_stream<12, 7, 5, 5, 2, 0>(d, c, inv, s);
+        case 11: return launch_sched<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 12: return launch_sched<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 13: return launch_sched<13, 7, 6, 6, 1, 0>(d, c, inv, s);
+        case 14: return launch_persist<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 15: return launch_persist<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 16: return launch_stream<13, 8, 5, 4, 4, 0>(d, c, inv, s);
+        case 17: return launch_stream<13, 9, 4, 4, 4, 1>(d, c, inv, s);
+        case 18: return launch_sched<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 19: return launch_sched<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 20: return launch_sched<14, 8, 6, 6, 2, 0>(d, c, inv, s);
+        case 21: return launch_persist<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 22: return launch_persist<14, 10, 4, 4, 4, 2>(d, c, inv, s);
+        case 23: return launch_stream<14, 9, 5, 5, 4, 0>(d, c, inv, s);
+        case 24: return launch_stream<14, 10, 4, 4, 4, 2>(d, c, inv, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -751,10 +753,10 @@ hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hip
 int ntt_default_schedule(uint32_t logN) {
     switch (logN) {
         case 10: return 0;
-        case 11: return 1;
-        case 12: return 2;
-        case 13: return 9;
-        case 14: return 17;
+        case 11: return 3;   // one wave per limb-polynomial: no workgroup barrier
+        case 12: return 4;
+        case 13: return 11;
+        case 14: return 19;
         default: return -1;
     }
 }

@@ -378,7 +378,8 @@ def test_every_mac_schedule_matches_oracle(dev, lay, c_n, batch):
     assert ran >= (4 if lay.depthwise else len(streamed))
 
 
-@pytest.mark.parametrize("N,L,bits", [(4096, 2, 30), (8192, 3, 31), (8192, 2, 30), (16384, 2, 31)])
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 30), (2048, 1, 31), (4096, 2, 30), (8192, 3, 31), (8192, 2, 30),
+                                      (16384, 2, 31)])
 def test_every_ntt_schedule_matches_oracle(dev, N, L, bits):
     ctx = ctx_for(N, L, bits)
     rng = np.random.default_rng(N + bits)
@@ -394,7 +395,7 @@ def test_every_ntt_schedule_matches_oracle(dev, N, L, bits):
         assert np.array_equal(from_dev(d), a), sid
 
 
-@pytest.mark.parametrize("N,L,bits", [(8192, 3, 31), (4096, 2, 30), (16384, 2, 31)])
+@pytest.mark.parametrize("N,L,bits", [(8192, 3, 31), (4096, 2, 30), (16384, 2, 31), (2048, 2, 31)])
 def test_ntt_schedules_many_polys(dev, N, L, bits):
     """Every schedule on more limb-polynomials than a persistent grid holds
     (so persistent blocks loop and prefetch), against the default schedule
