@@ -350,8 +350,8 @@ __global__ void __launch_bounds__(STH) keyswitch_keys_kernel(const uint32_t *wor
 // rotation are read once per KS_R ciphertexts. The permutation maps the
 // wave's aligned block of 64 source slots onto one aligned block of output
 // slots, so keys are loaded and sums stored in slot order (lane j at slot
-// block + j, 256 contiguous bytes per access) and permuted across the wave's
-// lanes in registers.
+// block + j, 256 contiguous bytes per access) and moved between the wave's
+// lanes by ds_bpermute (a cross-lane read that takes no LDS space).
 constexpr uint32_t KS_R = 8;
 
 struct RotInv {
