@@ -753,7 +753,7 @@ hipError_t launch_idx(int i, const NttSegs &d, const hyena_ctx *c, bool inv, hip
 int ntt_default_schedule(uint32_t logN) {
     switch (logN) {
         case 10: return 0;
-        case 11: return 3;   // one wave per limb-polynomial: no workgroup barrier
+        case 11: return 1;
         case 12: return 4;
         case 13: return 11;
         case 14: return 19;
