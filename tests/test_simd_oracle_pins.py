@@ -104,6 +104,34 @@ def test_slot_layout_under_galois_maps():
     assert np.array_equal(sw[:h], v[h:]) and np.array_equal(sw[h:], v[:h])
 
 
+def test_galois_map_permutes_ntt_slots_in_aligned_blocks():
+    """In the NTT domain (slot s evaluates at psi^(2 brv(s) + 1)), X -> X^g is
+    the slot permutation s <- src(s) with 2 brv(src(s)) + 1 = (2 brv(s) + 1) g
+    mod 2N, checked against the oracle's transform of the automorphism; the
+    inverse map uses g^-1 mod 2N; and every aligned block of 64 slots is
+    carried onto one aligned block (what lets a wave's key-switch loads and
+    stores stay in slot order)."""
+    N, q = 1024, orc.ntt_primes(1024, 1, 30)[0]
+    psi = orc.find_psi(q, N)
+    logn = N.bit_length() - 1
+    rng = np.random.default_rng(12)
+    a = rng.integers(0, q, N).astype(np.uint32)
+    A = orc.ntt(a, q, psi)
+
+    def src(s, g):
+        e = ((2 * orc.bitrev(s, logn) + 1) * g) % (2 * N)
+        return orc.bitrev(e >> 1, logn)
+
+    for g in (3, 5, 25, 2 * N - 1, 2 * N - 3, pow(3, 37, 2 * N)):
+        Ag = orc.ntt(simd.automorphism(a, g, q), q, psi)
+        perm = [src(s, g) for s in range(N)]
+        assert np.array_equal(Ag, A[perm]), g
+        gi = pow(g, -1, 2 * N)
+        assert [src(perm[s], gi) for s in range(N)] == list(range(N)), g
+        for b in range(0, N, 64):
+            assert len({perm[s] // 64 for s in range(b, b + 64)}) == 1, (g, b)
+
+
 def test_automorphism_brute_force_and_group_laws():
     """a(X^g) by substitution and reduction of the full polynomial for tiny n;
     monomials map to signed monomials; sigma_g2 o sigma_g1 = sigma_{g1 g2}."""
