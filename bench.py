@@ -121,6 +121,8 @@ def parse():
                     help="skip the supplementary run of the SIMD-setting kernels (HRot, batch encoding, PMult)")
     ap.add_argument("--no-synth", action="store_true",
                     help="skip the supplementary run of the evaluation-domain weight synthesis")
+    ap.add_argument("--no-walsh-vgg", action="store_true",
+                    help="skip the supplementary VGG-16 step with Walsh-Hadamard packing (c_n = 2)")
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the supplementary run of the ImageNet ResNet layers with Walsh-Hadamard packing")
     ap.add_argument("--no-costmodel", action="store_true",
@@ -540,6 +542,8 @@ def main():
         out["kernels"]["wht"] = wht_bandwidth(ctx, layers, hy, torch)
     if not args.no_client:   # before alt_primes, which releases this run's buffers
         out["client"] = client_side(args, ctx, layers, hy, torch, head["ms_per_step"], n_layer_runs)
+    if head_mode == "tuned" and not args.no_walsh_vgg:
+        out["walsh_vgg"] = walsh_vgg(args, ctx, layers, hy, torch, batch, head["ms_per_step"], total_macs)
     layers_host = [Layer() for _ in layers]   # what the random part of the baseline needs
     for h, o in zip(layers_host, layers):
         h.lay, h.w = o.lay, o.w
@@ -573,6 +577,63 @@ def main():
     else:
         log("no oracle run: outputs not checked (--no-cpu-baseline)")
     print(json.dumps(out))
+
+
+def walsh_vgg(args, ctx, layers, hy, torch, batch1, step_ms, total_macs):
+    """Supplementary figure: the headline step with Walsh-Hadamard output
+    packing over pairs of output channels (c_n = 2: Walsh kernels
+    c_n^-1 (K_2G + K_2G+1) and c_n^-1 (K_2G - K_2G+1), butterflies fused into
+    the MAC epilogue), tuned like the headline. The butterflies recombine the
+    pair, so every output coefficient equals the c_n = 1 step's: one step of
+    each from the same inputs is compared on all outputs (the c_n = 1 outputs
+    are the ones the oracle checks)."""
+    log("supplementary run: VGG-16 step with Walsh-Hadamard packing, c_n = 2 ...")
+    n_img = args.images
+    items = []
+    for o in layers:
+        lay = o.lay
+        d2 = hy.hyena_conv_plan(ctx, lay.H, lay.W, lay.Ci, lay.Co, lay.k, c_n=2, flags=hy.HYENA_FUSE_WHT,
+                                batch=n_img)
+        d1 = o.desc_b
+        if (d2.n_in, d2.n_groups, d2.ci, d2.tiles) != (d1.n_in, d1.n_groups, d1.ci, d1.tiles):
+            raise SystemExit(f"c_n = 2 plan of {lay.name} packs its inputs differently")
+        wn2 = torch.empty(hy.wntt_words(ctx, d2), dtype=torch.int32, device="cuda")
+        hy.hyena_encode_weights(ctx, d2, o.d_w, wn2)
+        items.append((d2, wn2, torch.empty_like(o.out)))
+    flags = hy.HYENA_BATCH_TUNE | hy.HYENA_BATCH_PERSISTENT | hy.HYENA_BATCH_GRAPH | hy.HYENA_BATCH_TIMING
+    batch2 = hy.hyena_batch_create(ctx, [(d2, o.ct, wn2, out2) for o, (d2, wn2, out2) in zip(layers, items)],
+                                   flags)
+    for b in (batch1, batch2):
+        for o in layers:
+            o.ct.copy_(o.ct0)
+        hy.hyena_batch_run(b)
+        torch.cuda.synchronize()
+    for o, (_, _, out2) in zip(layers, items):
+        if not torch.equal(o.out, out2):
+            raise SystemExit(f"c_n = 2 outputs of {o.lay.name} differ from the c_n = 1 outputs")
+    for _ in range(args.warmup):
+        hy.hyena_batch_run(batch2)
+    torch.cuda.synchronize()
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hy.hyena_batch_run(batch2)
+        phases.append(hy.hyena_batch_phase_ms(batch2))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ph = np.array(phases).mean(axis=0)
+    res = {"workload": f"VGG-16 {len(layers)} conv layers at 224x224, {n_img} images, N=8192, c_n=2 "
+                       "(output-channel pairs, fused butterflies)",
+           "c_n": 2, "ms_per_step": dt * 1e3, "coeff_macs_per_s": total_macs / dt,
+           "over_c_n_1": dt * 1e3 / step_ms,
+           "kernels_ms": {"ntt": float(ph[0]), "mac": float(ph[1]), "intt": float(ph[2])},
+           "outputs_equal_to_c_n_1": True, "compared_output_words": sum(int(o.out.numel()) for o in layers),
+           "schedules": hy.hyena_batch_info(batch2)}
+    hy.hyena_batch_destroy(batch2)
+    del items
+    torch.cuda.empty_cache()
+    log(f"c_n = 2: {dt * 1e3:.2f} ms/step ({res['over_c_n_1']:.3f} of c_n = 1), outputs equal")
+    return res
 
 
 def weight_synthesis(ctx, layers, hy, torch):
