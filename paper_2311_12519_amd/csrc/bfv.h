@@ -22,22 +22,17 @@ std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c);   // floor(q / t) 
 void bfv_error_thresholds(uint64_t *t64);                        // the 2B sampler thresholds
 void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B);   // decryption, per limb
 
-// Forward NTT of P polynomials with a gathered source and a pointwise product:
-// dst[p][i] = NTT_i(src[p][i]) . mul[i] mod q_i, src[p][i] at
-// src + p src_stride + i N, dst contiguous [P][L][N], mul [L][N] holding
-// m 2^32 mod q_i (Montgomery form). src may equal dst with src_stride = L N;
-// otherwise they must not overlap. dst and mul 16-byte aligned (ntt.hip).
-int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
-                       const uint32_t *mul, hipStream_t s);
-
-// Inverse NTT of P polynomials a [P][L][N] in place, adding as it stores
-// limb i of polynomial p at add_src + p add_stride + i N (mod q_i; canonical
-// inputs); add_src must not overlap a; a 16-byte aligned (ntt.hip).
-int launch_ntt_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+// Decryption's v = c0 + c1 s for n ciphertexts ct [n][2][L][N] into
+// v [n][L][N] in one kernel: per limb-polynomial the forward transform of c1,
+// the product with mul [L][N] (NTT(s) 2^32 mod q_i), the inverse transform
+// and the sum with c0. mul 16-byte aligned; v must not overlap ct (ntt.hip).
+int launch_ntt_c1s_add(const hyena_ctx *c, const uint32_t *ct, size_t n, uint32_t *v, const uint32_t *mul,
                        hipStream_t s);
 
-// Encryption's uniform polynomials drawn inside the forward NTT: for message m
+// Encryption's uniform polynomials drawn inside the transform: for message m
 // and limb i, a = floor(q_i sm64(seed, 2 ((m L + i) N + j)) / 2^64); writes
-// c1 = -a into ct [n][2][L][N] and NTT(a) . mul into dst [n][L][N] (ntt.hip).
-int launch_ntt_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
-                          uint64_t seed, hipStream_t s);
+// c1 = -a into ct [n][2][L][N] and a s mod q_i = INTT(NTT(a) . NTT(s)) into
+// dst [n][L][N], with mul [L][N] holding NTT(s) 2^32 mod q_i, in one kernel
+// (ntt.hip).
+int launch_ntt_sample_as(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+                         uint64_t seed, hipStream_t s);

@@ -247,10 +247,8 @@ extern "C" int hyena_encrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     bfv_error_thresholds(th.t);
     for (int k = 0; k + 1 < 2 * kErrBound; k++)   // the kernel's binary search relies on it
         if (th.t[k] > th.t[k + 1]) return set_error(HYENA_EINVAL, std::string(who) + ": sampler table not monotone");
-    // a drawn inside the forward transform, which writes c1 = -a and NTT(a) . NTT(s) into the workspace;
-    // a s = INTT of that
-    if (int rc = launch_ntt_fwd_sample(c, d_ct, n, d_work, d_s_hat, seed, s)) return rc;
-    if (int rc = launch_ntt(c, d_work, n, true, s)) return rc;
+    // a drawn inside the transform, which writes c1 = -a and a s into the workspace
+    if (int rc = launch_ntt_sample_as(c, d_ct, n, d_work, d_s_hat, seed, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
     hipLaunchKernelGGL(encrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_ct, d_work, d_msg, n,
                        c->logN, L, seed, c->lt, cc, th);
@@ -275,11 +273,8 @@ extern "C" int hyena_decrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
         return set_error(HYENA_EINVAL, std::string(who) + ": d_work or d_msg overlaps another array");
     const hipStream_t s = (hipStream_t)stream;
     const ClientConst cc = client_constants(c);
-    // c1 s = INTT(NTT(c1) . NTT(s)): the forward transform reads c1 of every ciphertext in place
-    // and writes the product into the workspace
-    if (int rc = launch_ntt_fwd_mul(c, d_ct + LN, 2 * LN, n, d_work, d_s_hat, s)) return rc;
-    // v = c0 + c1 s: the inverse transform adds c0 as it stores
-    if (int rc = launch_ntt_inv_add(c, d_work, n, d_ct, 2 * LN, s)) return rc;
+    // v = c0 + INTT(NTT(c1) . NTT(s)) into the workspace, one kernel per limb-polynomial
+    if (int rc = launch_ntt_c1s_add(c, d_ct, n, d_work, d_s_hat, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
     hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_work, d_msg, n, c->logN,
                        L, c->log2_t, c->lt, cc);

@@ -419,63 +419,26 @@ ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32
     else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lt.c[limb].qinv_neg, lds);
 }
 
-// Forward transform with a gathered source and a pointwise product on the
-// store, for the client operations: block p (limb-polynomial p of a [P][L][N]
-// result) reads limb p mod L of polynomial p / L at src + (p / L) src_stride,
-// transforms it as ntt_kernel does and stores NTT(a) . m mod q, with mul
-// holding m 2^32 mod q in [L][N] (Montgomery form). src may equal dst (the
-// whole polynomial is in registers before the first store).
-template <int LOGT, int E_LOG, int EP>
-__device__ __forceinline__ void store_runs_mul(const uint32_t (&x)[1 << E_LOG], uint32_t *__restrict__ a,
-                                               const uint32_t *__restrict__ mul, uint32_t q, uint32_t qn,
-                                               uint32_t tid) {
-    constexpr int GE = 1 << EP, NG = (1 << E_LOG) >> EP;
-    static_assert(GE >= 4, "runs of at least four residues");
-#pragma unroll
-    for (int kg = 0; kg < NG; kg++) {
-        const size_t base = (size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EP;
-#pragma unroll
-        for (int r = 0; r < GE; r += 4) {
-            const uint4 m = *reinterpret_cast<const uint4 *>(mul + base + r);
-            *reinterpret_cast<uint4 *>(a + base + r) = make_uint4(
-                csub(mont_mul(x[kg * GE + r], m.x, q, qn), q), csub(mont_mul(x[kg * GE + r + 1], m.y, q, qn), q),
-                csub(mont_mul(x[kg * GE + r + 2], m.z, q, qn), q), csub(mont_mul(x[kg * GE + r + 3], m.w, q, qn), q));
-        }
-    }
-}
-
+// Encryption's a s, with a drawn in the load: block p (limb p mod L of
+// message p / L) takes a_j = floor(q sm64(seed, 2 (p N + j)) / 2^64), writes
+// c1 = -a of that ciphertext ([n][2][L][N]), transforms a, multiplies by
+// NTT(s) (mul [L][N], Montgomery form) in the runs layout the forward
+// transform ends in and the inverse starts from, transforms back and stores
+// a s mod q into dst [n][L][N]; the product never leaves the chip.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
 __global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
-ntt_fwd_mul_kernel(const uint32_t *src, size_t src_stride, uint32_t *dst, const uint32_t *__restrict__ mul,
-                   const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
-    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << (LOGN - LOGT);
-    __shared__ uint32_t lds[N + N / 32];
-    const uint32_t p = blockIdx.x, limb = p % L, poly = p / L;
-    const uint32_t *a = src + (size_t)poly * src_stride + (size_t)limb * N;
-    const uint32_t *tw = tw_all + (size_t)limb * N;
-    const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg, tid = threadIdx.x;
-    uint32_t x[E];
-#pragma unroll
-    for (int r = 0; r < E; r++) x[r] = a[tid + r * T];
-    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
-    store_runs_mul<LOGT, LOGN - LOGT, (E3 > 0 ? E3 : E2)>(x, dst + (size_t)p * N, mul + (size_t)limb * N, q, qn, tid);
-}
-
-// Forward transform of the encryption's uniform polynomials, drawn in the
-// load: block p (limb p mod L of message p / L) takes
-// a_j = floor(q sm64(seed, 2 (p N + j)) / 2^64), writes c1 = -a of that
-// ciphertext ([n][2][L][N]) and stores NTT(a) . mul into dst [n][L][N].
-template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
-__global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
-ntt_fwd_sample_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ mul, uint64_t seed,
-                      const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
-    constexpr int N = 1 << LOGN, T = 1 << LOGT, E = 1 << (LOGN - LOGT);
+ntt_sample_as_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ mul, uint64_t seed,
+                     const uint32_t *__restrict__ fw_all, const uint32_t *__restrict__ iw_all, LimbTable lt,
+                     uint32_t L) {
+    constexpr int N = 1 << LOGN, T = 1 << LOGT, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
+    constexpr int EF = E3 > 0 ? E3 : E2, GE = 1 << EF, NG = E >> EF;
+    static_assert(GE >= 4, "16-byte loads of NTT(s) in the runs layout");
     __shared__ uint32_t lds[N + N / 32];
     const uint32_t p = blockIdx.x, limb = p % L, m = p / L, tid = threadIdx.x;
     const size_t LN = (size_t)L * N;
     uint32_t *c1 = ct + (size_t)m * 2 * LN + LN + (size_t)limb * N;
-    const uint32_t *tw = tw_all + (size_t)limb * N;
-    const uint32_t q = lt.c[limb].q, qn = lt.c[limb].qinv_neg;
+    const LimbConst lc = lt.c[limb];
+    const uint32_t q = lc.q, qn = lc.qinv_neg;
     uint32_t x[E];
 #pragma unroll
     for (int r = 0; r < E; r++) {
@@ -484,69 +447,94 @@ ntt_fwd_sample_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ 
         x[r] = a;
         c1[j] = a ? q - a : 0;
     }
-    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, q, qn, lds, tid);
-    store_runs_mul<LOGT, LOGN - LOGT, (E3 > 0 ? E3 : E2)>(x, dst + (size_t)p * N, mul + (size_t)limb * N, q, qn, tid);
+    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, fw_all + (size_t)limb * N, q, qn, lds, tid);
+    const uint32_t *sh = mul + (size_t)limb * N;
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++)
+#pragma unroll
+        for (int j = 0; j < GE; j += 4) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(sh + ((tid + (uint32_t)kg * T) << EF) + j);
+            uint32_t *xv = &x[kg * GE + j];
+            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
+            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
+            xv[2] = csub(mont_mul(xv[2], u.z, q, qn), q);
+            xv[3] = csub(mont_mul(xv[3], u.w, q, qn), q);
+        }
+    __syncthreads();   // every wave's reads of the forward exchanges are done
+    const uint32_t *iw = iw_all + (size_t)limb * N;
+    inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, iw, lc, lds, tid);
+    inv_back<LOGN, LOGT, E0, LAZY>(x, dst + (size_t)p * N, iw, lc, tid);
 }
 
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
-hipError_t launch_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
-                             uint64_t seed, hipStream_t s) {
+hipError_t launch_sample_as(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+                            uint64_t seed, hipStream_t s) {
     const dim3 grid((unsigned)(n * c->L)), block(1u << LOGT);
     if (c->lazy_ntt)
-        hipLaunchKernelGGL((ntt_fwd_sample_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, ct, dst, mul,
-                           seed, c->d_fw, c->lt, c->L);
+        hipLaunchKernelGGL((ntt_sample_as_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, ct, dst, mul,
+                           seed, c->d_fw, c->d_iw, c->lt, c->L);
     else
-        hipLaunchKernelGGL((ntt_fwd_sample_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, ct, dst, mul,
-                           seed, c->d_fw, c->lt, c->L);
+        hipLaunchKernelGGL((ntt_sample_as_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, ct, dst,
+                           mul, seed, c->d_fw, c->d_iw, c->lt, c->L);
     return hipGetLastError();
 }
 
-template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
-hipError_t launch_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
-                          const uint32_t *mul, hipStream_t s) {
-    const dim3 grid((unsigned)(P * c->L)), block(1u << LOGT);
-    if (c->lazy_ntt)
-        hipLaunchKernelGGL((ntt_fwd_mul_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, src, src_stride,
-                           dst, mul, c->d_fw, c->lt, c->L);
-    else
-        hipLaunchKernelGGL((ntt_fwd_mul_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, src,
-                           src_stride, dst, mul, c->d_fw, c->lt, c->L);
-    return hipGetLastError();
-}
 
-// Inverse transform that adds another array as it stores: block p (limb-
-// polynomial p of a [P][L][N] array a) stores INTT(a_p) + add mod q, with add
-// limb p mod L of polynomial p / L at add_src + (p / L) add_stride (decryption
-// adds c0 to c1 s this way). add_src must not overlap a.
+// Decryption's c0 + c1 s in one pass over each limb-polynomial: block p
+// (limb p mod L of ciphertext p / L of ct [n][2][L][N]) transforms c1 (the
+// forward passes), multiplies by NTT(s) (mul [L][N], Montgomery form) in the
+// runs layout the forward transform ends in and the inverse starts from,
+// transforms back and stores INTT(NTT(c1) . NTT(s)) + c0 mod q into
+// v [n][L][N]; the product never leaves the chip.
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3, bool LAZY>
 __global__ void __launch_bounds__(1 << LOGT) __attribute__((amdgpu_waves_per_eu(1, ntt_waves_per_simd(LOGN, LOGT))))
-ntt_inv_add_kernel(uint32_t *a_all, const uint32_t *__restrict__ add_src, size_t add_stride,
-                   const uint32_t *__restrict__ tw_all, LimbTable lt, uint32_t L) {
+ntt_c1s_add_kernel(const uint32_t *__restrict__ ct, uint32_t *__restrict__ v, const uint32_t *__restrict__ mul,
+                   const uint32_t *__restrict__ fw_all, const uint32_t *__restrict__ iw_all, LimbTable lt,
+                   uint32_t L) {
     constexpr int N = 1 << LOGN, T = 1 << LOGT, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
+    constexpr int EF = E3 > 0 ? E3 : E2, GE = 1 << EF, NG = E >> EF;
+    static_assert(GE >= 4, "16-byte loads of NTT(s) in the runs layout");
     __shared__ uint32_t lds[N + N / 32];
-    const uint32_t p = blockIdx.x, limb = p % L, poly = p / L, tid = threadIdx.x;
-    uint32_t *a = a_all + (size_t)p * N;
-    const uint32_t *ad = add_src + (size_t)poly * add_stride + (size_t)limb * N;
-    const uint32_t *tw = tw_all + (size_t)limb * N;
+    const uint32_t p = blockIdx.x, limb = p % L, m = p / L, tid = threadIdx.x;
+    const size_t LN = (size_t)L * N;
+    const uint32_t *c0 = ct + (size_t)m * 2 * LN + (size_t)limb * N, *c1 = c0 + LN;
     const LimbConst lc = lt.c[limb];
+    const uint32_t q = lc.q, qn = lc.qinv_neg;
     uint32_t x[E];
-    load_runs<LOGT, E_LOG, (E3 > 0 ? E3 : E2)>(x, a, tid);
-    inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, tw, lc, lds, tid);
-    inv_pass<LOGN, LOGT, E_LOG, 0, E0, true, LAZY>(x, tw, lc, tid);
 #pragma unroll
-    for (int r = 0; r < E; r++) a[tid + r * T] = csub(x[r] + ad[tid + r * T], lc.q);
+    for (int r = 0; r < E; r++) x[r] = c1[tid + r * T];
+    fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, fw_all + (size_t)limb * N, q, qn, lds, tid);
+    const uint32_t *sh = mul + (size_t)limb * N;
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++)
+#pragma unroll
+        for (int j = 0; j < GE; j += 4) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(sh + ((tid + (uint32_t)kg * T) << EF) + j);
+            uint32_t *xv = &x[kg * GE + j];
+            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
+            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
+            xv[2] = csub(mont_mul(xv[2], u.z, q, qn), q);
+            xv[3] = csub(mont_mul(xv[3], u.w, q, qn), q);
+        }
+    __syncthreads();   // every wave's reads of the forward exchanges are done
+    const uint32_t *iw = iw_all + (size_t)limb * N;
+    inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, iw, lc, lds, tid);
+    inv_pass<LOGN, LOGT, E_LOG, 0, E0, true, LAZY>(x, iw, lc, tid);
+    uint32_t *o = v + (size_t)p * N;
+#pragma unroll
+    for (int r = 0; r < E; r++) o[tid + r * T] = csub(x[r] + c0[tid + r * T], q);
 }
 
 template <int LOGN, int LOGT, int E0, int E1, int E2, int E3>
-hipError_t launch_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+hipError_t launch_c1s_add(const hyena_ctx *c, const uint32_t *ct, size_t n, uint32_t *v, const uint32_t *mul,
                           hipStream_t s) {
-    const dim3 grid((unsigned)(P * c->L)), block(1u << LOGT);
+    const dim3 grid((unsigned)(n * c->L)), block(1u << LOGT);
     if (c->lazy_ntt)
-        hipLaunchKernelGGL((ntt_inv_add_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, a, add_src,
-                           add_stride, c->d_iw, c->lt, c->L);
+        hipLaunchKernelGGL((ntt_c1s_add_kernel<LOGN, LOGT, E0, E1, E2, E3, true>), grid, block, 0, s, ct, v, mul,
+                           c->d_fw, c->d_iw, c->lt, c->L);
     else
-        hipLaunchKernelGGL((ntt_inv_add_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, a, add_src,
-                           add_stride, c->d_iw, c->lt, c->L);
+        hipLaunchKernelGGL((ntt_c1s_add_kernel<LOGN, LOGT, E0, E1, E2, E3, false>), grid, block, 0, s, ct, v, mul,
+                           c->d_fw, c->d_iw, c->lt, c->L);
     return hipGetLastError();
 }
 
@@ -805,27 +793,7 @@ int launch_ntt(const hyena_ctx *c, uint32_t *d, size_t P, bool inv, hipStream_t 
     return launch_ntt_sched(c, d, P, inv, -1, s);
 }
 
-int launch_ntt_fwd_mul(const hyena_ctx *c, const uint32_t *src, size_t src_stride, size_t P, uint32_t *dst,
-                       const uint32_t *mul, hipStream_t s) {
-    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
-    if (P == 0) return HYENA_OK;
-    if (P * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
-    if (((uintptr_t)dst | (uintptr_t)mul) & 15u)
-        return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
-    hipError_t e;
-    switch (c->logN) {   // the default schedule of each N (one block per limb-polynomial)
-        case 10: e = launch_fwd_mul<10, 6, 4, 3, 3, 0>(c, src, src_stride, P, dst, mul, s); break;
-        case 11: e = launch_fwd_mul<11, 7, 4, 4, 3, 0>(c, src, src_stride, P, dst, mul, s); break;
-        case 12: e = launch_fwd_mul<12, 8, 4, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
-        case 13: e = launch_fwd_mul<13, 8, 5, 4, 4, 0>(c, src, src_stride, P, dst, mul, s); break;
-        case 14: e = launch_fwd_mul<14, 10, 4, 4, 4, 2>(c, src, src_stride, P, dst, mul, s); break;
-        default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
-    }
-    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
-    return HYENA_OK;
-}
-
-int launch_ntt_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
+int launch_ntt_sample_as(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *dst, const uint32_t *mul,
                           uint64_t seed, hipStream_t s) {
     if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
     if (n == 0) return HYENA_OK;
@@ -834,33 +802,33 @@ int launch_ntt_fwd_sample(const hyena_ctx *c, uint32_t *ct, size_t n, uint32_t *
         return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
     hipError_t e;
     switch (c->logN) {
-        case 10: e = launch_fwd_sample<10, 6, 4, 3, 3, 0>(c, ct, n, dst, mul, seed, s); break;
-        case 11: e = launch_fwd_sample<11, 7, 4, 4, 3, 0>(c, ct, n, dst, mul, seed, s); break;
-        case 12: e = launch_fwd_sample<12, 8, 4, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
-        case 13: e = launch_fwd_sample<13, 8, 5, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
-        case 14: e = launch_fwd_sample<14, 10, 4, 4, 4, 2>(c, ct, n, dst, mul, seed, s); break;
+        case 10: e = launch_sample_as<10, 6, 4, 3, 3, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 11: e = launch_sample_as<11, 7, 4, 4, 3, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 12: e = launch_sample_as<12, 8, 4, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 13: e = launch_sample_as<13, 8, 5, 4, 4, 0>(c, ct, n, dst, mul, seed, s); break;
+        case 14: e = launch_sample_as<14, 10, 4, 4, 4, 2>(c, ct, n, dst, mul, seed, s); break;
         default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
     }
     if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
     return HYENA_OK;
 }
 
-int launch_ntt_inv_add(const hyena_ctx *c, uint32_t *a, size_t P, const uint32_t *add_src, size_t add_stride,
+int launch_ntt_c1s_add(const hyena_ctx *c, const uint32_t *ct, size_t n, uint32_t *v, const uint32_t *mul,
                        hipStream_t s) {
-    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_intt: context was created host-only");
-    if (P == 0) return HYENA_OK;
-    if (P * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_intt: too many polynomials");
-    if ((uintptr_t)a & 15u) return set_error(HYENA_EINVAL, "hyena_intt: polynomial array is not 16-byte aligned");
+    if (!c->d_fw) return set_error(HYENA_EINVAL, "hyena_ntt: context was created host-only");
+    if (n == 0) return HYENA_OK;
+    if (n * c->L > 0x7fffffffull) return set_error(HYENA_EINVAL, "hyena_ntt: too many polynomials");
+    if ((uintptr_t)mul & 15u) return set_error(HYENA_EINVAL, "hyena_ntt: polynomial array is not 16-byte aligned");
     hipError_t e;
     switch (c->logN) {   // the default schedule of each N (one block per limb-polynomial)
-        case 10: e = launch_inv_add<10, 6, 4, 3, 3, 0>(c, a, P, add_src, add_stride, s); break;
-        case 11: e = launch_inv_add<11, 7, 4, 4, 3, 0>(c, a, P, add_src, add_stride, s); break;
-        case 12: e = launch_inv_add<12, 8, 4, 4, 4, 0>(c, a, P, add_src, add_stride, s); break;
-        case 13: e = launch_inv_add<13, 8, 5, 4, 4, 0>(c, a, P, add_src, add_stride, s); break;
-        case 14: e = launch_inv_add<14, 10, 4, 4, 4, 2>(c, a, P, add_src, add_stride, s); break;
-        default: return set_error(HYENA_EUNSUPPORTED, "hyena_intt: unsupported N");
+        case 10: e = launch_c1s_add<10, 6, 4, 3, 3, 0>(c, ct, n, v, mul, s); break;
+        case 11: e = launch_c1s_add<11, 7, 4, 4, 3, 0>(c, ct, n, v, mul, s); break;
+        case 12: e = launch_c1s_add<12, 8, 4, 4, 4, 0>(c, ct, n, v, mul, s); break;
+        case 13: e = launch_c1s_add<13, 8, 5, 4, 4, 0>(c, ct, n, v, mul, s); break;
+        case 14: e = launch_c1s_add<14, 10, 4, 4, 4, 2>(c, ct, n, v, mul, s); break;
+        default: return set_error(HYENA_EUNSUPPORTED, "hyena_ntt: unsupported N");
     }
-    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_intt: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return set_error(HYENA_EHIP, std::string("hyena_ntt: ") + hipGetErrorString(e));
     return HYENA_OK;
 }
 
