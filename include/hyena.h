@@ -148,7 +148,7 @@ int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
  * d_sk.
  *
  * hyena_encrypt_device: d_msg device int32 [n][N]; d_work device uint32
- * [n][L][N], 16-byte aligned, overwritten (a, then a s); d_ct device uint32
+ * [n][L][N], 16-byte aligned, overwritten (with a s); d_ct device uint32
  * [n][2][L][N], written whole. d_work and d_ct must not overlap each other,
  * d_msg or d_s_hat. a and e are drawn exactly as in hyena_encrypt from
  * `seed`. Messages are taken as residues mod q_i (hyena_encrypt's range
@@ -156,8 +156,9 @@ int hyena_decrypt(const hyena_ctx *ctx, const int8_t *sk, const uint32_t *ct,
  *
  * hyena_decrypt_device: d_ct device uint32 [n][2][L][N] with every residue
  * below its prime (not checked: others give unspecified messages); d_work
- * device uint32 [n][L][N], 16-byte aligned, overwritten; d_msg device int32
- * [n][N]. d_work and d_msg must not overlap each other, d_ct or d_s_hat.
+ * device uint32 [n][L][N], 16-byte aligned, overwritten (with c0 + c1 s mod
+ * q_i); d_msg device int32 [n][N]. d_work and d_msg must not overlap each
+ * other, d_ct or d_s_hat.
  *
  * Errors: EINVAL (NULL argument, host-only context, alignment, overlap,
  * n L >= 2^31), EHIP. n = 0 does nothing.
