@@ -126,10 +126,11 @@ int hyena_encrypt(const hyena_ctx *ctx, const int8_t *sk, const int32_t *msg,
  * Decryption m = [round(t * [c0 + c1 s]_q / q)]_t, centered in (-t/2, t/2].
  * ct: host uint32 [n][2][L][N] coefficient domain; msg: host int32 [n][N].
  * Computed in RNS form (Halevi, Polyakov & Shoup 2019) with the fractions of
- * the L terms summed in 32.32 fixed point, truncated: the result is the exact
- * rounding except where the fractional part of t v / q (v = [c0 + c1 s]_q)
- * lies in [1/2, 1/2 + L 2^-32), where it may be one less. So it is exact
- * whenever the noise is below Delta/2 by a margin of L * 2^-32 q/t.
+ * the L terms taken in 0.64 fixed point (each short by less than 2^-33) and
+ * summed with the integer parts: the result is the exact rounding except
+ * where the fractional part of t v / q (v = [c0 + c1 s]_q) lies in
+ * [1/2, 1/2 + L 2^-33), where it may be one less. So it is exact whenever the
+ * noise is below Delta/2 by a margin of L * 2^-33 q/t.
  * hyena_decrypt_device computes the same values. Errors: EINVAL (NULL, a
  * residue not below its prime).
  */

@@ -20,7 +20,9 @@ constexpr int kErrBound = 32;   // error bound B = 10 sigma; the sampler has 2B 
 
 std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c);   // floor(q / t) mod q_i
 void bfv_error_thresholds(uint64_t *t64);                        // the 2B sampler thresholds
-void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B);   // decryption, per limb
+// decryption's RNS rounding, per limb: A_i = floor(t y_i / q_i) and
+// F_i = floor(2^64 (t y_i mod q_i) / q_i), y_i = (q / q_i)^-1 mod q_i
+void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *F);
 
 // Decryption's v = c0 + c1 s for n ciphertexts ct [n][2][L][N] into
 // v [n][L][N] in one kernel: per limb-polynomial the forward transform of c1,

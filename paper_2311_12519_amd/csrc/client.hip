@@ -8,7 +8,8 @@
 //   c1 = [-a]_{q_i},  c0 = [Delta_i lift(msg) + INTT(NTT(a) . NTT(s)) + lift(e)]_{q_i}
 // with e the rounded Gaussian drawn from sm64(seed, 2(m N + j) + 1).
 // Decryption: v = [c0 + INTT(NTT(c1) . NTT(s))]_{q_i}, then the RNS rounding of
-// t v / q of Halevi, Polyakov and Shoup, in the same integer steps as the host.
+// t v / q of Halevi, Polyakov and Shoup, in the same integer steps as the host
+// (fractions in 0.64 fixed point).
 #include <mutex>
 
 #include "bfv.h"
@@ -26,8 +27,7 @@ struct Thresholds {
 struct ClientConst {
     uint32_t dm[HYENA_MAX_LIMBS];   // Delta_i 2^32 mod q_i (Montgomery form)
     uint64_t A[HYENA_MAX_LIMBS];    // floor(t y_i / q_i)
-    uint64_t B[HYENA_MAX_LIMBS];    // t y_i mod q_i
-    uint64_t rcp[HYENA_MAX_LIMBS];  // floor((2^64 - 1) / q_i) = floor(2^64 / q_i)
+    uint64_t F[HYENA_MAX_LIMBS];    // floor(2^64 (t y_i mod q_i) / q_i)
 };
 
 __device__ __forceinline__ uint32_t ccsub(uint32_t x, uint32_t q) { return min(x, x - q); }
@@ -48,19 +48,6 @@ __device__ __forceinline__ uint32_t clift(int32_t x, uint32_t q) {
     return x >= 0 || r == 0 ? r : q - r;
 }
 
-// floor(x / q) and x mod q, exactly, for x < 2^63, with rcp = floor(2^64 / q):
-// x rcp / 2^64 lies in (x/q - 1/2, x/q], so the estimate is the quotient or
-// one below it and a single correction makes it exact.
-__device__ __forceinline__ uint64_t cdivmod(uint64_t x, uint32_t q, uint64_t rcp, uint64_t &rem) {
-    uint64_t qh = __umul64hi(x, rcp);
-    uint64_t r = x - qh * q;
-    if (r >= q) {
-        qh++;
-        r -= q;
-    }
-    rem = r;
-    return qh;
-}
 
 // Blocks walk chunks of 256 coefficients; chunk c of a [P][L][N] array is
 // coefficients (c mod N/256) 256 ... + 255 of limb-polynomial c / (N/256).
@@ -123,26 +110,29 @@ __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const
 // msg <- round(t v / q) mod t, centered, v = work = [c0 + c1 s]_q; the host decryption's integer steps
 __global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *work, int32_t *msg,
                                                              size_t n, uint32_t logN, uint32_t L, uint32_t log2_t,
-                                                             LimbTable lt, ClientConst cc) {
+                                                             ClientConst cc) {
     const uint32_t cpl = 1u << (logN - 8);
     const size_t LN = (size_t)L << logN, chunks = n * cpl;
-    const uint64_t t = 1ull << log2_t;
+    const uint32_t t = 1u << log2_t;
     for (size_t c = blockIdx.x; c < chunks; c += gridDim.x) {
         const size_t m = c >> (logN - 8);
         const size_t mj = (c << 8) + threadIdx.x;
         const uint32_t j = (uint32_t)(mj & ((1u << logN) - 1));
-        uint64_t ipart = 0, fsum = 0;
+        // integer part mod 2^32 (t divides it) and the 0.64 fraction, as the
+        // host sums them: per limb v A_i + v F_i / 2^64, v F_i a 96-bit product
+        uint32_t ipart = 0;
+        uint64_t frac = 0;
         for (uint32_t i = 0; i < L; i++) {
-            const uint32_t q = lt.c[i].q;
-            const size_t r = ((size_t)i << logN) + j;
-            const uint64_t v = work[m * LN + r];                 // c0 + c1 s mod q_i
-            ipart += v * cc.A[i];
-            uint64_t rem, unused;
-            ipart += cdivmod(v * cc.B[i], q, cc.rcp[i], rem);        // v B_i < 2^62
-            fsum += cdivmod(rem << 32, q, cc.rcp[i], unused);         // fraction in 32.32
+            const uint32_t v = work[m * LN + ((size_t)i << logN) + j];   // c0 + c1 s mod q_i
+            const uint64_t a = (uint64_t)v * (uint32_t)cc.F[i];          // v F_lo
+            const uint64_t b = (uint64_t)v * (uint32_t)(cc.F[i] >> 32);  // v F_hi
+            const uint64_t lo = a + (b << 32);                           // low 64 bits of v F
+            ipart += v * (uint32_t)cc.A[i] + (uint32_t)(b >> 32) + (lo < a);
+            frac += lo;
+            ipart += frac < lo;
         }
-        const uint64_t rr = (ipart + ((fsum + (1ull << 31)) >> 32)) & (t - 1);
-        msg[mj] = (int32_t)(rr > t / 2 ? (int64_t)rr - (int64_t)t : (int64_t)rr);
+        const uint32_t rr = (ipart + (uint32_t)(frac >> 63)) & (t - 1);
+        msg[mj] = rr > t / 2 ? (int32_t)rr - (int32_t)t : (int32_t)rr;
     }
 }
 
@@ -168,11 +158,8 @@ int launched(const char *who) {
 ClientConst client_constants(const hyena_ctx *c) {
     ClientConst cc{};
     const auto delta = bfv_delta_residues(c);
-    bfv_hps_constants(c, cc.A, cc.B);
-    for (uint32_t i = 0; i < c->L; i++) {
-        cc.dm[i] = to_montgomery(delta[i], c->q[i]);
-        cc.rcp[i] = ~0ull / c->q[i];
-    }
+    bfv_hps_constants(c, cc.A, cc.F);
+    for (uint32_t i = 0; i < c->L; i++) cc.dm[i] = to_montgomery(delta[i], c->q[i]);
     return cc;
 }
 
@@ -277,7 +264,7 @@ extern "C" int hyena_decrypt_device(const hyena_ctx *c, const uint32_t *d_s_hat,
     if (int rc = launch_ntt_c1s_add(c, d_ct, n, d_work, d_s_hat, s)) return rc;
     const size_t fchunks = n << (c->logN - 8);
     hipLaunchKernelGGL(decrypt_finish_kernel, dim3(grid_for(fchunks)), dim3(CTH), 0, s, d_work, d_msg, n, c->logN,
-                       L, c->log2_t, c->lt, cc);
+                       L, c->log2_t, cc);
     return launched(who);
 }
 

@@ -112,7 +112,7 @@ std::vector<uint32_t> bfv_delta_residues(const hyena_ctx *c) { return delta_resi
 void bfv_error_thresholds(uint64_t *t64) {
     for (int k = 0; k < 2 * kB; k++) t64[k] = cdt().t[k];
 }
-void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B) {
+void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *F) {
     const uint64_t t = 1ull << c->log2_t;
     for (uint32_t i = 0; i < c->L; i++) {
         const uint32_t q = c->q[i];
@@ -122,7 +122,7 @@ void bfv_hps_constants(const hyena_ctx *c, uint64_t *A, uint64_t *B) {
         const uint64_t yi = h_powmod((uint32_t)Mi, q - 2, q);
         const uint64_t ty = (t % q) * yi;  // t * y_i (< 2^51), exact
         A[i] = ty / q;
-        B[i] = ty % q;
+        F[i] = (uint64_t)(((unsigned __int128)(ty % q) << 64) / q);   // (t y_i mod q_i) / q_i in 0.64
     }
 }
 
@@ -174,16 +174,19 @@ extern "C" int hyena_encrypt(const hyena_ctx *c, const int8_t *sk, const int32_t
 // RNS decryption (Halevi, Polyakov & Shoup, CT-RSA 2019): with v the CRT
 // value of the residues v_i and y_i = (q/q_i)^{-1} mod q_i,
 //   t v / q = sum_i v_i t y_i / q_i  (mod t).
-// Each term splits into an integer part and a fraction D_i / q_i; the
-// fractions are summed in 32.32 fixed point (error below L * 2^-32).
+// Each term splits into an integer part v_i A_i and a fraction v_i B_i / q_i
+// (A_i, B_i the quotient and remainder of t y_i by q_i); with
+// F_i = floor(2^64 B_i / q_i) the fraction is taken as v_i F_i / 2^64, a 96-bit
+// product, short of it by less than v_i 2^-64 < 2^-33, and the terms are
+// summed in 32.64 fixed point (the sum short by less than L 2^-33).
 extern "C" int hyena_decrypt(const hyena_ctx *c, const int8_t *sk, const uint32_t *ct, size_t n,
                              int32_t *msg) {
     if (!c || !sk || (n && (!msg || !ct))) return set_error(HYENA_EINVAL, "hyena_decrypt: NULL argument");
     const uint32_t N = c->N, L = c->L;
     const uint64_t t = 1ull << c->log2_t;
     const auto s_hat = secret_ntt(c, sk);
-    std::vector<uint64_t> A(L), B(L);
-    bfv_hps_constants(c, A.data(), B.data());
+    std::vector<uint64_t> A(L), F(L);
+    bfv_hps_constants(c, A.data(), F.data());
     for (size_t k = 0; k < n * L; k++) {
         const uint32_t q = c->q[k % L];
         for (uint32_t j = 0; j < N; j++)
@@ -207,15 +210,17 @@ extern "C" int hyena_decrypt(const hyena_ctx *c, const int8_t *sk, const uint32_
             }
         }
         for (uint32_t j = 0; j < N; j++) {
-            uint64_t ipart = 0, fsum = 0;
+            uint64_t ipart = 0, frac = 0;   // integer part (mod 2^64) and 0.64 fraction
             for (uint32_t i = 0; i < L; i++) {
-                const uint64_t vi = v[(size_t)i * N + j], q = c->q[i];
+                const uint64_t vi = v[(size_t)i * N + j];
                 ipart += vi * A[i];
-                const uint64_t vb = vi * B[i];           // < 2^62
-                ipart += vb / q;
-                fsum += ((vb % q) << 32) / q;            // fraction in 32.32
+                const unsigned __int128 p = (unsigned __int128)vi * F[i];   // < 2^95
+                const uint64_t lo = (uint64_t)p;
+                ipart += (uint64_t)(p >> 64);
+                frac += lo;
+                ipart += frac < lo;                      // carry of the fraction sum
             }
-            uint64_t r = (ipart + ((fsum + (1ull << 31)) >> 32)) & (t - 1);
+            uint64_t r = (ipart + (frac >> 63)) & (t - 1);   // round half up
             int64_t sr = (int64_t)r;
             if (r > t / 2) sr -= (int64_t)t;
             msg[(size_t)m * N + j] = (int32_t)sr;

@@ -143,10 +143,11 @@ def test_decrypt_device_matches_host_on_arbitrary_residues(dev, N, L, bits, n):
     d_ct = torch.from_numpy(ct.view(np.int32)).cuda()
     got = decrypt_dev(ctx, d_s_hat, d_ct.reshape(-1))
     assert np.array_equal(got, hy.hyena_decrypt(ctx, sk, ct))
-    # and the oracle's exact rounding round(t v / q): the library sums the
-    # fractions of the RNS terms in 32.32 fixed point, truncated, so it may
-    # round down only where frac(t v / q) lies in [1/2, 1/2 + L 2^-32); every
-    # coefficient outside that window must equal the oracle's
+    # and the oracle's exact rounding round(t v / q): the library takes the
+    # fractions of the RNS terms in 0.64 fixed point, each short by less than
+    # 2^-33, so it may round down only where frac(t v / q) lies in
+    # [1/2, 1/2 + L 2^-33); every coefficient outside that window must equal
+    # the oracle's
     q = math.prod(int(p) for p in ctx.primes)
     t = 1 << 20
     want = orc.decrypt(ctx.primes, 20, sk, ct)
@@ -155,7 +156,7 @@ def test_decrypt_device_matches_host_on_arbitrary_residues(dev, N, L, bits, n):
         v = orc.decrypt_phase(ctx.primes, sk, ct[m])
         for j, x in enumerate(v):
             r = (t * x) % q                           # frac(t v / q) = r / q
-            in_window = 2 * r >= q and (r - (q + 1) // 2) * (1 << 32) < L * q
+            in_window = 2 * r >= q and (2 * r - q) * (1 << 32) < L * q
             if in_window:
                 assert (int(got[m, j]) - int(want[m, j])) % t in (0, t - 1)
             else:

@@ -101,6 +101,36 @@ def test_decrypt_matches_oracle_on_noisy_ciphertexts():
     assert np.array_equal(hy.hyena_decrypt(ctx, s, Y), orc.decrypt(ctx.primes, 20, s, Y))
 
 
+@pytest.mark.parametrize("N,L,flags", [(1024, 2, hy.HYENA_ALLOW_INSECURE), (4096, 3, hy.HYENA_PRIMES_30BIT)])
+def test_decrypt_rounding_window_on_arbitrary_residues(N, L, flags):
+    """Uniform residues put frac(t v / q) everywhere in [0, 1): the library's
+    RNS rounding (fractions in 0.64 fixed point) equals the oracle's exact
+    round(t v / q) on every coefficient whose fraction lies outside
+    [1/2, 1/2 + L 2^-33), and is at most one less inside it."""
+    import math
+    ctx = hy.hyena_create(N, L, flags=HOST | flags)
+    rng = np.random.default_rng(N + L)
+    ct = np.empty((2, 2, L, N), dtype=np.uint32)
+    for i, q in enumerate(ctx.primes):
+        ct[:, :, i, :] = rng.integers(0, q, size=(2, 2, N))
+    s = orc.keygen(N, 9)
+    got = hy.hyena_decrypt(ctx, s, ct)
+    want = orc.decrypt(ctx.primes, 20, s, ct)
+    q = math.prod(int(p) for p in ctx.primes)
+    t = 1 << 20
+    outside = 0
+    for m in range(2):
+        v = orc.decrypt_phase(ctx.primes, s, ct[m])
+        for j, x in enumerate(v):
+            r = (t * x) % q
+            if 2 * r >= q and (2 * r - q) * (1 << 32) < L * q:
+                assert (int(got[m, j]) - int(want[m, j])) % t in (0, t - 1)
+            else:
+                assert got[m, j] == want[m, j], (m, j)
+                outside += 1
+    assert outside >= 2 * N - 2
+
+
 def test_decrypt_rejects_noncanonical_residue():
     ctx = hy.hyena_create(4096, 2, flags=HOST | hy.HYENA_PRIMES_30BIT)
     ct = np.zeros((1, 2, 2, 4096), dtype=np.uint32)
