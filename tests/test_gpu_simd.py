@@ -380,14 +380,17 @@ def test_simd_conv_cn2_on_gpu_matches_oracle(dev):
             assert np.array_equal(frame[1:1 + H, 1:1 + W], (2 * k * y[o]) % p), (o, row)
 
 
-def test_simd_conv_cn2_entry_point(dev):
-    """hyena_simd_conv_cn2 over two input ciphertexts (4 channels -> 3 outputs)
+@pytest.mark.parametrize("Co", [3, 23, 45])
+def test_simd_conv_cn2_entry_point(dev, Co):
+    """hyena_simd_conv_cn2 over two input ciphertexts (4 channels -> Co outputs)
     at the paper's parameters: equal to the oracle's convolution bit for bit,
-    decrypting to 2k conv(x); a too-small workspace is refused."""
+    decrypting to 2k conv(x); a too-small workspace is refused. The output
+    counts take the CMult-accumulate's one, two and four outputs per thread,
+    the last two with a ragged final group (23 = 11 x 2 + 1, 45 = 11 x 4 + 1)."""
     import torch
     n, L, p, b = 2048, 3, 307201, 8
-    fh, fw, G, Co = 32, 32, 2, 3
-    say("hyena_simd_conv_cn2 n=2048, 2 inputs")
+    fh, fw, G = 32, 32, 2
+    say(f"hyena_simd_conv_cn2 n=2048, 2 inputs, {Co} outputs")
     ctx = ctx_for(n, L, 30)
     primes = ctx.primes
     s = orc.keygen(n, 19)
@@ -415,7 +418,7 @@ def test_simd_conv_cn2_entry_point(dev):
     got = from_dev(out).reshape(Co, 2, L, n)
     assert np.array_equal(got, want)
     y = orc.direct_conv(x, w, 3)
-    for o in range(Co):
+    for o in sorted({0, 1, Co - 1}):
         slots = simd.decode(simd.decrypt_p(primes, p, s, got[o][None])[0], p, n).astype(np.int64)
         for row in range(2):
             frame = slots[row * (n // 2):(row + 1) * (n // 2)].reshape(fh, fw)
