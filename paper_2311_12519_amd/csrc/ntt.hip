@@ -39,21 +39,30 @@ __device__ __forceinline__ uint32_t mont_mul(uint32_t a, uint32_t wm, uint32_t q
     return (uint32_t)(((uint64_t)m * q + t) >> 32);
 }
 
-// (lo, hi) -> (lo + w hi, lo - w hi). Exact variant (any q < 2^31): all values
-// stay canonical in [0, q). Lazy variant (Harvey's butterfly, q < 2^30):
-// values in [0, 4q) between stages.
+// (lo, hi) -> (lo + w hi, lo - w hi). Exact variant (any q < 2^31): values
+// in [0, 2q) between stages (2q < 2^32), canonical inputs to the first stage
+// and canonical outputs of the last (first, last: the butterfly's stage, known
+// once the stage loops are unrolled). Lazy variant (Harvey's butterfly,
+// q < 2^30): values in [0, 4q) between stages, reduced after the transform.
 template <bool LAZY>
-__device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t q, uint32_t qn) {
+__device__ __forceinline__ void ct_bfly(uint32_t &lo, uint32_t &hi, uint32_t w, uint32_t q, uint32_t qn, bool first,
+                                        bool last) {
     if (LAZY) {
         const uint32_t x = min(lo, lo - 2 * q);           // [0, 2q)
         const uint32_t t = mont_mul(hi, w, q, qn);        // [0, 2q)
         lo = x + t;                                       // [0, 4q)
         hi = x - t + 2 * q;                               // (0, 4q)
     } else {
+        const uint32_t x = first ? lo : csub(lo, q);      // [0, q)
         const uint32_t t = csub(mont_mul(hi, w, q, qn), q);
-        const uint32_t d = lo - t;
-        hi = min(d, d + q);       // lo - t wraps above 2q exactly when lo < t
-        lo = csub(lo + t, q);
+        if (last) {
+            const uint32_t d = x - t;
+            hi = min(d, d + q);   // x - t wraps above 2q exactly when x < t
+            lo = csub(x + t, q);
+        } else {
+            lo = x + t;           // [0, 2q)
+            hi = x - t + q;       // (0, 2q)
+        }
     }
 }
 
@@ -127,7 +136,8 @@ __device__ __forceinline__ void fwd_pass(uint32_t (&x)[1 << E_LOG], const uint32
             for (int r = 0; r < GE; r++) {
                 if (r & half) continue;
                 const uint32_t widx = (1u << (S0 + u)) + (b << u) + ((uint32_t)r >> (EP - u));
-                ct_bfly<LAZY>(x[kg * GE + r], x[kg * GE + r + half], tw[widx], q, qn);
+                ct_bfly<LAZY>(x[kg * GE + r], x[kg * GE + r + half], tw[widx], q, qn, S0 + u == 0,
+                              S0 + u == LOGN - 1);
             }
         }
     }
