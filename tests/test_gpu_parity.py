@@ -395,6 +395,36 @@ def test_every_ntt_schedule_matches_oracle(dev, N, L, bits):
         assert np.array_equal(from_dev(d), a), sid
 
 
+@pytest.mark.parametrize("N,L,bits", [(2048, 2, 31), (8192, 2, 31), (4096, 2, 30)])
+def test_every_ntt_schedule_on_extreme_residues(dev, N, L, bits):
+    """Inputs that keep the butterflies' intermediate values at the top of
+    their ranges (every residue q - 1, alternating 0 and q - 1, q - 1 at one
+    end, zero), forward and inverse, through every schedule, against the
+    oracle's transforms."""
+    ctx = ctx_for(N, L, bits)
+    pats = []
+    for kind in range(4):
+        a = np.zeros((L, N), dtype=np.uint64)
+        for i, q in enumerate(ctx.primes):
+            if kind == 0:
+                a[i] = q - 1
+            elif kind == 1:
+                a[i, 1::2] = q - 1
+            elif kind == 2:
+                a[i, -1] = q - 1
+        pats.append(a)
+    a = np.stack(pats)                                   # [4][L][N]
+    want_f = np.stack([[orc.ntt(a[k, i], q, ctx.psi[i]) for i, q in enumerate(ctx.primes)] for k in range(4)])
+    want_i = np.stack([[orc.intt(a[k, i], q, ctx.psi[i]) for i, q in enumerate(ctx.primes)] for k in range(4)])
+    for sid in hy.hyena_ntt_schedules(N):
+        d = to_dev(a)
+        hy.hyena_ntt_sched(ctx, d, False, sid)
+        assert np.array_equal(from_dev(d), want_f), ("forward", sid)
+        d = to_dev(a)
+        hy.hyena_ntt_sched(ctx, d, True, sid)
+        assert np.array_equal(from_dev(d), want_i), ("inverse", sid)
+
+
 @pytest.mark.parametrize("N,L,bits", [(8192, 3, 31), (4096, 2, 30), (16384, 2, 31), (2048, 2, 31)])
 def test_ntt_schedules_many_polys(dev, N, L, bits):
     """Every schedule on more limb-polynomials than a persistent grid holds
