@@ -429,6 +429,36 @@ ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32
     else ntt_fwd_body<LOGN, LOGT, E0, E1, E2, E3, LAZY>(a, tw, lt.c[limb].q, lt.c[limb].qinv_neg, lds);
 }
 
+// x <- x . NTT(s) mod q, canonical, in the runs layout the forward transform
+// ends in (group kg of thread tid: residues [(tid + kg T) 2^EF, + 2^EF));
+// mul holds NTT(s) of the limb in Montgomery form, read 16 (or 8) bytes at a
+// time.
+template <int LOGT, int E_LOG, int EF>
+__device__ __forceinline__ void mul_runs(uint32_t (&x)[1 << E_LOG], const uint32_t *__restrict__ mul, uint32_t q,
+                                         uint32_t qn, uint32_t tid) {
+    constexpr int GE = 1 << EF, NG = (1 << E_LOG) >> EF;
+    static_assert(GE >= 2, "runs of at least two residues");
+#pragma unroll
+    for (int kg = 0; kg < NG; kg++) {
+        const uint32_t *m = mul + ((size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EF);
+        uint32_t *xv = &x[kg * GE];
+        if constexpr (GE >= 4) {
+#pragma unroll
+            for (int j = 0; j < GE; j += 4) {
+                const uint4 u = *reinterpret_cast<const uint4 *>(m + j);
+                xv[j] = csub(mont_mul(xv[j], u.x, q, qn), q);
+                xv[j + 1] = csub(mont_mul(xv[j + 1], u.y, q, qn), q);
+                xv[j + 2] = csub(mont_mul(xv[j + 2], u.z, q, qn), q);
+                xv[j + 3] = csub(mont_mul(xv[j + 3], u.w, q, qn), q);
+            }
+        } else {
+            const uint2 u = *reinterpret_cast<const uint2 *>(m);
+            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
+            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
+        }
+    }
+}
+
 // Encryption's a s, with a drawn in the load: block p (limb p mod L of
 // message p / L) takes a_j = floor(q sm64(seed, 2 (p N + j)) / 2^64), writes
 // c1 = -a of that ciphertext ([n][2][L][N]), transforms a, multiplies by
@@ -441,8 +471,7 @@ ntt_sample_as_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ m
                      const uint32_t *__restrict__ fw_all, const uint32_t *__restrict__ iw_all, LimbTable lt,
                      uint32_t L) {
     constexpr int N = 1 << LOGN, T = 1 << LOGT, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
-    constexpr int EF = E3 > 0 ? E3 : E2, GE = 1 << EF, NG = E >> EF;
-    static_assert(GE >= 4, "16-byte loads of NTT(s) in the runs layout");
+    constexpr int EF = E3 > 0 ? E3 : E2;
     __shared__ uint32_t lds[N + N / 32];
     const uint32_t p = blockIdx.x, limb = p % L, m = p / L, tid = threadIdx.x;
     const size_t LN = (size_t)L * N;
@@ -459,17 +488,7 @@ ntt_sample_as_kernel(uint32_t *ct, uint32_t *dst, const uint32_t *__restrict__ m
     }
     fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, fw_all + (size_t)limb * N, q, qn, lds, tid);
     const uint32_t *sh = mul + (size_t)limb * N;
-#pragma unroll
-    for (int kg = 0; kg < NG; kg++)
-#pragma unroll
-        for (int j = 0; j < GE; j += 4) {
-            const uint4 u = *reinterpret_cast<const uint4 *>(sh + ((tid + (uint32_t)kg * T) << EF) + j);
-            uint32_t *xv = &x[kg * GE + j];
-            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
-            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
-            xv[2] = csub(mont_mul(xv[2], u.z, q, qn), q);
-            xv[3] = csub(mont_mul(xv[3], u.w, q, qn), q);
-        }
+    mul_runs<LOGT, E_LOG, EF>(x, sh, q, qn, tid);
     __syncthreads();   // every wave's reads of the forward exchanges are done
     const uint32_t *iw = iw_all + (size_t)limb * N;
     inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, iw, lc, lds, tid);
@@ -502,8 +521,7 @@ ntt_c1s_add_kernel(const uint32_t *__restrict__ ct, uint32_t *__restrict__ v, co
                    const uint32_t *__restrict__ fw_all, const uint32_t *__restrict__ iw_all, LimbTable lt,
                    uint32_t L) {
     constexpr int N = 1 << LOGN, T = 1 << LOGT, E_LOG = LOGN - LOGT, E = 1 << E_LOG;
-    constexpr int EF = E3 > 0 ? E3 : E2, GE = 1 << EF, NG = E >> EF;
-    static_assert(GE >= 4, "16-byte loads of NTT(s) in the runs layout");
+    constexpr int EF = E3 > 0 ? E3 : E2;
     __shared__ uint32_t lds[N + N / 32];
     const uint32_t p = blockIdx.x, limb = p % L, m = p / L, tid = threadIdx.x;
     const size_t LN = (size_t)L * N;
@@ -515,17 +533,7 @@ ntt_c1s_add_kernel(const uint32_t *__restrict__ ct, uint32_t *__restrict__ v, co
     for (int r = 0; r < E; r++) x[r] = c1[tid + r * T];
     fwd_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, fw_all + (size_t)limb * N, q, qn, lds, tid);
     const uint32_t *sh = mul + (size_t)limb * N;
-#pragma unroll
-    for (int kg = 0; kg < NG; kg++)
-#pragma unroll
-        for (int j = 0; j < GE; j += 4) {
-            const uint4 u = *reinterpret_cast<const uint4 *>(sh + ((tid + (uint32_t)kg * T) << EF) + j);
-            uint32_t *xv = &x[kg * GE + j];
-            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
-            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
-            xv[2] = csub(mont_mul(xv[2], u.z, q, qn), q);
-            xv[3] = csub(mont_mul(xv[3], u.w, q, qn), q);
-        }
+    mul_runs<LOGT, E_LOG, EF>(x, sh, q, qn, tid);
     __syncthreads();   // every wave's reads of the forward exchanges are done
     const uint32_t *iw = iw_all + (size_t)limb * N;
     inv_front<LOGN, LOGT, E0, E1, E2, E3, LAZY>(x, iw, lc, lds, tid);
