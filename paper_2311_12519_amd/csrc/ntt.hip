@@ -431,30 +431,23 @@ ntt_kernel(NttSegs sg, const uint32_t *__restrict__ tw_all, LimbTable lt, uint32
 
 // x <- x . NTT(s) mod q, canonical, in the runs layout the forward transform
 // ends in (group kg of thread tid: residues [(tid + kg T) 2^EF, + 2^EF));
-// mul holds NTT(s) of the limb in Montgomery form, read 16 (or 8) bytes at a
-// time.
+// mul holds NTT(s) of the limb in Montgomery form, read 16 bytes at a time.
 template <int LOGT, int E_LOG, int EF>
 __device__ __forceinline__ void mul_runs(uint32_t (&x)[1 << E_LOG], const uint32_t *__restrict__ mul, uint32_t q,
                                          uint32_t qn, uint32_t tid) {
     constexpr int GE = 1 << EF, NG = (1 << E_LOG) >> EF;
-    static_assert(GE >= 2, "runs of at least two residues");
+    static_assert(GE >= 4, "16-byte loads of NTT(s) in the runs layout");
 #pragma unroll
     for (int kg = 0; kg < NG; kg++) {
         const uint32_t *m = mul + ((size_t)(tid + (uint32_t)kg * (1u << LOGT)) << EF);
         uint32_t *xv = &x[kg * GE];
-        if constexpr (GE >= 4) {
 #pragma unroll
-            for (int j = 0; j < GE; j += 4) {
-                const uint4 u = *reinterpret_cast<const uint4 *>(m + j);
-                xv[j] = csub(mont_mul(xv[j], u.x, q, qn), q);
-                xv[j + 1] = csub(mont_mul(xv[j + 1], u.y, q, qn), q);
-                xv[j + 2] = csub(mont_mul(xv[j + 2], u.z, q, qn), q);
-                xv[j + 3] = csub(mont_mul(xv[j + 3], u.w, q, qn), q);
-            }
-        } else {
-            const uint2 u = *reinterpret_cast<const uint2 *>(m);
-            xv[0] = csub(mont_mul(xv[0], u.x, q, qn), q);
-            xv[1] = csub(mont_mul(xv[1], u.y, q, qn), q);
+        for (int j = 0; j < GE; j += 4) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(m + j);
+            xv[j] = csub(mont_mul(xv[j], u.x, q, qn), q);
+            xv[j + 1] = csub(mont_mul(xv[j + 1], u.y, q, qn), q);
+            xv[j + 2] = csub(mont_mul(xv[j + 2], u.z, q, qn), q);
+            xv[j + 3] = csub(mont_mul(xv[j + 3], u.w, q, qn), q);
         }
     }
 }
