@@ -325,6 +325,25 @@ def test_hrot_rejects_bad_arguments(dev):
         hy.hyena_hrot_hoisted(ctx, ct, [3], 16, k, work, work[:2 * L * N])
 
 
+def test_simd_calls_on_empty_inputs(dev):
+    """Degenerate sizes: no ciphertexts to rotate, no polynomials to permute
+    or multiply, no output channels (nothing written, no error); no inputs to
+    accumulate (every output is the zero ciphertext)."""
+    import torch
+    N, L = 1024, 2
+    ctx = ctx_for(N, L, 30)
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    k = torch.zeros(2 * L * hy.n_digits(16) * 2 * L * N, dtype=torch.int32, device="cuda")   # two rotations' keys
+    hy.hyena_hrot_hoisted(ctx, empty, [3, 5], 16, k, empty, empty)
+    hy.hyena_automorphism(ctx, empty, 3, empty)
+    hy.hyena_pmult_sparse(ctx, empty, [1], [1], empty)
+    hy.hyena_cmult_accumulate(ctx, empty, torch.zeros((0, 0), dtype=torch.int32, device="cuda"), empty)
+    sentinel = torch.full((3 * 2 * L * N,), 12345, dtype=torch.int32, device="cuda")
+    hy.hyena_cmult_accumulate(ctx, empty, torch.zeros((3, 0), dtype=torch.int32, device="cuda"), sentinel)
+    assert not from_dev(sentinel).any()
+    torch.cuda.synchronize()
+
+
 def test_simd_conv_cn2_on_gpu_matches_oracle(dev):
     """The paper's SIMD convolution with c_n = 2 at its parameters (n = 2048,
     p = 307201, k = 11), composed from the library's calls (hoisted HRot,
