@@ -96,13 +96,19 @@ __global__ void __launch_bounds__(CTH) encrypt_finish_kernel(uint32_t *ct, const
         if (cnt == 2 * kErrBound - 1 && u >= thr[2 * kErrBound - 1]) cnt++;
         const int32_t e = (int32_t)cnt - kErrBound;
         const int32_t x = msg[mj];
-        for (uint32_t i = 0; i < L; i++) {
+        uint32_t ws[HYENA_MAX_LIMBS];   // loaded together, as in decrypt_finish_kernel
+#pragma unroll
+        for (uint32_t i = 0; i < HYENA_MAX_LIMBS; i++)
+            if (i < L) ws[i] = work[m * LN + ((size_t)i << logN) + j];
+#pragma unroll
+        for (uint32_t i = 0; i < HYENA_MAX_LIMBS; i++) {
+            if (i >= L) break;
             const LimbConst lc = lt.c[i];
             const uint32_t q = lc.q;
             const size_t r = ((size_t)i << logN) + j;
             const uint32_t dm = cmont(cc.dm[i], clift(x, q), lc);
             const uint32_t le = e >= 0 ? (uint32_t)e : q - (uint32_t)(-e);
-            ct[m * 2 * LN + r] = caddmod(caddmod(dm, work[m * LN + r], q), le, q);
+            ct[m * 2 * LN + r] = caddmod(caddmod(dm, ws[i], q), le, q);
         }
     }
 }
@@ -120,10 +126,18 @@ __global__ void __launch_bounds__(CTH) decrypt_finish_kernel(const uint32_t *wor
         const uint32_t j = (uint32_t)(mj & ((1u << logN) - 1));
         // integer part mod 2^32 (t divides it) and the 0.64 fraction, as the
         // host sums them: per limb v A_i + v F_i / 2^64, v F_i a 96-bit product
+        // the limbs' words are loaded before any of them is used, so that
+        // their loads are in flight together
+        uint32_t vs[HYENA_MAX_LIMBS];
+#pragma unroll
+        for (uint32_t i = 0; i < HYENA_MAX_LIMBS; i++)
+            if (i < L) vs[i] = work[m * LN + ((size_t)i << logN) + j];   // c0 + c1 s mod q_i
         uint32_t ipart = 0;
         uint64_t frac = 0;
-        for (uint32_t i = 0; i < L; i++) {
-            const uint32_t v = work[m * LN + ((size_t)i << logN) + j];   // c0 + c1 s mod q_i
+#pragma unroll
+        for (uint32_t i = 0; i < HYENA_MAX_LIMBS; i++) {
+            if (i >= L) break;
+            const uint32_t v = vs[i];
             const uint64_t a = (uint64_t)v * (uint32_t)cc.F[i];          // v F_lo
             const uint64_t b = (uint64_t)v * (uint32_t)(cc.F[i] >> 32);  // v F_hi
             const uint64_t lo = a + (b << 32);                           // low 64 bits of v F
