@@ -96,6 +96,30 @@ __global__ void __launch_bounds__(STH) ntt_to_slots_kernel(const uint32_t *ntt, 
     }
 }
 
+// Encoding's permutation with each polynomial staged in LDS (one block per
+// polynomial, arrays 16-byte aligned): the global loads and stores are 16-byte
+// pieces contiguous across lanes and the scatter happens in LDS (0.051 ->
+// 0.036 ms for 2048 polynomials at n = 2048, NTT included; the same staging
+// for decoding's gather was slower than gathering through L2).
+__global__ void __launch_bounds__(STH) slots_to_ntt_lds_kernel(const uint32_t *slots, uint32_t *ntt, size_t P,
+                                                               uint32_t logN, uint32_t p) {
+    extern __shared__ uint32_t sh[];
+    const uint32_t N = 1u << logN;
+    for (size_t poly = blockIdx.x; poly < P; poly += gridDim.x) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(slots + (poly << logN));
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) {
+            const uint4 v = src[c];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 4; u++) sh[slot_to_ntt(4 * c + u, logN)] = w[u] < p ? w[u] : w[u] % p;
+        }
+        __syncthreads();
+        uint4 *dst = reinterpret_cast<uint4 *>(ntt + (poly << logN));
+        for (uint32_t c = threadIdx.x; c < N / 4; c += STH) dst[c] = reinterpret_cast<const uint4 *>(sh)[c];
+        __syncthreads();   // the stores' LDS reads precede the next polynomial's writes
+    }
+}
+
 // out = in(X^g) per limb-polynomial, gathered: output coefficient i comes from
 // j = i g^-1 mod 2N (sign + if j < N, else from j - N with sign -)
 __global__ void __launch_bounds__(STH) automorphism_kernel(const uint32_t *in, uint32_t *out, size_t polys,
@@ -581,8 +605,12 @@ extern "C" int hyena_simd_encode(const hyena_ctx *c, const uint32_t *d_slots, si
     const size_t bytes = P * c->N * 4;
     if (soverlap(d_slots, bytes, d_coef, bytes)) return set_error(HYENA_EINVAL, std::string(who) + ": d_coef overlaps d_slots");
     const hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(slots_to_ntt_kernel, dim3(sgrid(P << (c->logN - 8))), dim3(STH), 0, s, d_slots, d_coef, P,
-                       c->logN, c->q[0]);
+    if ((((uintptr_t)d_slots | (uintptr_t)d_coef) & 15u) == 0)
+        hipLaunchKernelGGL(slots_to_ntt_lds_kernel, dim3((unsigned)P), dim3(STH), c->N * 4, s, d_slots, d_coef, P,
+                           c->logN, c->q[0]);
+    else
+        hipLaunchKernelGGL(slots_to_ntt_kernel, dim3(sgrid(P << (c->logN - 8))), dim3(STH), 0, s, d_slots, d_coef, P,
+                           c->logN, c->q[0]);
     if (int rc = slaunched(who)) return rc;
     return launch_ntt(c, d_coef, P, true, s);
 }
