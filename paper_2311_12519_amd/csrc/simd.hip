@@ -442,19 +442,22 @@ __global__ void __launch_bounds__(STH) keyswitch_rot_kernel(const uint32_t *work
 // of residues by small signed integers summed exactly in a signed 64-bit word
 // (|W| <= 2^16, R <= 4096: |sum| < 2^59 <= q 2^30), one reduction per output
 // coefficient (CMult and HAdd without reduction, "Lazy Reduction")
-__global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *in, const int32_t *W, uint32_t *out,
-                                                        uint32_t R, uint32_t O, uint32_t logN, uint32_t L,
-                                                        LimbTable lt) {
+__global__ void __launch_bounds__(STH) cmult_acc_kernel(const uint32_t *__restrict__ in, const int32_t *__restrict__ W,
+                                                        uint32_t *__restrict__ out, uint32_t R, uint32_t O,
+                                                        uint32_t logN, uint32_t L, LimbTable lt) {
     const size_t PLN = (size_t)2 * L << logN;               // words per ciphertext
     const uint32_t chunks = (uint32_t)(((size_t)O * 2 * L) << (logN - 8));   // < 2^31 (checked on the host)
     for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
         const uint32_t op = c >> (logN - 8);                // o (2 L) + part L + limb
         const uint32_t o = op / (2 * L), limb = op % L;
         const size_t idx = ((size_t)(op % (2 * L)) << logN) + ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
-        const int32_t *w = W + (size_t)o * R;
+        // the weight row is the same for every lane (scalar loads); residues are
+        // below 2^31, so as signed 32-bit words their products with the
+        // weights are single v_mad_i64_i32 instructions
+        const int32_t *w = W + (size_t)__builtin_amdgcn_readfirstlane(o) * R;
         int64_t acc = 0;
 #pragma unroll 8
-        for (uint32_t r = 0; r < R; r++) acc += (int64_t)w[r] * (int64_t)in[(size_t)r * PLN + idx];
+        for (uint32_t r = 0; r < R; r++) acc += (int64_t)w[r] * (int64_t)(int32_t)in[(size_t)r * PLN + idx];
         const LimbConst &lc = lt.c[limb];
         const uint64_t t = (uint64_t)(acc + ((int64_t)lc.q << 30));          // in [0, q 2^31)
         // t 2^-32 mod q by one Montgomery reduction, then times 2^64 mod q
@@ -475,8 +478,10 @@ __device__ __forceinline__ uint32_t lazy_result(int64_t acc, const LimbConst &lc
 
 // OPT outputs per thread: each input word read from L2 once per OPT outputs
 template <uint32_t OPT>
-__global__ void __launch_bounds__(STH) cmult_acc2_kernel(const uint32_t *in, const int32_t *WA, const int32_t *WB,
-                                                         uint32_t *outA, uint32_t *outB, uint32_t R, uint32_t O,
+__global__ void __launch_bounds__(STH) cmult_acc2_kernel(const uint32_t *__restrict__ in,
+                                                         const int32_t *__restrict__ WA,
+                                                         const int32_t *__restrict__ WB, uint32_t *__restrict__ outA,
+                                                         uint32_t *__restrict__ outB, uint32_t R, uint32_t O,
                                                          uint32_t logN, uint32_t L, LimbTable lt) {
     const size_t PLN = (size_t)2 * L << logN;
     const uint32_t og = (O + OPT - 1) / OPT;
@@ -487,16 +492,23 @@ __global__ void __launch_bounds__(STH) cmult_acc2_kernel(const uint32_t *in, con
         const size_t idx = ((size_t)(op % (2 * L)) << logN) + ((c & ((1u << (logN - 8)) - 1)) << 8) + threadIdx.x;
         const uint32_t no = min(OPT, O - o0);
         int64_t a[OPT], b[OPT];
+        // the weight rows are the same for every lane: scalar pointers, so
+        // that the weights come through scalar loads (rows past O repeat the
+        // last and are not stored)
+        const int32_t *wa[OPT], *wb[OPT];
 #pragma unroll
-        for (uint32_t u = 0; u < OPT; u++) a[u] = 0, b[u] = 0;
+        for (uint32_t u = 0; u < OPT; u++) {
+            const uint32_t o = __builtin_amdgcn_readfirstlane(min(o0 + u, O - 1));
+            wa[u] = WA + (size_t)o * R, wb[u] = WB + (size_t)o * R;
+            a[u] = 0, b[u] = 0;
+        }
 #pragma unroll 4
         for (uint32_t r = 0; r < R; r++) {
-            const int64_t x = (int64_t)in[(size_t)r * PLN + idx];
+            const int32_t x = (int32_t)in[(size_t)r * PLN + idx];   // < 2^31: one v_mad_i64_i32 per product
 #pragma unroll
             for (uint32_t u = 0; u < OPT; u++) {
-                const uint32_t o = min(o0 + u, O - 1);   // uniform; rows past O repeat the last and are not stored
-                a[u] += (int64_t)WA[(size_t)o * R + r] * x;
-                b[u] += (int64_t)WB[(size_t)o * R + r] * x;
+                a[u] += (int64_t)wa[u][r] * (int64_t)x;
+                b[u] += (int64_t)wb[u][r] * (int64_t)x;
             }
         }
         const LimbConst &lc = lt.c[limb];
