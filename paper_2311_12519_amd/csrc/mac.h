@@ -248,11 +248,15 @@ __device__ __forceinline__ void mac_lds_block(const MacArgs &a, uint32_t logical
         if constexpr (TM > 0) {
             constexpr int R = OB / 4;
             const uint32_t ob = wave * R;
-            const int32_t *tp[R];
+            // the taps are read-only in the kernel and the same on every lane:
+            // read through the constant address space, so that they arrive by
+            // scalar loads rather than by vector loads of one address per lane
+            typedef const __attribute__((address_space(4))) int32_t ctap;
+            ctap *tp[R];
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 const uint32_t o = min(o0 + ob + r, a.Co - 1);
-                tp[r] = a.taps + ((size_t)o * a.w_groups + g) * a.T4;
+                tp[r] = (ctap *)(a.taps + ((size_t)o * a.w_groups + g) * a.T4);
             }
             // |sum| < T 2^13 2^31 <= 2^49 < q 2^20: starting from q 2^20 the
             // signed sum stays positive and below q 2^32, and q 2^20 adds
